@@ -1,0 +1,191 @@
+/*
+ * libsv -- sliced state-vector contraction on one MI355X (gfx950).
+ *
+ * C-ABI of the hot path of the tensor-contraction-deferral simulator of
+ * Pednault et al., "Leveraging Secondary Storage to Simulate Deep 54-qubit
+ * Sycamore Circuits": Schroedinger-style evolution of one subcircuit slice's
+ * amplitude tensor (Sec. 2), with gates aggregated into dense k-qubit blocks
+ * (Sec. 5, aggregate gates of at most 5 qubits), diagonal (hyperedge) gates
+ * applied as element-wise phases (Sec. 2, diagonal and separable tensors),
+ * index permutes that re-choose the sliced ("global") qubits (Sec. 4, the
+ * local/global reorganisation between subcircuits), slices staged to a
+ * secondary tier (Sec. 4, logical files read and written whole), and the
+ * accumulation of amplitudes across slices (Sec. 2, tensor slicing).
+ *
+ * Conventions
+ *   - Qubits are logical labels 0..n-1.  A bitstring / amplitude index has
+ *     bit q = value of qubit q (little-endian).
+ *   - A k-qubit matrix on qubits (q_0, ..., q_{k-1}) is row-major 2^k x 2^k
+ *     with row/column index c = sum_j b(q_j) 2^j.
+ *   - The library keeps a logical-to-physical layout.  The top s =
+ *     popcount(slice_mask) physical positions are the sliced qubits; a slice
+ *     is one fixed assignment of them and holds 2^(n-s) amplitudes.
+ *   - Matrices and phase tables are passed in the state's dtype: interleaved
+ *     (re, im) float pairs for SV_C64, double pairs for SV_C128.  Outputs of
+ *     gather/reduce are always complex128 (double pairs).
+ *
+ * Return values: SV_OK (0) or a negative SV_E* code.  No call throws or
+ * aborts.  Argument errors are detected before anything is queued and leave
+ * the state unchanged.  A device or transfer error poisons the handle: every
+ * later call on it returns SV_ESTATE until destroy_state.  last_error()
+ * describes the most recent failure.
+ *
+ * Ordering and ownership: apply_fused / apply_diag validate, copy their
+ * inputs and queue the operation; the caller may free its buffers on return.
+ * Queued operations run, in order, on the handle's HIP stream at the next
+ * permute_qubits, gather_amplitudes, reduce_slices or sync_state (or when the
+ * queue is large).  gather_amplitudes and reduce_slices return complete host
+ * results.  One host thread may use a handle at a time; different handles are
+ * independent.  Identical call sequences give bitwise identical results.
+ */
+#ifndef SV_H
+#define SV_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+    SV_OK = 0,
+    SV_EINVAL = -1,   /* bad argument (qubit out of range, duplicate, NULL, k out of range) */
+    SV_ENOMEM = -2,   /* device or pinned-host allocation failed */
+    SV_EDEVICE = -3,  /* HIP runtime or kernel error (handle poisoned) */
+    SV_ESLICED = -4,  /* non-diagonal operation on a sliced qubit */
+    SV_ESTATE = -5,   /* handle poisoned by an earlier device/transfer error */
+    SV_EIO = -6       /* slice staging to / from the host tier failed (handle poisoned) */
+};
+
+enum { SV_C64 = 0, SV_C128 = 1 };
+
+/* Flags OR-ed into the dtype argument of create_state. */
+enum {
+    SV_FLAG_TIER = 0x100   /* keep slices in the pinned host tier even if they fit in HBM */
+};
+
+typedef struct sv_state* sv_handle;
+
+/*
+ * create_state -- allocate an n-qubit state |0...0> (Sec. 2: each qubit
+ * starts in |0>).  slice_mask selects the sliced qubits (Sec. 2, tensor
+ * slicing; Sec. 4, global qubits); they take the top physical positions in
+ * ascending label order, the rest take positions 0.. in ascending order.
+ * dtype: SV_C64 or SV_C128, optionally | SV_FLAG_TIER.  hip_stream: a
+ * hipStream_t to run on, or NULL for a stream owned by the handle.
+ * If the whole state fits in device memory all slices are resident in one
+ * HBM buffer; otherwise (or with SV_FLAG_TIER) slices live in pinned host
+ * memory and are staged through device slots.  n in [1, 40], s <= 12.
+ * Errors: SV_EINVAL, SV_ENOMEM, SV_EDEVICE.  *out is set only on success.
+ */
+int create_state(int n, uint64_t slice_mask, int dtype, void* hip_stream, sv_handle* out);
+
+/*
+ * create_state_ext -- as create_state, but the amplitudes live in the
+ * caller's device buffer dev_buf (at least 2^n amplitudes of the dtype,
+ * e.g. a torch tensor), which the handle neither frees nor reallocates.
+ * The buffer is initialised to |0...0> unless dtype has SV_FLAG_KEEP set, in
+ * which case its current contents (in the initial layout) are the state.
+ * All slices are resident.  Errors: SV_EINVAL (buffer NULL or too small).
+ */
+enum { SV_FLAG_KEEP = 0x200 };
+int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream,
+                     void* dev_buf, size_t bytes, sv_handle* out);
+
+/* destroy_state -- wait for queued work, free everything the handle owns.
+   Accepts a poisoned handle; NULL is a no-op.  */
+int destroy_state(sv_handle h);
+
+/*
+ * apply_fused -- queue a dense k-qubit block (Sec. 5: gates aggregated into a
+ * k-qubit kernel represented by a 2^k x 2^k unitary), 1 <= k <= 6 for SV_C64,
+ * 1 <= k <= 5 for SV_C128; every qubit must be unsliced.  qubits: k distinct logical labels; matrix:
+ * row-major 2^k x 2^k in the state dtype (need not be unitary).
+ * Errors: SV_EINVAL; SV_ESLICED if a qubit is currently sliced.
+ */
+int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix);
+
+/*
+ * apply_diag -- queue a diagonal gate on m qubits (Sec. 2: a diagonal tensor
+ * is a hyperedge; it mixes no amplitudes): psi[i] *= phases[c(i)],
+ * c(i) = sum_j b_{q_j}(i) 2^j.  1 <= m <= 12.  Sliced qubits are allowed:
+ * their bits come from the slice being processed.  Errors: SV_EINVAL.
+ */
+int apply_diag(sv_handle h, int m, const int* qubits, const void* phases);
+
+/*
+ * permute_qubits -- choose a new layout (Sec. 4: switching subcircuits
+ * reorganises which indices are local and which are global; the listing's
+ * all2all rows give the new index order).  order[p] = logical qubit placed
+ * at physical position p (p = 0 least significant); the top s positions
+ * become the sliced qubits.  Flushes queued work.  Results of later calls
+ * are unaffected (operations address logical qubits).
+ * Errors: SV_EINVAL (not a permutation), SV_ENOMEM (no room for the
+ * re-arrangement), SV_EDEVICE / SV_EIO (handle poisoned).
+ */
+int permute_qubits(sv_handle h, const int* order);
+
+/*
+ * gather_amplitudes -- flush, then out[j] = psi[bitstrings[j]] as complex128
+ * for j < count (bit q of a bitstring = qubit q; must be < 2^n).  out is a
+ * host buffer of 2*count doubles.  Errors: SV_EINVAL (bitstring >= 2^n or
+ * NULL with count > 0), SV_EDEVICE.
+ */
+int gather_amplitudes(sv_handle h, int64_t count, const uint64_t* bitstrings, void* out_c128);
+
+/*
+ * reduce_slices -- flush, then accumulate across slices in FP64 (Sec. 2:
+ * iterating over the slices and summing their contributions):
+ *     out[j] = sum_t T[r(x_j), t] * psi_t(x_j with its sliced bits set to t)
+ * where r(x) is x's sliced bits and t runs over the 2^s slices; bit i of r
+ * and t belongs to the i-th sliced qubit in ascending label order.
+ * trailing_c128: host 2^s x 2^s row-major complex128 T, or NULL for the
+ * identity (then out[j] = psi[x_j]).  T lets the last gates on sliced qubits
+ * be applied in the reduction instead of by a permute.
+ * stats (may be NULL): [0] = sum over all amplitudes of |psi|^2 (before T),
+ * [1] = sum_j N |out[j]|^2, [2] = sum_j ln(N |out[j]|^2), N = 2^n, all FP64.
+ * Errors as gather_amplitudes.
+ */
+int reduce_slices(sv_handle h, const void* trailing_c128, int64_t count,
+                  const uint64_t* bitstrings, void* out_c128, double stats[3]);
+
+/* sync_state -- run everything queued and wait for it.  */
+int sync_state(sv_handle h);
+
+/* last_error -- text of the most recent failure on h (or of the last failed
+   create when h is NULL).  Valid until the next call on the same handle. */
+const char* last_error(sv_handle h);
+
+/* ---- introspection and tuning (not part of the paper's operation set) ---- */
+
+/* Current layout: order[p] = logical qubit at physical position p. */
+int sv_get_order(sv_handle h, int* order);
+
+/* Copy of the raw device amplitude buffer pointer (resident states) and its
+   size in bytes; *dev = NULL for tiered states. */
+int sv_device_buffer(sv_handle h, void** dev, size_t* bytes);
+
+enum {
+    SV_OPT_TIMING = 1,     /* 1: time every dense sweep with HIP events on the handle's stream */
+    SV_OPT_MFMA = 2,       /* 0: never use the MFMA kernel for k=5 (c64); 1 (default): use it */
+    SV_OPT_FOLD_DIAG = 3,  /* 1 (default): fold a diagonal op into the preceding dense sweep */
+    SV_OPT_SLOTS = 4       /* tier: number of device slice slots (>= 2) */
+};
+int sv_set_option(sv_handle h, int option, int64_t value);
+
+/*
+ * sv_counters -- work done since creation: [0] dense sweeps, [1] diagonal
+ * sweeps, [2] permute sweeps, [3] amplitudes touched by sweeps, [4] bytes
+ * staged host->device, [5] bytes staged device->host, [6] slices skipped
+ * because they are known to be zero.
+ * sv_sweep_time -- with SV_OPT_TIMING: total milliseconds and count of timed
+ * dense sweeps (HIP events on the handle's stream), reset by the call.
+ */
+int sv_counters(sv_handle h, int64_t counters[8]);
+int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SV_H */

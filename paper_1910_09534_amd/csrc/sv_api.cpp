@@ -1,0 +1,885 @@
+// C-ABI of libsv: handles, argument checks, the operation queue and its
+// executor, slicing with a pinned host tier, permutes, gathers and the
+// cross-slice FP64 reduction.  See include/sv.h for the contract.
+//
+// Layout.  Physical bit positions of an n-qubit state: [0, L) are local
+// (L = n - s), [L, n) are sliced.  A slice t holds the 2^L amplitudes whose
+// sliced bits equal t.  In the host tier the top s local positions
+// [L - s, L) form the "file" index (Sec. 4: the logical files are indexed by
+// the union of the two alternating slice sets and always read or written
+// whole): slice t is 2^s files of 2^(L - s) amplitudes, and re-choosing the
+// sliced qubits among the 2s top positions only relabels files.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <new>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "sv_internal.h"
+
+using namespace sv;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+enum OpKind { OP_DENSE = 0, OP_DIAG = 1, OP_LPERM = 2 };
+
+struct Op {
+    int kind = OP_DENSE;
+    int k = 0;                 // dense: qubit count; diag: m
+    int pos[kMaxDiag] = {};    // physical positions at queue time
+    size_t off = 0;            // arena offset of matrix / table
+    BitRuns runs;              // OP_LPERM: destination -> source over local bits
+};
+
+}  // namespace
+
+struct sv_state {
+    int n = 0, s = 0, L = 0, dtype = 0;
+    size_t amp = 8;
+    uint64_t slice_mask = 0;
+    std::vector<int> order, pos;          // order[p] = logical at p; pos[q] = position of q
+
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool tier = false;
+
+    // resident storage
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    bool own_dev = false;
+    void* scratch = nullptr;              // permute target (resident)
+
+    // host tier
+    std::vector<void*> files;             // [t * 2^s + u], pinned, 2^(L-s) amplitudes each
+    std::vector<uint8_t> slice_zero;      // slice known to be all zero
+    std::vector<void*> slots;             // device slice buffers
+    void* pslot = nullptr;                // device buffer for local permutes
+    hipStream_t s_in = nullptr, s_out = nullptr;
+    std::vector<hipEvent_t> ev_in, ev_comp, ev_out;
+
+    // operation queue
+    std::vector<Op> ops;
+    std::vector<uint8_t> arena;
+    void* d_arena = nullptr;
+    size_t d_arena_cap = 0;
+    void* h_arena = nullptr;
+    size_t h_arena_cap = 0;
+    hipEvent_t ev_arena = nullptr;
+
+    // reduction work buffers
+    void* d_bits = nullptr;  size_t d_bits_cap = 0;
+    void* d_acc = nullptr;   size_t d_acc_cap = 0;
+    void* d_part = nullptr;  size_t d_part_cap = 0;
+    void* d_tcol = nullptr;  size_t d_tcol_cap = 0;
+    void* d_rowmap = nullptr; size_t d_rowmap_cap = 0;
+    void* d_small = nullptr;              // 8 doubles
+
+    // options and accounting
+    bool timing = false, mfma = true, fold = true;
+    int nslots = 3;
+    std::vector<hipEvent_t> tev_pool;
+    size_t tev_used = 0;
+    double t_ms = 0.0;
+    int64_t t_count = 0;
+    int64_t counters[8] = {};
+
+    bool poisoned = false;
+    std::string err;
+};
+
+namespace {
+
+int set_err(sv_state* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+int fail_dev(sv_state* h, const char* what, hipError_t e, int code = SV_EDEVICE)
+{
+    std::string m = std::string(what) + ": " + hipGetErrorString(e);
+    if (h) {
+        h->poisoned = true;
+        h->err = m;
+    } else {
+        g_create_error = m;
+    }
+    return code;
+}
+
+#define TRY(h, expr)                                                 \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return fail_dev((h), #expr, e_);       \
+    } while (0)
+
+#define TRY_IO(h, expr)                                              \
+    do {                                                             \
+        hipError_t e_ = (expr);                                      \
+        if (e_ != hipSuccess) return fail_dev((h), #expr, e_, SV_EIO); \
+    } while (0)
+
+#define CHECK_HANDLE(h)                                                          \
+    do {                                                                         \
+        if (!(h)) return set_err(nullptr, SV_EINVAL, "NULL handle");              \
+        if ((h)->poisoned) return SV_ESTATE;                                     \
+    } while (0)
+
+int ensure_dev(sv_state* h, void** p, size_t* cap, size_t need)
+{
+    if (*cap >= need) return SV_OK;
+    if (*p) {
+        hipError_t e = hipStreamSynchronize(h->stream);
+        if (e != hipSuccess) return fail_dev(h, "hipStreamSynchronize", e);
+        (void)hipFree(*p);
+        *p = nullptr;
+        *cap = 0;
+    }
+    size_t want = std::max(need, (size_t)4096);
+    if (hipMalloc(p, want) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return set_err(h, SV_ENOMEM, "device allocation of work buffer failed");
+    }
+    *cap = want;
+    return SV_OK;
+}
+
+int check_qubit_list(sv_state* h, int k, const int* q, int kmax)
+{
+    if (!q) return set_err(h, SV_EINVAL, "qubit list is NULL");
+    if (k < 1 || k > kmax) return set_err(h, SV_EINVAL, "qubit count out of range");
+    for (int j = 0; j < k; ++j) {
+        if (q[j] < 0 || q[j] >= h->n) return set_err(h, SV_EINVAL, "qubit label out of range");
+        for (int l = 0; l < j; ++l)
+            if (q[l] == q[j]) return set_err(h, SV_EINVAL, "duplicate qubit label");
+    }
+    return SV_OK;
+}
+
+size_t push_arena(sv_state* h, const void* src, size_t bytes)
+{
+    size_t off = (h->arena.size() + 255) & ~(size_t)255;
+    h->arena.resize(off + bytes);
+    std::memcpy(h->arena.data() + off, src, bytes);
+    return off;
+}
+
+// ---- timing of dense sweeps ----------------------------------------------
+hipEvent_t next_event(sv_state* h)
+{
+    if (h->tev_used == h->tev_pool.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        h->tev_pool.push_back(e);
+    }
+    return h->tev_pool[h->tev_used++];
+}
+
+int collect_timing(sv_state* h)
+{
+    if (h->tev_used == 0) return SV_OK;
+    TRY(h, hipEventSynchronize(h->tev_pool[h->tev_used - 1]));
+    for (size_t i = 0; i + 1 < h->tev_used; i += 2) {
+        float ms = 0.f;
+        TRY(h, hipEventElapsedTime(&ms, h->tev_pool[i], h->tev_pool[i + 1]));
+        h->t_ms += ms;
+        h->t_count += 1;
+    }
+    h->tev_used = 0;
+    return SV_OK;
+}
+
+// ---- running the queue over one range of amplitudes ----------------------
+// psi: 2^nloc amplitudes whose global index starts at idx_offset.
+int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset)
+{
+    const char* dbase = (const char*)h->d_arena;
+    const size_t nops = h->ops.size();
+    for (size_t i = 0; i < nops; ++i) {
+        const Op& op = h->ops[i];
+        if (op.kind == OP_DENSE) {
+            DiagSpec fold;
+            const DiagSpec* fp = nullptr;
+            if (h->fold && i + 1 < nops && h->ops[i + 1].kind == OP_DIAG) {
+                const Op& d = h->ops[i + 1];
+                fold.m = d.k;
+                for (int j = 0; j < d.k; ++j) fold.pos[j] = d.pos[j];
+                fold.table = dbase + d.off;
+                fp = &fold;
+                ++i;
+            }
+            hipEvent_t e0 = nullptr, e1 = nullptr;
+            if (h->timing) {
+                e0 = next_event(h);
+                e1 = next_event(h);
+                if (!e0 || !e1) return set_err(h, SV_EDEVICE, "event creation failed");
+                TRY(h, hipEventRecord(e0, st));
+            }
+            TRY(h, launch_dense(st, *psi, h->dtype, nloc, op.k, op.pos, dbase + op.off, fp,
+                                idx_offset, h->mfma));
+            if (h->timing) TRY(h, hipEventRecord(e1, st));
+            h->counters[0] += 1;
+            h->counters[3] += (int64_t)1 << nloc;
+        } else if (op.kind == OP_DIAG) {
+            DiagSpec d;
+            d.m = op.k;
+            for (int j = 0; j < op.k; ++j) d.pos[j] = op.pos[j];
+            d.table = dbase + op.off;
+            TRY(h, launch_diag(st, *psi, h->dtype, nloc, idx_offset, d));
+            h->counters[1] += 1;
+            h->counters[3] += (int64_t)1 << nloc;
+        } else {
+            TRY(h, launch_bitperm(st, *psi, alt, h->dtype, nloc, op.runs));
+            std::swap(*psi, alt);
+            h->counters[2] += 1;
+            h->counters[3] += (int64_t)1 << nloc;
+        }
+    }
+    return SV_OK;
+}
+
+int upload_arena(sv_state* h)
+{
+    const size_t bytes = h->arena.size();
+    if (bytes == 0) return SV_OK;
+    if (h->ev_arena) TRY(h, hipEventSynchronize(h->ev_arena));   // pinned staging reusable
+    if (h->h_arena_cap < bytes) {
+        if (h->h_arena) (void)hipHostFree(h->h_arena);
+        h->h_arena = nullptr;
+        h->h_arena_cap = 0;
+        size_t want = std::max(bytes * 2, (size_t)1 << 20);
+        if (hipHostMalloc(&h->h_arena, want, hipHostMallocDefault) != hipSuccess) {
+            h->h_arena = nullptr;
+            (void)hipGetLastError();
+            return set_err(h, SV_ENOMEM, "pinned staging allocation failed");
+        }
+        h->h_arena_cap = want;
+    }
+    int rc = ensure_dev(h, &h->d_arena, &h->d_arena_cap, std::max(bytes * 2, (size_t)1 << 20));
+    if (rc) return rc;
+    std::memcpy(h->h_arena, h->arena.data(), bytes);
+    TRY(h, hipMemcpyAsync(h->d_arena, h->h_arena, bytes, hipMemcpyHostToDevice, h->stream));
+    if (!h->ev_arena) TRY(h, hipEventCreateWithFlags(&h->ev_arena, hipEventDisableTiming));
+    TRY(h, hipEventRecord(h->ev_arena, h->stream));
+    return SV_OK;
+}
+
+// ---- tier staging ------------------------------------------------------------
+size_t file_amps(const sv_state* h) { return (size_t)1 << (h->L - h->s); }
+
+int stage_in(sv_state* h, hipStream_t st, uint64_t t, void* slot)
+{
+    const size_t fa = file_amps(h), fb = fa * h->amp;
+    const int nf = 1 << h->s;
+    for (int u = 0; u < nf; ++u) {
+        char* dst = (char*)slot + (size_t)u * fb;
+        TRY_IO(h, hipMemcpyAsync(dst, h->files[t * nf + u], fb, hipMemcpyHostToDevice, st));
+        h->counters[4] += (int64_t)fb;
+    }
+    return SV_OK;
+}
+
+int stage_out(sv_state* h, hipStream_t st, uint64_t t, const void* slot)
+{
+    const size_t fa = file_amps(h), fb = fa * h->amp;
+    const int nf = 1 << h->s;
+    for (int u = 0; u < nf; ++u) {
+        const char* src = (const char*)slot + (size_t)u * fb;
+        TRY_IO(h, hipMemcpyAsync(h->files[t * nf + u], src, fb, hipMemcpyDeviceToHost, st));
+        h->counters[5] += (int64_t)fb;
+    }
+    return SV_OK;
+}
+
+// Run the queue over every non-zero slice of the tier: stage in (copy-in
+// stream), compute (handle stream), stage out (copy-out stream), pipelined
+// over the device slots.  visit (optional) runs on the compute stream after
+// the ops of each slice, with the slice's buffer.
+template <typename F>
+int tier_pass(sv_state* h, bool write_back, F&& visit)
+{
+    const int ns = 1 << h->s;
+    const int R = (int)h->slots.size();
+    int idx = 0;
+    for (int t = 0; t < ns; ++t) {
+        if (h->slice_zero[t]) {
+            h->counters[6] += 1;
+            continue;
+        }
+        const int k = idx % R;
+        void* slot = h->slots[k];
+        if (idx >= R) TRY(h, hipStreamWaitEvent(h->s_in, h->ev_out[k], 0));
+        if (idx >= R) TRY(h, hipStreamWaitEvent(h->s_in, h->ev_comp[k], 0));
+        int rc = stage_in(h, h->s_in, (uint64_t)t, slot);
+        if (rc) return rc;
+        TRY(h, hipEventRecord(h->ev_in[k], h->s_in));
+        TRY(h, hipStreamWaitEvent(h->stream, h->ev_in[k], 0));
+        void* cur = slot;
+        void* alt = h->pslot;
+        rc = run_ops(h, h->stream, &cur, alt, h->L, (uint64_t)t << h->L);
+        if (rc) return rc;
+        if (cur != slot) {
+            // an odd number of local permutes left the data in the permute
+            // buffer: swap roles so the slot keeps pointing at live data
+            h->slots[k] = cur;
+            h->pslot = slot;
+            slot = cur;
+        }
+        rc = visit(t, slot);
+        if (rc) return rc;
+        TRY(h, hipEventRecord(h->ev_comp[k], h->stream));
+        if (write_back) {
+            TRY(h, hipStreamWaitEvent(h->s_out, h->ev_comp[k], 0));
+            rc = stage_out(h, h->s_out, (uint64_t)t, slot);
+            if (rc) return rc;
+        }
+        TRY(h, hipEventRecord(h->ev_out[k], h->s_out));
+        ++idx;
+    }
+    TRY(h, hipStreamSynchronize(h->s_in));
+    TRY(h, hipStreamSynchronize(h->stream));
+    TRY(h, hipStreamSynchronize(h->s_out));
+    return SV_OK;
+}
+
+int flush(sv_state* h)
+{
+    if (h->ops.empty()) return SV_OK;
+    int rc = upload_arena(h);
+    if (rc) return rc;
+    if (!h->tier) {
+        void* cur = h->dev;
+        rc = run_ops(h, h->stream, &cur, h->scratch, h->n, 0);
+        if (rc) return rc;
+        if (cur != h->dev) return set_err(h, SV_EDEVICE, "internal: permute left in scratch");
+    } else {
+        TRY(h, hipEventRecord(h->ev_arena, h->stream));
+        TRY(h, hipStreamWaitEvent(h->s_in, h->ev_arena, 0));
+        rc = tier_pass(h, true, [](int, void*) { return SV_OK; });
+        if (rc) return rc;
+    }
+    h->ops.clear();
+    h->arena.clear();
+    if (h->timing) return collect_timing(h);
+    return SV_OK;
+}
+
+void release(sv_state* h)
+{
+    if (!h) return;
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    if (h->s_in) (void)hipStreamSynchronize(h->s_in);
+    if (h->s_out) (void)hipStreamSynchronize(h->s_out);
+    if (h->own_dev && h->dev) (void)hipFree(h->dev);
+    if (h->scratch) (void)hipFree(h->scratch);
+    for (void* p : h->files)
+        if (p) (void)hipHostFree(p);
+    for (void* p : h->slots)
+        if (p) (void)hipFree(p);
+    if (h->pslot) (void)hipFree(h->pslot);
+    for (void** p : {&h->d_arena, &h->d_bits, &h->d_acc, &h->d_part, &h->d_tcol, &h->d_rowmap,
+                     &h->d_small})
+        if (*p) (void)hipFree(*p);
+    if (h->h_arena) (void)hipHostFree(h->h_arena);
+    for (auto* v : {&h->ev_in, &h->ev_comp, &h->ev_out, &h->tev_pool})
+        for (hipEvent_t e : *v) (void)hipEventDestroy(e);
+    if (h->ev_arena) (void)hipEventDestroy(h->ev_arena);
+    if (h->s_in) (void)hipStreamDestroy(h->s_in);
+    if (h->s_out) (void)hipStreamDestroy(h->s_out);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+    delete h;
+}
+
+void default_layout(sv_state* h)
+{
+    h->order.clear();
+    for (int q = 0; q < h->n; ++q)
+        if (!((h->slice_mask >> q) & 1)) h->order.push_back(q);
+    for (int q = 0; q < h->n; ++q)
+        if ((h->slice_mask >> q) & 1) h->order.push_back(q);
+    h->pos.assign(h->n, 0);
+    for (int p = 0; p < h->n; ++p) h->pos[h->order[p]] = p;
+}
+
+int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext, size_t ext_bytes,
+                  sv_handle* out)
+{
+    if (!out) return set_err(nullptr, SV_EINVAL, "out is NULL");
+    const int base = dtype & 0xff;
+    if (base != SV_C64 && base != SV_C128) return set_err(nullptr, SV_EINVAL, "bad dtype");
+    if (n < 1 || n > 40) return set_err(nullptr, SV_EINVAL, "n out of range [1, 40]");
+    if (n < 64 && (slice_mask >> n)) return set_err(nullptr, SV_EINVAL, "slice_mask names a qubit >= n");
+    const int s = __builtin_popcountll(slice_mask);
+    if (s > 12 || s > n - 1) return set_err(nullptr, SV_EINVAL, "too many sliced qubits");
+
+    sv_state* h = new (std::nothrow) sv_state();
+    if (!h) return set_err(nullptr, SV_ENOMEM, "host allocation failed");
+    h->n = n;
+    h->s = s;
+    h->L = n - s;
+    h->dtype = base;
+    h->amp = base ? 16 : 8;
+    h->slice_mask = slice_mask;
+    default_layout(h);
+    hipError_t e;
+    if (stream) {
+        h->stream = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { release(h); return fail_dev(nullptr, "hipStreamCreate", e); }
+        h->own_stream = true;
+    }
+    const size_t total = ((size_t)1 << n) * h->amp;
+    bool tier = (dtype & SV_FLAG_TIER) != 0;
+    if (ext) {
+        if (tier) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer cannot be tiered"); }
+        if (ext_bytes < total) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer too small"); }
+        h->dev = ext;
+        h->dev_bytes = ext_bytes;
+    } else if (!tier) {
+        size_t freeb = 0, totb = 0;
+        e = hipMemGetInfo(&freeb, &totb);
+        if (e != hipSuccess) { release(h); return fail_dev(nullptr, "hipMemGetInfo", e); }
+        const size_t margin = (size_t)2 << 30;
+        if (total + margin > freeb) {
+            if (s == 0) { release(h); return set_err(nullptr, SV_ENOMEM, "state does not fit in device memory and is not sliced"); }
+            tier = true;
+        } else {
+            if (hipMalloc(&h->dev, total) != hipSuccess) {
+                (void)hipGetLastError();
+                release(h);
+                return set_err(nullptr, SV_ENOMEM, "device allocation of the state failed");
+            }
+            h->own_dev = true;
+            h->dev_bytes = total;
+        }
+    }
+    h->tier = tier;
+    if (tier) {
+        if (s < 1 || h->L - s < 0) { release(h); return set_err(nullptr, SV_EINVAL, "tier needs 1 <= s <= n/2"); }
+        const int ns = 1 << s;
+        const size_t fb = file_amps(h) * h->amp;
+        h->files.assign((size_t)ns * ns, nullptr);
+        for (auto& f : h->files) {
+            if (hipHostMalloc(&f, fb, hipHostMallocDefault) != hipSuccess) {
+                f = nullptr;
+                (void)hipGetLastError();
+                release(h);
+                return set_err(nullptr, SV_ENOMEM, "pinned host tier allocation failed");
+            }
+            std::memset(f, 0, fb);
+        }
+        // |0...0>: amplitude 0 lives in file (t = 0, u = 0)
+        if (base) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
+        else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
+        h->slice_zero.assign(ns, 1);
+        h->slice_zero[0] = 0;
+        const size_t sb = ((size_t)1 << h->L) * h->amp;
+        h->slots.assign(h->nslots, nullptr);
+        for (auto& p : h->slots)
+            if (hipMalloc(&p, sb) != hipSuccess) {
+                p = nullptr;
+                (void)hipGetLastError();
+                release(h);
+                return set_err(nullptr, SV_ENOMEM, "device slot allocation failed");
+            }
+        if (hipMalloc(&h->pslot, sb) != hipSuccess) {
+            h->pslot = nullptr;
+            (void)hipGetLastError();
+            release(h);
+            return set_err(nullptr, SV_ENOMEM, "device slot allocation failed");
+        }
+        e = hipStreamCreateWithFlags(&h->s_in, hipStreamNonBlocking);
+        if (e == hipSuccess) e = hipStreamCreateWithFlags(&h->s_out, hipStreamNonBlocking);
+        if (e != hipSuccess) { release(h); return fail_dev(nullptr, "hipStreamCreate", e); }
+        for (auto* v : {&h->ev_in, &h->ev_comp, &h->ev_out}) {
+            v->assign(h->nslots, nullptr);
+            for (auto& ev : *v) {
+                e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+                if (e != hipSuccess) { release(h); return fail_dev(nullptr, "hipEventCreate", e); }
+            }
+        }
+        e = hipEventCreateWithFlags(&h->ev_arena, hipEventDisableTiming);
+        if (e != hipSuccess) { release(h); return fail_dev(nullptr, "hipEventCreate", e); }
+    } else if (!(ext && (dtype & SV_FLAG_KEEP))) {
+        e = launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << n, true);
+        if (e != hipSuccess) { release(h); return fail_dev(nullptr, "init kernel", e); }
+    }
+    if (hipMalloc(&h->d_small, 64) != hipSuccess) {
+        (void)hipGetLastError();
+        release(h);
+        return set_err(nullptr, SV_ENOMEM, "device allocation failed");
+    }
+    *out = h;
+    return SV_OK;
+}
+
+// FP64 host reduction helpers ------------------------------------------------
+int finish_sum(sv_state* h, hipStream_t st, int nblocks, int width, double* host_out)
+{
+    TRY(h, launch_finish_sum(st, (const double*)h->d_part, nblocks, width, (double*)h->d_small));
+    TRY(h, hipMemcpyAsync(host_out, h->d_small, sizeof(double) * width, hipMemcpyDeviceToHost, st));
+    TRY(h, hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* bits, void* out,
+              double* stats)
+{
+    CHECK_HANDLE(h);
+    if (count < 0 || (count > 0 && (!bits || !out))) return set_err(h, SV_EINVAL, "bad output arguments");
+    const uint64_t lim = h->n >= 64 ? ~0ull : ((1ull << h->n) - 1);
+    for (int64_t j = 0; j < count; ++j)
+        if (bits[j] > lim) return set_err(h, SV_EINVAL, "bitstring >= 2^n");
+    int rc = flush(h);
+    if (rc) return rc;
+    const int ns = 1 << h->s;
+    const size_t cnt = (size_t)std::max<int64_t>(count, 1);
+    if ((rc = ensure_dev(h, &h->d_bits, &h->d_bits_cap, cnt * 8))) return rc;
+    if ((rc = ensure_dev(h, &h->d_acc, &h->d_acc_cap, cnt * 16))) return rc;
+    if ((rc = ensure_dev(h, &h->d_part, &h->d_part_cap, 4096 * 16 * sizeof(double)))) return rc;
+    if ((rc = ensure_dev(h, &h->d_tcol, &h->d_tcol_cap, (size_t)ns * 16))) return rc;
+    if ((rc = ensure_dev(h, &h->d_rowmap, &h->d_rowmap_cap, (size_t)ns * 4))) return rc;
+
+    // logical bitstring -> physical index
+    std::vector<int> from(h->n), to(h->n);
+    for (int q = 0; q < h->n; ++q) { from[q] = q; to[q] = h->pos[q]; }
+    const BitRuns l2p = make_runs(h->n, from.data(), to.data());
+    // physical slice id -> T index (bit i = i-th sliced qubit in ascending label order)
+    std::vector<int> sl;
+    for (int q = 0; q < h->n; ++q)
+        if (h->pos[q] >= h->L) sl.push_back(q);
+    std::vector<int> rowmap(ns);
+    for (int t = 0; t < ns; ++t) {
+        int r = 0;
+        for (int i = 0; i < h->s; ++i)
+            if ((t >> (h->pos[sl[i]] - h->L)) & 1) r |= 1 << i;
+        rowmap[t] = r;
+    }
+    hipStream_t st = h->stream;
+    if (count > 0) {
+        TRY(h, hipMemcpyAsync(h->d_bits, bits, (size_t)count * 8, hipMemcpyHostToDevice, st));
+        TRY(h, hipMemsetAsync(h->d_acc, 0, (size_t)count * 16, st));
+    }
+    TRY(h, hipMemcpyAsync(h->d_rowmap, rowmap.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+    std::vector<double> tcol;
+    const double* T = (const double*)trailing;
+    auto set_col = [&](int t) -> int {
+        if (!T) return SV_OK;
+        tcol.assign((size_t)ns * 2, 0.0);
+        const int c = rowmap[t];
+        for (int r = 0; r < ns; ++r) {
+            tcol[2 * r] = T[2 * ((size_t)r * ns + c)];
+            tcol[2 * r + 1] = T[2 * ((size_t)r * ns + c) + 1];
+        }
+        // synchronous copy: tcol is reused for the next slice
+        TRY(h, hipMemcpyAsync(h->d_tcol, tcol.data(), (size_t)ns * 16, hipMemcpyHostToDevice, st));
+        TRY(h, hipStreamSynchronize(st));
+        return SV_OK;
+    };
+    double norm = 0.0;
+    std::vector<double> slice_norm(ns, 0.0);
+    auto visit = [&](int t, const void* slice_buf) -> int {
+        int r = set_col(t);
+        if (r) return r;
+        TRY(h, launch_accumulate(st, slice_buf, h->dtype, h->L, (uint64_t)t, l2p, count,
+                                 (const uint64_t*)h->d_bits, T ? h->d_tcol : nullptr,
+                                 (const int*)h->d_rowmap, (double*)h->d_acc));
+        if (stats) {
+            int nb = 0;
+            TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)h->d_part, &nb));
+            r = finish_sum(h, st, nb, 1, &slice_norm[t]);
+            if (r) return r;
+        }
+        return SV_OK;
+    };
+    if (!h->tier) {
+        if (!T && h->s == 0) {
+            rc = visit(0, h->dev);
+        } else {
+            for (int t = 0; t < ns && !rc; ++t)
+                rc = visit(t, (const char*)h->dev + ((size_t)t << h->L) * h->amp);
+        }
+    } else {
+        rc = tier_pass(h, false, visit);
+    }
+    if (rc) return rc;
+    for (int t = 0; t < ns; ++t) norm += slice_norm[t];   // fixed slice order
+    if (count > 0) {
+        TRY(h, hipMemcpyAsync(out, h->d_acc, (size_t)count * 16, hipMemcpyDeviceToHost, st));
+    }
+    if (stats) {
+        double x[2] = {0.0, 0.0};
+        if (count > 0) {
+            int nb = 0;
+            TRY(h, launch_xeb_partials(st, (const double*)h->d_acc, count, (double)h->n,
+                                       (double*)h->d_part, &nb));
+            rc = finish_sum(h, st, nb, 2, x);
+            if (rc) return rc;
+        }
+        stats[0] = norm;
+        stats[1] = x[0];
+        stats[2] = x[1];
+    }
+    TRY(h, hipStreamSynchronize(st));
+    return SV_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C-ABI
+// ===========================================================================
+extern "C" {
+
+int create_state(int n, uint64_t slice_mask, int dtype, void* hip_stream, sv_handle* out)
+{
+    return create_common(n, slice_mask, dtype, hip_stream, nullptr, 0, out);
+}
+
+int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream, void* dev_buf,
+                     size_t bytes, sv_handle* out)
+{
+    if (!dev_buf) return set_err(nullptr, SV_EINVAL, "dev_buf is NULL");
+    return create_common(n, slice_mask, dtype, hip_stream, dev_buf, bytes, out);
+}
+
+int destroy_state(sv_handle h)
+{
+    if (!h) return SV_OK;
+    release(h);
+    return SV_OK;
+}
+
+int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix)
+{
+    CHECK_HANDLE(h);
+    const int kmax = h->dtype ? 5 : 6;
+    int rc = check_qubit_list(h, k, qubits, kmax);
+    if (rc) return rc;
+    if (!matrix) return set_err(h, SV_EINVAL, "matrix is NULL");
+    if (k > h->L) return set_err(h, SV_EINVAL, "block wider than the local qubits");
+    for (int j = 0; j < k; ++j)
+        if (h->pos[qubits[j]] >= h->L) return set_err(h, SV_ESLICED, "dense op on a sliced qubit");
+    Op op;
+    op.kind = OP_DENSE;
+    op.k = k;
+    for (int j = 0; j < k; ++j) op.pos[j] = h->pos[qubits[j]];
+    op.off = push_arena(h, matrix, ((size_t)1 << (2 * k)) * h->amp);
+    h->ops.push_back(op);
+    if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
+    return SV_OK;
+}
+
+int apply_diag(sv_handle h, int m, const int* qubits, const void* phases)
+{
+    CHECK_HANDLE(h);
+    int rc = check_qubit_list(h, m, qubits, kMaxDiag);
+    if (rc) return rc;
+    if (!phases) return set_err(h, SV_EINVAL, "phase table is NULL");
+    Op op;
+    op.kind = OP_DIAG;
+    op.k = m;
+    for (int j = 0; j < m; ++j) op.pos[j] = h->pos[qubits[j]];
+    op.off = push_arena(h, phases, ((size_t)1 << m) * h->amp);
+    h->ops.push_back(op);
+    if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
+    return SV_OK;
+}
+
+int permute_qubits(sv_handle h, const int* order)
+{
+    CHECK_HANDLE(h);
+    if (!order) return set_err(h, SV_EINVAL, "order is NULL");
+    std::vector<int> seen(h->n, 0);
+    for (int p = 0; p < h->n; ++p) {
+        if (order[p] < 0 || order[p] >= h->n || seen[order[p]]) return set_err(h, SV_EINVAL, "order is not a permutation");
+        seen[order[p]] = 1;
+    }
+    std::vector<int> npos(h->n);
+    for (int p = 0; p < h->n; ++p) npos[order[p]] = p;
+    bool same = true;
+    for (int q = 0; q < h->n; ++q) same = same && (npos[q] == h->pos[q]);
+    if (same) return SV_OK;
+
+    if (!h->tier) {
+        int rc = flush(h);
+        if (rc) return rc;
+        if (!h->scratch) {
+            if (hipMalloc(&h->scratch, h->dev_bytes) != hipSuccess) {
+                h->scratch = nullptr;
+                (void)hipGetLastError();
+                return set_err(h, SV_ENOMEM, "no device memory for the permute buffer");
+            }
+        }
+        // out[new index] = in[old index]: destination bit npos[q] <- source bit pos[q]
+        std::vector<int> from(h->n), to(h->n);
+        for (int q = 0; q < h->n; ++q) { from[q] = npos[q]; to[q] = h->pos[q]; }
+        const BitRuns r = make_runs(h->n, from.data(), to.data());
+        TRY(h, launch_bitperm(h->stream, h->dev, h->scratch, h->dtype, h->n, r));
+        TRY(h, hipMemcpyAsync(h->dev, h->scratch, ((size_t)1 << h->n) * h->amp,
+                              hipMemcpyDeviceToDevice, h->stream));
+        h->counters[2] += 1;
+        h->counters[3] += (int64_t)1 << h->n;
+    } else {
+        // (1) per-slice local permute bringing the qubits that become sliced
+        //     into the file positions [L-s, L); (2) relabel files; (3) per-slice
+        //     local permute to the requested local order (queued for the next pass).
+        const int L = h->L, s = h->s, F = L - s;
+        std::vector<int> mid(h->n);              // intermediate position of each qubit
+        for (int q = 0; q < h->n; ++q) mid[q] = h->pos[q];
+        std::vector<int> incoming;               // new sliced qubits now in [0, F)
+        for (int q = 0; q < h->n; ++q)
+            if (npos[q] >= L && h->pos[q] < F) incoming.push_back(q);
+        std::vector<int> evict;                  // file-region qubits that stay local
+        for (int p = F; p < L; ++p) {
+            const int q = h->order[p];
+            if (npos[q] < L) evict.push_back(q);
+        }
+        if (evict.size() < incoming.size()) return set_err(h, SV_EINVAL, "internal: file region too small");
+        for (size_t i = 0; i < incoming.size(); ++i) std::swap(mid[incoming[i]], mid[evict[i]]);
+        bool moved1 = false;
+        for (int q = 0; q < h->n; ++q) moved1 = moved1 || (mid[q] != h->pos[q]);
+        if (moved1) {
+            Op op;
+            op.kind = OP_LPERM;
+            std::vector<int> from, to;
+            for (int q = 0; q < h->n; ++q)
+                if (h->pos[q] < L) { from.push_back(mid[q]); to.push_back(h->pos[q]); }
+            op.runs = make_runs((int)from.size(), from.data(), to.data());
+            h->ops.push_back(op);
+        }
+        int rc = flush(h);
+        if (rc) return rc;
+        // (2) top 2s positions [F, n): after (1) every new sliced qubit is there.
+        // new positions within the top block: sliced ones go to npos; the others
+        // (becoming or staying file-region) keep npos if it is in [F, L), else
+        // take the remaining file slots in ascending order.
+        std::vector<int> top_new(h->n, -1);
+        std::vector<int> used(h->n, 0);
+        for (int q = 0; q < h->n; ++q)
+            if (mid[q] >= F && npos[q] >= F) { top_new[q] = npos[q]; used[npos[q]] = 1; }
+        int slot = F;
+        for (int q = 0; q < h->n; ++q) {
+            if (mid[q] >= F && top_new[q] < 0) {
+                while (used[slot]) ++slot;
+                top_new[q] = slot;
+                used[slot] = 1;
+            }
+        }
+        // file pointer relabel: old top index (bits at mid positions) -> new top index
+        const int ns = 1 << s, nf = 1 << (2 * s);
+        std::vector<void*> nfiles(nf, nullptr);
+        std::vector<uint8_t> nzero(ns, 1);
+        for (int oldidx = 0; oldidx < nf; ++oldidx) {
+            int newidx = 0;
+            for (int q = 0; q < h->n; ++q)
+                if (mid[q] >= F && ((oldidx >> (mid[q] - F)) & 1)) newidx |= 1 << (top_new[q] - F);
+            const int ot = oldidx >> s, nt = newidx >> s;
+            nfiles[newidx] = h->files[oldidx];
+            if (!h->slice_zero[ot]) nzero[nt] = 0;
+        }
+        // files of slice t are stored at [t * 2^s + u]: the index above is (t << s) | u
+        h->files.swap(nfiles);
+        h->slice_zero.swap(nzero);
+        // (3) remaining local permutation
+        std::vector<int> cur(h->n);
+        for (int q = 0; q < h->n; ++q) cur[q] = mid[q] >= F ? top_new[q] : mid[q];
+        bool moved3 = false;
+        for (int q = 0; q < h->n; ++q) moved3 = moved3 || (cur[q] != npos[q]);
+        if (moved3) {
+            Op op;
+            op.kind = OP_LPERM;
+            std::vector<int> from, to;
+            for (int q = 0; q < h->n; ++q)
+                if (npos[q] < L) { from.push_back(npos[q]); to.push_back(cur[q]); }
+            op.runs = make_runs((int)from.size(), from.data(), to.data());
+            h->ops.push_back(op);
+        }
+    }
+    h->pos = npos;
+    for (int p = 0; p < h->n; ++p) h->order[p] = order[p];
+    return SV_OK;
+}
+
+int gather_amplitudes(sv_handle h, int64_t count, const uint64_t* bitstrings, void* out_c128)
+{
+    return do_reduce(h, nullptr, count, bitstrings, out_c128, nullptr);
+}
+
+int reduce_slices(sv_handle h, const void* trailing_c128, int64_t count, const uint64_t* bitstrings,
+                  void* out_c128, double stats[3])
+{
+    return do_reduce(h, trailing_c128, count, bitstrings, out_c128, stats);
+}
+
+int sync_state(sv_handle h)
+{
+    CHECK_HANDLE(h);
+    int rc = flush(h);
+    if (rc) return rc;
+    TRY(h, hipStreamSynchronize(h->stream));
+    return SV_OK;
+}
+
+const char* last_error(sv_handle h)
+{
+    if (!h) return g_create_error.c_str();
+    return h->err.c_str();
+}
+
+int sv_get_order(sv_handle h, int* order)
+{
+    if (!h || !order) return SV_EINVAL;
+    for (int p = 0; p < h->n; ++p) order[p] = h->order[p];
+    return SV_OK;
+}
+
+int sv_device_buffer(sv_handle h, void** dev, size_t* bytes)
+{
+    if (!h || !dev || !bytes) return SV_EINVAL;
+    *dev = h->tier ? nullptr : h->dev;
+    *bytes = h->tier ? 0 : ((size_t)1 << h->n) * h->amp;
+    return SV_OK;
+}
+
+int sv_set_option(sv_handle h, int option, int64_t value)
+{
+    CHECK_HANDLE(h);
+    switch (option) {
+        case SV_OPT_TIMING: h->timing = value != 0; return SV_OK;
+        case SV_OPT_MFMA: h->mfma = value != 0; return SV_OK;
+        case SV_OPT_FOLD_DIAG: h->fold = value != 0; return SV_OK;
+        case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
+    }
+    return set_err(h, SV_EINVAL, "unknown option");
+}
+
+int sv_counters(sv_handle h, int64_t counters[8])
+{
+    if (!h || !counters) return SV_EINVAL;
+    for (int i = 0; i < 8; ++i) counters[i] = h->counters[i];
+    return SV_OK;
+}
+
+int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
+{
+    CHECK_HANDLE(h);
+    int rc = collect_timing(h);
+    if (rc) return rc;
+    if (total_ms) *total_ms = h->t_ms;
+    if (count) *count = h->t_count;
+    h->t_ms = 0.0;
+    h->t_count = 0;
+    return SV_OK;
+}
+
+}  // extern "C"

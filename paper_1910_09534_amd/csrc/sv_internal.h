@@ -1,0 +1,79 @@
+// Internal interface between the C-ABI host code (sv_api.cpp) and the gfx950
+// kernels (sv_kernels.hip).  Not installed; not part of the C-ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sv {
+
+constexpr int kMaxDense = 6;    // largest fused block (c64); c128 stops at 5
+constexpr int kMaxDiag = 12;    // largest diagonal op
+constexpr int kMaxRuns = 48;    // bit-move runs of a permutation
+
+// A diagonal table applied in the epilogue of a dense sweep (or on its own).
+// phase index of amplitude i = sum_j bit(i + idx_offset, pos[j]) << j.
+struct DiagSpec {
+    int m = 0;
+    int pos[kMaxDiag] = {};
+    const void* table = nullptr;   // device, 2^m entries of the state dtype
+};
+
+// Bit-position moves: dst_index = sum_r shift(src_index & mask[r], sh[r]).
+struct BitRuns {
+    int count = 0;
+    uint64_t mask[kMaxRuns] = {};
+    int shift[kMaxRuns] = {};      // > 0 left shift, < 0 right shift
+};
+
+// Build runs for "value at bit from[p] goes to bit to[p]" for p < nbits.
+BitRuns make_runs(int nbits, const int* from, const int* to);
+
+// Zero-fill count amplitudes, then set element 0 to 1 if one_at_zero.
+hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, bool one_at_zero);
+
+// Dense 2^k x 2^k block on physical positions pos[0..k) of a range of 2^nloc
+// amplitudes.  mat: device, row-major, state dtype.  fold: optional diagonal
+// applied to the outputs (same sweep).  idx_offset: global index of the
+// range's first element (feeds fold's bits above nloc).
+hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
+                        const void* mat, const DiagSpec* fold, uint64_t idx_offset,
+                        bool allow_mfma);
+
+// Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
+hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,
+                       const DiagSpec& d);
+
+// Out-of-place bit permutation of 2^nbits amplitudes: out[dst(i)] = in[i],
+// runs map destination index -> source index (dst-major gather form).
+hipError_t launch_bitperm(hipStream_t st, const void* in, void* out, int dtype, int nbits,
+                          const BitRuns& dst_to_src);
+
+// Cross-slice accumulation for `count` bitstrings (FP64 accumulators acc,
+// device, 2*count doubles).  For every j:
+//   phys = runs(x_j)                   (logical bitstring -> physical index)
+//   t    = phys >> nloc                (physical slice id of x_j)
+//   if tcol == nullptr:  acc[j] += psi_slice[phys & lowmask]  when t == slice
+//   else:                acc[j] += tcol[rowmap(t)] * psi_slice[...]  (any t)
+// rowmap: 2^s table physical-slice-id -> row index of T (device, int32).
+hipError_t launch_accumulate(hipStream_t st, const void* psi_slice, int dtype, int nloc,
+                             uint64_t slice, const BitRuns& log_to_phys, int64_t count,
+                             const uint64_t* bits, const void* tcol, const int* rowmap,
+                             double* acc);
+
+// Deterministic FP64 sum of |psi|^2 over 2^nloc amplitudes: writes
+// nblocks partial sums to partial (device), returns the block count used.
+hipError_t launch_norm_partials(hipStream_t st, const void* psi, int dtype, int nloc,
+                                double* partial, int* nblocks);
+
+// Sum of N |a_j|^2 and of ln(N |a_j|^2) over count FP64 amplitudes, written
+// as per-block pairs to partial (2 * nblocks doubles).
+hipError_t launch_xeb_partials(hipStream_t st, const double* amps, int64_t count, double logN,
+                               double* partial, int* nblocks);
+
+// Fixed-order sum of `count` runs of `width` doubles (single workgroup):
+// out[w] = sum_b partial[b * width + w].
+hipError_t launch_finish_sum(hipStream_t st, const double* partial, int count, int width,
+                             double* out);
+
+}  // namespace sv

@@ -1,0 +1,467 @@
+// gfx950 kernels of the sliced state-vector path.
+//
+// Every kernel streams the amplitude array once (read + write) and keeps the
+// per-amplitude arithmetic in registers:
+//   k_fill    initial state |0...0>                           (8/16 B per amp)
+//   k_dense   fused dense 2^k x 2^k block, optional folded diagonal epilogue
+//             (Sec. 5 aggregate gates; Sec. 2 diagonal gates as phases)
+//   k_diag    diagonal op on its own                          (Sec. 2 hyperedges)
+//   k_bitperm index permutation between layouts               (Sec. 4 reorganisation)
+//   k_accum   gather / cross-slice FP64 accumulation          (Sec. 2 slicing)
+//   k_norm, k_xeb, k_finish  fixed-order FP64 reductions (deterministic)
+//
+// Wavefronts are 64 lanes.  Lane l of a dense sweep owns group g = (block
+// base + l); the group counter is spread over the non-target bit positions
+// in ascending order, so for targets above bit 5 the 64 lanes of one load
+// instruction read 64 consecutive amplitudes (512 B for complex64).
+#include "sv_internal.h"
+
+namespace sv {
+
+template <typename R> struct Vec2;
+template <> struct Vec2<float> { using T = float2; };
+template <> struct Vec2<double> { using T = double2; };
+
+struct RunsK {
+    int count;
+    uint64_t mask[kMaxRuns];
+    int shift[kMaxRuns];
+};
+
+__device__ __forceinline__ uint64_t apply_runs(uint64_t v, const RunsK& r)
+{
+    uint64_t out = 0;
+    for (int i = 0; i < r.count; ++i) {
+        const uint64_t b = v & r.mask[i];
+        const int s = r.shift[i];
+        out |= s >= 0 ? (b << s) : (b >> (-s));
+    }
+    return out;
+}
+
+static RunsK to_k(const BitRuns& b)
+{
+    RunsK r;
+    r.count = b.count;
+    for (int i = 0; i < kMaxRuns; ++i) {
+        r.mask[i] = b.mask[i];
+        r.shift[i] = b.shift[i];
+    }
+    return r;
+}
+
+BitRuns make_runs(int nbits, const int* from, const int* to)
+{
+    // bit from[p] of the input goes to bit to[p] of the output; group
+    // maximal runs of consecutive source bits that keep the same shift.
+    int dst_of[64];
+    for (int i = 0; i < 64; ++i) dst_of[i] = -1;
+    for (int p = 0; p < nbits; ++p) dst_of[from[p]] = to[p];
+    BitRuns r;
+    int b = 0;
+    while (b < 64) {
+        if (dst_of[b] < 0) { ++b; continue; }
+        const int sh = dst_of[b] - b;
+        uint64_t mask = 0;
+        while (b < 64 && dst_of[b] >= 0 && dst_of[b] - b == sh) {
+            mask |= 1ull << b;
+            ++b;
+        }
+        r.mask[r.count] = mask;
+        r.shift[r.count] = sh;
+        ++r.count;
+    }
+    return r;
+}
+
+static unsigned grid_for(uint64_t work, unsigned block, unsigned cap = 1u << 20)
+{
+    uint64_t g = (work + block - 1) / block;
+    if (g < 1) g = 1;
+    if (g > cap) g = cap;
+    return (unsigned)g;
+}
+
+// ---------------------------------------------------------------------------
+// initial state
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_fill(uint4* __restrict__ p, uint64_t n16, uint4 first)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+        p[i] = (i == 0) ? first : make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, bool one_at_zero)
+{
+    const uint64_t bytes = count * (dtype ? 16u : 8u);
+    if (bytes % 16) return hipErrorInvalidValue;
+    uint4 first = make_uint4(0u, 0u, 0u, 0u);
+    if (one_at_zero) {
+        if (dtype) first.y = 0x3FF00000u;   // double 1.0 (high word)
+        else first.x = 0x3F800000u;         // float 1.0
+    }
+    const uint64_t n16 = bytes / 16;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n16, 256)), dim3(256), 0, st, (uint4*)psi, n16, first);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// fused dense block
+// ---------------------------------------------------------------------------
+struct DenseK {
+    uint64_t groups;
+    uint64_t idx_offset;
+    uint64_t lowmask[kMaxDense];       // (1 << p) - 1 for target positions, ascending
+    uint64_t off[1 << kMaxDense];      // offset of local index c (matrix order)
+    int fold_m;
+    int fold_pos[kMaxDiag];
+    uint32_t fold_map[1 << kMaxDense]; // fold-table bits contributed by local index c
+};
+
+template <typename R, int K, bool FOLD>
+__global__ __launch_bounds__(256) void k_dense(typename Vec2<R>::T* __restrict__ psi,
+                                               const typename Vec2<R>::T* __restrict__ mat,
+                                               const typename Vec2<R>::T* __restrict__ ftab,
+                                               DenseK a)
+{
+    using V = typename Vec2<R>::T;
+    constexpr int D = 1 << K;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.groups; g += stride) {
+        uint64_t base = g;
+#pragma unroll
+        for (int j = 0; j < K; ++j) {
+            const uint64_t low = base & a.lowmask[j];
+            base = ((base ^ low) << 1) | low;
+        }
+        V x[D];
+#pragma unroll
+        for (int c = 0; c < D; ++c) x[c] = psi[base + a.off[c]];
+        uint32_t fb = 0;
+        if (FOLD) {
+            const uint64_t gi = base + a.idx_offset;
+            for (int j = 0; j < a.fold_m; ++j) fb |= (uint32_t)((gi >> a.fold_pos[j]) & 1u) << j;
+        }
+#pragma unroll
+        for (int r = 0; r < D; ++r) {
+            R re = 0, im = 0;
+#pragma unroll
+            for (int c = 0; c < D; ++c) {
+                const V m = mat[r * D + c];
+                re = fma(m.x, x[c].x, re);
+                re = fma(-m.y, x[c].y, re);
+                im = fma(m.x, x[c].y, im);
+                im = fma(m.y, x[c].x, im);
+            }
+            if (FOLD) {
+                const V p = ftab[fb | a.fold_map[r]];
+                const R t = re * p.x - im * p.y;
+                im = re * p.y + im * p.x;
+                re = t;
+            }
+            psi[base + a.off[r]] = V{re, im};
+        }
+    }
+}
+
+template <typename R, int K>
+static hipError_t dense_dispatch(hipStream_t st, void* psi, const void* mat, const void* ftab,
+                                 const DenseK& a, bool fold)
+{
+    using V = typename Vec2<R>::T;
+    const dim3 grid(grid_for(a.groups, 256)), block(256);
+    if (fold)
+        hipLaunchKernelGGL((k_dense<R, K, true>), grid, block, 0, st, (V*)psi, (const V*)mat,
+                           (const V*)ftab, a);
+    else
+        hipLaunchKernelGGL((k_dense<R, K, false>), grid, block, 0, st, (V*)psi, (const V*)mat,
+                           (const V*)ftab, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
+                        const void* mat, const DiagSpec* fold, uint64_t idx_offset, bool allow_mfma)
+{
+    (void)allow_mfma;
+    if (k < 1 || k > kMaxDense || k > nloc) return hipErrorInvalidValue;
+    if (dtype && k > 5) return hipErrorInvalidValue;
+    DenseK a{};
+    a.groups = 1ull << (nloc - k);
+    a.idx_offset = idx_offset;
+    int sp[kMaxDense];
+    for (int j = 0; j < k; ++j) sp[j] = pos[j];
+    for (int j = 1; j < k; ++j)
+        for (int l = j; l > 0 && sp[l - 1] > sp[l]; --l) {
+            const int t = sp[l]; sp[l] = sp[l - 1]; sp[l - 1] = t;
+        }
+    for (int j = 0; j < k; ++j) a.lowmask[j] = (1ull << sp[j]) - 1;
+    for (int c = 0; c < (1 << k); ++c) {
+        uint64_t o = 0;
+        for (int j = 0; j < k; ++j)
+            if ((c >> j) & 1) o |= 1ull << pos[j];
+        a.off[c] = o;
+    }
+    const bool do_fold = fold && fold->m > 0;
+    if (do_fold) {
+        a.fold_m = fold->m;
+        for (int j = 0; j < fold->m; ++j) a.fold_pos[j] = fold->pos[j];
+        for (int c = 0; c < (1 << k); ++c) {
+            uint32_t b = 0;
+            for (int j = 0; j < fold->m; ++j)
+                if ((a.off[c] >> fold->pos[j]) & 1) b |= 1u << j;
+            a.fold_map[c] = b;
+        }
+    }
+    const void* ft = do_fold ? fold->table : nullptr;
+    if (dtype == 0) {
+        switch (k) {
+            case 1: return dense_dispatch<float, 1>(st, psi, mat, ft, a, do_fold);
+            case 2: return dense_dispatch<float, 2>(st, psi, mat, ft, a, do_fold);
+            case 3: return dense_dispatch<float, 3>(st, psi, mat, ft, a, do_fold);
+            case 4: return dense_dispatch<float, 4>(st, psi, mat, ft, a, do_fold);
+            case 5: return dense_dispatch<float, 5>(st, psi, mat, ft, a, do_fold);
+            case 6: return dense_dispatch<float, 6>(st, psi, mat, ft, a, do_fold);
+        }
+    } else {
+        switch (k) {
+            case 1: return dense_dispatch<double, 1>(st, psi, mat, ft, a, do_fold);
+            case 2: return dense_dispatch<double, 2>(st, psi, mat, ft, a, do_fold);
+            case 3: return dense_dispatch<double, 3>(st, psi, mat, ft, a, do_fold);
+            case 4: return dense_dispatch<double, 4>(st, psi, mat, ft, a, do_fold);
+            case 5: return dense_dispatch<double, 5>(st, psi, mat, ft, a, do_fold);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+// ---------------------------------------------------------------------------
+// diagonal op
+// ---------------------------------------------------------------------------
+struct DiagK {
+    uint64_t count;
+    uint64_t idx_offset;
+    int m;
+    int pos[kMaxDiag];
+};
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_diag(typename Vec2<R>::T* __restrict__ psi,
+                                              const typename Vec2<R>::T* __restrict__ tab, DiagK a)
+{
+    using V = typename Vec2<R>::T;
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += stride) {
+        const uint64_t gi = i + a.idx_offset;
+        uint32_t c = 0;
+        for (int j = 0; j < a.m; ++j) c |= (uint32_t)((gi >> a.pos[j]) & 1u) << j;
+        const V p = tab[c];
+        const V v = psi[i];
+        psi[i] = V{v.x * p.x - v.y * p.y, v.x * p.y + v.y * p.x};
+    }
+}
+
+hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,
+                       const DiagSpec& d)
+{
+    if (d.m < 1 || d.m > kMaxDiag) return hipErrorInvalidValue;
+    DiagK a{};
+    a.count = 1ull << nloc;
+    a.idx_offset = idx_offset;
+    a.m = d.m;
+    for (int j = 0; j < d.m; ++j) a.pos[j] = d.pos[j];
+    const dim3 grid(grid_for(a.count, 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_diag<float>, grid, block, 0, st, (float2*)psi, (const float2*)d.table, a);
+    else
+        hipLaunchKernelGGL(k_diag<double>, grid, block, 0, st, (double2*)psi, (const double2*)d.table, a);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// bit permutation (out-of-place gather form)
+// ---------------------------------------------------------------------------
+template <typename V>
+__global__ __launch_bounds__(256) void k_bitperm(const V* __restrict__ in, V* __restrict__ out,
+                                                 uint64_t count, RunsK dst_to_src)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t o = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; o < count; o += stride)
+        out[o] = in[apply_runs(o, dst_to_src)];
+}
+
+hipError_t launch_bitperm(hipStream_t st, const void* in, void* out, int dtype, int nbits,
+                          const BitRuns& dst_to_src)
+{
+    const uint64_t count = 1ull << nbits;
+    const RunsK r = to_k(dst_to_src);
+    const dim3 grid(grid_for(count, 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_bitperm<float2>, grid, block, 0, st, (const float2*)in, (float2*)out, count, r);
+    else
+        hipLaunchKernelGGL(k_bitperm<double2>, grid, block, 0, st, (const double2*)in, (double2*)out, count, r);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// gather / cross-slice accumulation in FP64
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(256) void k_accum(const typename Vec2<R>::T* __restrict__ psi, int nloc,
+                                               uint64_t slice, RunsK l2p, int64_t count,
+                                               const uint64_t* __restrict__ bits,
+                                               const double2* __restrict__ tcol,
+                                               const int* __restrict__ rowmap,
+                                               double2* __restrict__ acc)
+{
+    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= count) return;
+    const uint64_t ph = apply_runs(bits[j], l2p);
+    const uint64_t t = nloc >= 64 ? 0 : (ph >> nloc);
+    const uint64_t li = ph & ((nloc >= 64) ? ~0ull : ((1ull << nloc) - 1));
+    if (tcol == nullptr) {
+        if (t == slice) {
+            const auto a = psi[li];
+            double2 s = acc[j];
+            s.x += (double)a.x;
+            s.y += (double)a.y;
+            acc[j] = s;
+        }
+    } else {
+        const auto a = psi[li];
+        const double2 w = tcol[rowmap[t]];
+        const double ar = (double)a.x, ai = (double)a.y;
+        double2 s = acc[j];
+        s.x += w.x * ar - w.y * ai;
+        s.y += w.x * ai + w.y * ar;
+        acc[j] = s;
+    }
+}
+
+hipError_t launch_accumulate(hipStream_t st, const void* psi_slice, int dtype, int nloc,
+                             uint64_t slice, const BitRuns& log_to_phys, int64_t count,
+                             const uint64_t* bits, const void* tcol, const int* rowmap,
+                             double* acc)
+{
+    if (count <= 0) return hipSuccess;
+    const RunsK r = to_k(log_to_phys);
+    const dim3 grid((unsigned)((count + 255) / 256)), block(256);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_accum<float>, grid, block, 0, st, (const float2*)psi_slice, nloc, slice, r,
+                           count, bits, (const double2*)tcol, rowmap, (double2*)acc);
+    else
+        hipLaunchKernelGGL(k_accum<double>, grid, block, 0, st, (const double2*)psi_slice, nloc, slice,
+                           r, count, bits, (const double2*)tcol, rowmap, (double2*)acc);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// deterministic FP64 reductions
+// ---------------------------------------------------------------------------
+// Block-level tree in LDS with a fixed shape: the result depends only on the
+// input and the launch geometry, which depends only on the size.
+template <int W>
+__device__ __forceinline__ void block_tree(double (*sh)[256], double* v)
+{
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int w = 0; w < W; ++w) sh[w][t] = v[w];
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (t < h) {
+#pragma unroll
+            for (int w = 0; w < W; ++w) sh[w][t] += sh[w][t + h];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int w = 0; w < W; ++w) v[w] = sh[w][0];
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void k_norm(const typename Vec2<R>::T* __restrict__ psi,
+                                              uint64_t per_block, double* __restrict__ partial)
+{
+    __shared__ double sh[1][256];
+    const uint64_t b0 = (uint64_t)blockIdx.x * per_block;
+    double s = 0.0;
+    for (uint64_t i = threadIdx.x; i < per_block; i += 256) {
+        const auto a = psi[b0 + i];
+        const double re = (double)a.x, im = (double)a.y;
+        s = fma(re, re, s);
+        s = fma(im, im, s);
+    }
+    double v[1] = {s};
+    block_tree<1>(sh, v);
+    if (threadIdx.x == 0) partial[blockIdx.x] = v[0];
+}
+
+hipError_t launch_norm_partials(hipStream_t st, const void* psi, int dtype, int nloc,
+                                double* partial, int* nblocks)
+{
+    const int lb = nloc > 20 ? 12 : (nloc > 8 ? nloc - 8 : 0);
+    const int nb = 1 << lb;
+    const uint64_t per = 1ull << (nloc - lb);
+    if (dtype == 0)
+        hipLaunchKernelGGL(k_norm<float>, dim3(nb), dim3(256), 0, st, (const float2*)psi, per, partial);
+    else
+        hipLaunchKernelGGL(k_norm<double>, dim3(nb), dim3(256), 0, st, (const double2*)psi, per, partial);
+    *nblocks = nb;
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_xeb(const double2* __restrict__ amps, int64_t count,
+                                             int64_t per_block, double logN,
+                                             double* __restrict__ partial)
+{
+    __shared__ double sh[2][256];
+    const int64_t b0 = (int64_t)blockIdx.x * per_block;
+    const double N = exp2(logN);
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = threadIdx.x; i < per_block; i += 256) {
+        const int64_t j = b0 + i;
+        if (j >= count) break;
+        const double2 a = amps[j];
+        const double p = N * (a.x * a.x + a.y * a.y);
+        v[0] += p;
+        v[1] += log(p);
+    }
+    block_tree<2>(sh, v);
+    if (threadIdx.x == 0) {
+        partial[2 * blockIdx.x] = v[0];
+        partial[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+hipError_t launch_xeb_partials(hipStream_t st, const double* amps, int64_t count, double logN,
+                               double* partial, int* nblocks)
+{
+    int nb = (int)((count + 4095) / 4096);
+    if (nb < 1) nb = 1;
+    if (nb > 4096) nb = 4096;
+    const int64_t per = (count + nb - 1) / nb;
+    hipLaunchKernelGGL(k_xeb, dim3(nb), dim3(256), 0, st, (const double2*)amps, count, per, logN, partial);
+    *nblocks = nb;
+    return hipGetLastError();
+}
+
+__global__ __launch_bounds__(256) void k_finish(const double* __restrict__ partial, int count, int width,
+                                                double* __restrict__ out)
+{
+    __shared__ double sh[2][256];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < count; b += 256)
+        for (int w = 0; w < width && w < 2; ++w) v[w] += partial[(int64_t)b * width + w];
+    block_tree<2>(sh, v);
+    if (threadIdx.x == 0)
+        for (int w = 0; w < width && w < 2; ++w) out[w] = v[w];
+}
+
+hipError_t launch_finish_sum(hipStream_t st, const double* partial, int count, int width, double* out)
+{
+    if (width < 1 || width > 2) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_finish, dim3(1), dim3(256), 0, st, partial, count, width, out);
+    return hipGetLastError();
+}
+
+}  // namespace sv

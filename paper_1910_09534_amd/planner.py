@@ -1,0 +1,177 @@
+"""Host-side planning of a circuit into library operations (untimed).
+
+* Gate aggregation (Sec. 5): gates are grouped into clusters spanning at most
+  k qubits; each cluster becomes one 2^k x 2^k matrix, i.e. one dense sweep.
+  Clustering is greedy over the gate list: each open cluster owns a disjoint
+  set of qubits; a gate joins (and merges) the clusters it touches when the
+  union stays within k qubits, otherwise those clusters are emitted and the
+  gate starts a new one.  Per qubit, gate order is preserved, and clusters
+  on disjoint qubits commute, so the product is unchanged.
+* Diagonal extraction (Sec. 2: diagonal tensors are hyperedges; Eq. 1 has a
+  diagonal |11> phase): a two-qubit gate of the Eq. (1) sparsity pattern
+  splits exactly into diag(m00, 1, 1, m33) times a gate acting only on the
+  |01>, |10> block.  With fold_diag the diagonal part is emitted as its own
+  op right after the cluster holding the non-diagonal part, and the library
+  folds it into that cluster's sweep as an element-wise phase.
+* Slice phases (Sec. 4): `phase_schedule` splits the gate list into phases,
+  each with a set of sliced qubits on which only diagonal work may happen,
+  alternating between two slice sets like the paper's subcircuits 3..9.
+
+All arithmetic here is FP64 on tiny matrices; the results are handed to the
+library in the state's dtype.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Dict, List, Optional, Sequence, Tuple
+
+import numpy as np
+
+
+@dataclasses.dataclass
+class Op:
+    kind: str                       # "dense" | "diag" | "perm"
+    qubits: Tuple[int, ...] = ()
+    matrix: Optional[np.ndarray] = None   # dense: (2^k, 2^k); diag: (2^m,)
+    order: Optional[List[int]] = None     # perm
+    ngates: int = 0                 # circuit gates this op carries
+
+
+def embed_in(block_qubits: Sequence[int], gate_qubits: Sequence[int], g: np.ndarray) -> np.ndarray:
+    """Matrix of gate g (index = sum_j b(gate_qubits[j]) 2^j) on the index
+    space of block_qubits (a superset), as a 2^k x 2^k array."""
+    k = len(block_qubits)
+    where = [list(block_qubits).index(q) for q in gate_qubits]
+    idx = np.arange(1 << k)
+    sub = np.zeros(1 << k, dtype=np.int64)
+    rest = idx.copy()
+    for j, w in enumerate(where):
+        bit = (idx >> w) & 1
+        sub |= bit << j
+        rest &= ~(1 << w)
+    same = rest[:, None] == rest[None, :]
+    return np.where(same, g[sub[:, None], sub[None, :]], 0).astype(np.complex128)
+
+
+def split_eq1(m: np.ndarray):
+    """Split a 4x4 of the Eq. (1) pattern into (diag, middle-block gate):
+    m = diag(m00, 1, 1, m33) @ x.  Returns None for other matrices."""
+    if m.shape != (4, 4):
+        return None
+    mask = np.zeros((4, 4), dtype=bool)
+    mask[0, 0] = mask[3, 3] = True
+    mask[1:3, 1:3] = True
+    if np.any(m[~mask] != 0):
+        return None
+    d = np.array([m[0, 0], 1.0, 1.0, m[3, 3]], dtype=np.complex128)
+    x = np.eye(4, dtype=np.complex128)
+    x[1:3, 1:3] = m[1:3, 1:3]
+    return d, x
+
+
+class _Block:
+    __slots__ = ("qubits", "m", "ngates", "first")
+
+    def __init__(self, qubits, m, ngates, first):
+        self.qubits = list(qubits)
+        self.m = m
+        self.ngates = ngates
+        self.first = first
+
+
+def fuse(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
+    """Greedy aggregation of `gates` (objects with .qubits, .matrix) into
+    dense blocks of at most kmax qubits (and diagonal ops with fold_diag)."""
+    ops: List[Op] = []
+    owner: Dict[int, _Block] = {}
+    counter = [0]
+
+    def emit(b: _Block):
+        for q in b.qubits:
+            del owner[q]
+        ops.append(Op("dense", tuple(b.qubits), b.m, ngates=b.ngates))
+
+    def add_dense(qs, m, ng):
+        touching = []
+        for q in qs:
+            b = owner.get(q)
+            if b is not None and b not in touching:
+                touching.append(b)
+        union = []
+        for b in touching:
+            union += b.qubits
+        for q in qs:
+            if q not in union:
+                union.append(q)
+        if len(union) <= kmax:
+            # merge the touching blocks (disjoint: they commute) by Kronecker product
+            if touching:
+                cur_q = list(touching[0].qubits)
+                cur_m = touching[0].m
+                ngs = touching[0].ngates
+                first = min(b.first for b in touching)
+                for b in touching[1:]:
+                    cur_m = np.kron(b.m, cur_m)
+                    cur_q += b.qubits
+                    ngs += b.ngates
+                for b in touching:
+                    for q in b.qubits:
+                        del owner[q]
+            else:
+                cur_q, cur_m, ngs, first = [], np.eye(1, dtype=np.complex128), 0, counter[0]
+            for q in qs:
+                if q not in cur_q:
+                    cur_m = np.kron(np.eye(2, dtype=np.complex128), cur_m)
+                    cur_q.append(q)
+            cur_m = embed_in(cur_q, qs, m) @ cur_m
+            nb = _Block(cur_q, cur_m, ngs + ng, first)
+        else:
+            for b in touching:
+                emit(b)
+            nb = _Block(list(qs), np.array(m, dtype=np.complex128), ng, counter[0])
+        for q in nb.qubits:
+            owner[q] = nb
+        counter[0] += 1
+
+    for g in gates:
+        qs = tuple(g.qubits)
+        m = np.asarray(g.matrix, dtype=np.complex128)
+        parts = split_eq1(m) if (fold_diag and len(qs) == 2) else None
+        if parts is None:
+            add_dense(qs, m, 1)
+            continue
+        d, x = parts
+        add_dense(qs, x, 1)
+        # the diagonal commutes with x (same qubits); emit it right after the
+        # block that now holds x, and close that block so no later gate on
+        # these qubits is applied before the phase
+        b = owner[qs[0]]
+        emit(b)
+        ops.append(Op("diag", qs, d, ngates=0))
+    for b in sorted(set(owner.values()), key=lambda b: b.first):
+        ops.append(Op("dense", tuple(b.qubits), b.m, ngates=b.ngates))
+    return ops
+
+
+def stats(ops: Sequence[Op]) -> Dict[str, object]:
+    hist: Dict[int, int] = {}
+    for o in ops:
+        if o.kind == "dense":
+            hist[len(o.qubits)] = hist.get(len(o.qubits), 0) + 1
+    return {"dense": sum(1 for o in ops if o.kind == "dense"),
+            "diag": sum(1 for o in ops if o.kind == "diag"),
+            "perm": sum(1 for o in ops if o.kind == "perm"),
+            "k_hist": dict(sorted(hist.items())),
+            "flops_per_amp": sum((8 * (1 << len(o.qubits)) - 2) for o in ops if o.kind == "dense")}
+
+
+def enqueue(state_handle, ops: Sequence[Op], dtype) -> None:
+    """Hand a planned op list to the library (argument marshalling only)."""
+    from . import sv
+    for o in ops:
+        if o.kind == "dense":
+            sv.apply_fused(state_handle, o.qubits, o.matrix, dtype)
+        elif o.kind == "diag":
+            sv.apply_diag(state_handle, o.qubits, o.matrix, dtype)
+        else:
+            sv.permute_qubits(state_handle, o.order)

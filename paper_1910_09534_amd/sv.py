@@ -1,0 +1,239 @@
+"""Python binding of libsv (ctypes).  Argument marshalling only: every step of
+the path runs in the HIP library.  The names follow the C-ABI (include/sv.h).
+
+The library must have been built (`python -m paper_1910_09534_amd.build`);
+there is no fallback: importing this module without libsv.so raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsv.so")
+
+SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, -2, -3, -4, -5, -6
+SV_C64, SV_C128 = 0, 1
+SV_FLAG_TIER, SV_FLAG_KEEP = 0x100, 0x200
+SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS = 1, 2, 3, 4
+
+ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
+               SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
+
+EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "apply_diag",
+           "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "last_error",
+           "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time")
+
+
+class SVError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"{ERROR_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def load():
+    """Load libsv.so (raises if it has not been built)."""
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libsv.so not built ({LIB_PATH}); run python -m paper_1910_09534_amd.build")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
+    L.create_state.argtypes = [I, U64, I, P, ctypes.POINTER(P)]
+    L.create_state_ext.argtypes = [I, U64, I, P, P, SZ, ctypes.POINTER(P)]
+    L.destroy_state.argtypes = [P]
+    L.apply_fused.argtypes = [P, I, P, P]
+    L.apply_diag.argtypes = [P, I, P, P]
+    L.permute_qubits.argtypes = [P, P]
+    L.gather_amplitudes.argtypes = [P, I64, P, P]
+    L.reduce_slices.argtypes = [P, P, I64, P, P, P]
+    L.sync_state.argtypes = [P]
+    L.last_error.argtypes = [P]
+    L.last_error.restype = ctypes.c_char_p
+    L.sv_get_order.argtypes = [P, P]
+    L.sv_device_buffer.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(SZ)]
+    L.sv_set_option.argtypes = [P, I, I64]
+    L.sv_counters.argtypes = [P, P]
+    L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+    for name in EXPORTS:
+        getattr(L, name).restype = ctypes.c_char_p if name == "last_error" else ctypes.c_int
+    return L
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        _lib = load()
+    return _lib
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _check(rc: int, h=None):
+    if rc != SV_OK:
+        msg = lib().last_error(h)
+        raise SVError(rc, msg.decode() if msg else "")
+
+
+def _dtype_code(dtype) -> int:
+    if dtype in ("c64", "complex64", np.complex64, SV_C64):
+        return SV_C64
+    if dtype in ("c128", "complex128", np.complex128, SV_C128):
+        return SV_C128
+    raise ValueError(f"dtype {dtype!r}")
+
+
+def np_dtype(code: int):
+    return np.complex64 if code == SV_C64 else np.complex128
+
+
+def create_state(n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False):
+    """Returns an opaque handle (int)."""
+    h = ctypes.c_void_p()
+    code = _dtype_code(dtype) | (SV_FLAG_TIER if tier else 0)
+    _check(lib().create_state(n, slice_mask, code, stream, ctypes.byref(h)))
+    return h.value
+
+
+def create_state_ext(n: int, slice_mask: int, dtype, stream, dev_ptr: int, nbytes: int,
+                     keep: bool = False):
+    h = ctypes.c_void_p()
+    code = _dtype_code(dtype) | (SV_FLAG_KEEP if keep else 0)
+    _check(lib().create_state_ext(n, slice_mask, code, stream, dev_ptr, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def destroy_state(h) -> None:
+    _check(lib().destroy_state(h))
+
+
+def apply_fused(h, qubits: Sequence[int], matrix: np.ndarray, dtype) -> int:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    m = np.ascontiguousarray(matrix, dtype=np_dtype(_dtype_code(dtype)))
+    rc = lib().apply_fused(h, len(q), _ptr(q), _ptr(m))
+    _check(rc, h)
+    return rc
+
+
+def apply_diag(h, qubits: Sequence[int], phases: np.ndarray, dtype) -> int:
+    q = np.ascontiguousarray(qubits, dtype=np.int32)
+    d = np.ascontiguousarray(phases, dtype=np_dtype(_dtype_code(dtype)))
+    rc = lib().apply_diag(h, len(q), _ptr(q), _ptr(d))
+    _check(rc, h)
+    return rc
+
+
+def permute_qubits(h, order: Sequence[int]) -> None:
+    o = np.ascontiguousarray(order, dtype=np.int32)
+    _check(lib().permute_qubits(h, _ptr(o)), h)
+
+
+def gather_amplitudes(h, bitstrings: np.ndarray) -> np.ndarray:
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    out = np.empty(b.size, dtype=np.complex128)
+    _check(lib().gather_amplitudes(h, b.size, _ptr(b), _ptr(out)), h)
+    return out
+
+
+def reduce_slices(h, bitstrings: np.ndarray, trailing: Optional[np.ndarray] = None):
+    """Returns (amplitudes complex128, stats (norm, sum N p, sum ln N p))."""
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    out = np.empty(b.size, dtype=np.complex128)
+    stats = np.zeros(3, dtype=np.float64)
+    t = None if trailing is None else np.ascontiguousarray(trailing, dtype=np.complex128)
+    _check(lib().reduce_slices(h, None if t is None else _ptr(t), b.size, _ptr(b), _ptr(out),
+                               _ptr(stats)), h)
+    return out, tuple(float(x) for x in stats)
+
+
+def sync_state(h) -> None:
+    _check(lib().sync_state(h), h)
+
+
+def last_error(h=None) -> str:
+    m = lib().last_error(h)
+    return m.decode() if m else ""
+
+
+def get_order(h, n: int) -> list:
+    o = np.zeros(n, dtype=np.int32)
+    _check(lib().sv_get_order(h, _ptr(o)))
+    return o.tolist()
+
+
+def device_buffer(h):
+    p = ctypes.c_void_p()
+    sz = ctypes.c_size_t()
+    _check(lib().sv_device_buffer(h, ctypes.byref(p), ctypes.byref(sz)))
+    return p.value, sz.value
+
+
+def set_option(h, option: int, value: int) -> None:
+    _check(lib().sv_set_option(h, option, value), h)
+
+
+def counters(h) -> dict:
+    c = np.zeros(8, dtype=np.int64)
+    _check(lib().sv_counters(h, _ptr(c)))
+    keys = ("dense_sweeps", "diag_sweeps", "perm_sweeps", "amps_swept", "bytes_h2d", "bytes_d2h",
+            "zero_slices_skipped", "reserved")
+    return dict(zip(keys, (int(x) for x in c)))
+
+
+def sweep_time(h):
+    ms = ctypes.c_double()
+    cnt = ctypes.c_int64()
+    _check(lib().sv_sweep_time(h, ctypes.byref(ms), ctypes.byref(cnt)), h)
+    return ms.value, cnt.value
+
+
+class State:
+    """Owning wrapper around a handle (context manager)."""
+
+    def __init__(self, n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False):
+        self.n, self.slice_mask, self.dtype = n, slice_mask, _dtype_code(dtype)
+        self.h = create_state(n, slice_mask, dtype, stream, tier)
+
+    def fused(self, qubits, matrix):
+        apply_fused(self.h, qubits, matrix, self.dtype)
+
+    def diag(self, qubits, phases):
+        apply_diag(self.h, qubits, phases, self.dtype)
+
+    def permute(self, order):
+        permute_qubits(self.h, order)
+
+    def gather(self, bits):
+        return gather_amplitudes(self.h, bits)
+
+    def reduce(self, bits, trailing=None):
+        return reduce_slices(self.h, bits, trailing)
+
+    def sync(self):
+        sync_state(self.h)
+
+    def order(self):
+        return get_order(self.h, self.n)
+
+    def close(self):
+        if self.h:
+            destroy_state(self.h)
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,208 @@
+"""GPU parity: the HIP path (through the C-ABI) against the CPU oracle, on
+the same seeded inputs.  Tolerances: rel-L2 <= 1e-4 for complex64 state
+arithmetic, <= 1e-12 for complex128 (relative L2 over the returned
+amplitudes).  Every call goes through libsv.so; nothing falls back."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import brute
+from oracle import oracle as orc
+from paper_1910_09534_amd import planner, runner, sv
+from paper_1910_09534_amd import workload as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"c64": 1e-4, "c128": 1e-12}
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def state_from_numpy(psi: np.ndarray, dtype: str, slice_mask: int = 0):
+    """Resident state whose buffer (a torch tensor) holds psi in the initial
+    layout (unsliced qubits ascending, then sliced ones)."""
+    torch = _torch()
+    n = int(psi.size).bit_length() - 1
+    tdt = torch.complex64 if dtype == "c64" else torch.complex128
+    order = [q for q in range(n) if not (slice_mask >> q) & 1] + \
+            [q for q in range(n) if (slice_mask >> q) & 1]
+    phys = brute.permute_state(psi, n, order) if slice_mask else psi
+    t = torch.from_numpy(phys.astype(np.complex64 if dtype == "c64" else np.complex128)).to("cuda")
+    torch.cuda.synchronize()
+    h = sv.create_state_ext(n, slice_mask, dtype, None, t.data_ptr(), t.numel() * t.element_size(),
+                            keep=True)
+    return h, t
+
+
+def read_all(h, n):
+    return sv.gather_amplitudes(h, np.arange(1 << n, dtype=np.uint64))
+
+
+# ---- single operations on random states ---------------------------------------
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("qs", [(0,), (5,), (11,), (1, 0), (3, 9), (0, 6, 2), (7, 1, 10, 4),
+                                (2, 8, 0, 11, 5), (9, 3, 6, 0, 11, 1)])
+def test_dense_single_op(dtype, qs):
+    if dtype == "c128" and len(qs) > 5:
+        pytest.skip("complex128 blocks stop at k=5")
+    n = 12
+    rng = np.random.default_rng(len(qs) * 100 + qs[0])
+    psi = W.random_state(n, rng)
+    u = W.random_unitary(1 << len(qs), rng)
+    h, t = state_from_numpy(psi, dtype)
+    try:
+        sv.apply_fused(h, qs, u, dtype)
+        got = read_all(h, n)
+    finally:
+        sv.destroy_state(h)
+    ref = orc.apply_dense(psi.copy(), qs, u)
+    assert orc.rel_l2(got, ref) <= TOL[dtype] * 0.1
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+@pytest.mark.parametrize("fold", [True, False])
+def test_diag_standalone_and_folded(dtype, fold):
+    n = 13
+    rng = np.random.default_rng(7)
+    psi = W.random_state(n, rng)
+    u = W.random_unitary(8, rng)
+    d1 = W.random_phases(8, rng)
+    d2 = W.random_phases(4, rng)
+    h, t = state_from_numpy(psi, dtype)
+    try:
+        sv.set_option(h, sv.SV_OPT_FOLD_DIAG, 1 if fold else 0)
+        sv.apply_fused(h, (4, 0, 9), u, dtype)
+        sv.apply_diag(h, (12, 0, 5), d1, dtype)      # folded into the sweep above
+        sv.apply_diag(h, (3, 10), d2, dtype)         # standalone
+        got = read_all(h, n)
+    finally:
+        sv.destroy_state(h)
+    ref = orc.apply_dense(psi.copy(), (4, 0, 9), u)
+    orc.apply_diag(ref, (12, 0, 5), d1)
+    orc.apply_diag(ref, (3, 10), d2)
+    assert orc.rel_l2(got, ref) <= TOL[dtype] * 0.1
+
+
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
+def test_permute_resident(dtype):
+    n = 11
+    rng = np.random.default_rng(5)
+    psi = W.random_state(n, rng)
+    h, t = state_from_numpy(psi, dtype)
+    order = [int(x) for x in rng.permutation(n)]
+    try:
+        sv.permute_qubits(h, order)
+        assert sv.get_order(h, n) == order
+        sv.sync_state(h)
+        raw = t.cpu().numpy().astype(np.complex128)
+        # physical buffer = the layout map of the logical state
+        assert np.abs(raw - brute.permute_state(psi, n, order)).max() <= 1e-6
+        # logical reads are unaffected; gates after a permute address logical qubits
+        u = W.random_unitary(4, rng)
+        sv.apply_fused(h, (order[0], order[7]), u, dtype)
+        got = read_all(h, n)
+    finally:
+        sv.destroy_state(h)
+    ref = orc.apply_dense(psi.copy(), (order[0], order[7]), u)
+    assert orc.rel_l2(got, ref) <= TOL[dtype] * 0.1
+
+
+# ---- whole circuits ---------------------------------------------------------------
+
+def test_cfg1_all_amplitudes_c128():
+    """4x4 grid, depth 8, complex128: all 65536 amplitudes within 1e-12."""
+    c = W.config_circuit(1)
+    bits = W.config_bitstrings(1)
+    res = runner.simulate(c, bits, dtype="c128", kmax=4)
+    ref = orc.simulate(c)
+    assert orc.rel_l2(res["amps"], ref[bits.astype(np.int64)]) <= TOL["c128"]
+    assert abs(res["norm"] - 1) < 1e-12
+
+
+@pytest.mark.parametrize("kmax", [2, 3, 4, 5, 6])
+@pytest.mark.parametrize("fold", [False, True])
+def test_circuit_c64_vs_oracle(kmax, fold):
+    n, d = 20, 14
+    c = W.sycamore_circuit(n, d, seed=2002)
+    bits = W.bitstrings(n, 4096, seed=3)
+    res = runner.simulate(c, bits, dtype="c64", kmax=kmax, fold_diag=fold)
+    ref = orc.gather(orc.simulate(c), bits)
+    assert orc.rel_l2(res["amps"], ref) <= TOL["c64"]
+    assert abs(res["norm"] - 1) < 1e-4
+
+
+def test_circuit_c128_k5():
+    n = 18
+    c = W.sycamore_circuit(n, 10, seed=44)
+    bits = W.bitstrings(n, 2048, seed=4)
+    res = runner.simulate(c, bits, dtype="c128", kmax=5)
+    ref = orc.gather(orc.simulate(c), bits)
+    assert orc.rel_l2(res["amps"], ref) <= TOL["c128"]
+
+
+def test_stats_match_oracle():
+    n = 16
+    c = W.sycamore_circuit(n, 12, seed=9)
+    bits = W.bitstrings(n, 5000, seed=10)
+    res = runner.simulate(c, bits, dtype="c128", kmax=4)
+    psi = orc.simulate(c)
+    amps, (nrm, s1, s2) = orc.reduce_slices_ref(psi, (), None, bits)
+    assert abs(res["norm"] - nrm) < 1e-12
+    assert abs(res["xeb_sum"] - s1) < 1e-9 * abs(s1)
+    assert abs(res["xeb_log_sum"] - s2) < 1e-9 * abs(s2)
+
+
+# ---- slicing ----------------------------------------------------------------------
+
+def test_sliced_resident_reduce_with_trailing():
+    """Slices resident in HBM: out[x] = sum_t T[x_S, t] psi_t(x_L) equals the
+    unsliced state with T applied to the sliced qubits."""
+    n = 12
+    rng = np.random.default_rng(12)
+    S = (2, 7, 11)
+    mask = sum(1 << q for q in S)
+    c = W.sycamore_circuit(n, 6, seed=13)
+    psi = orc.simulate(c)
+    h, t = state_from_numpy(psi, "c128", slice_mask=mask)
+    T = W.random_unitary(8, rng)
+    bits = rng.integers(0, 1 << n, size=3000).astype(np.uint64)
+    try:
+        amps, stats = sv.reduce_slices(h, bits, T)
+        gath = sv.gather_amplitudes(h, bits)
+    finally:
+        sv.destroy_state(h)
+    ref, (nrm, s1, s2) = orc.reduce_slices_ref(psi, S, T, bits)
+    assert orc.rel_l2(amps, ref) <= 1e-12
+    assert abs(stats[0] - nrm) < 1e-12
+    assert orc.rel_l2(gath, psi[bits.astype(np.int64)]) <= 1e-12
+
+
+def test_dense_on_sliced_qubit_rejected():
+    _torch()
+    h = sv.create_state(8, 1 << 3, "c64")
+    try:
+        with pytest.raises(sv.SVError) as e:
+            sv.apply_fused(h, (3, 1), np.eye(4), "c64")
+        assert e.value.code == sv.SV_ESLICED
+        sv.apply_diag(h, (3, 1), np.ones(4), "c64")   # diagonal on a sliced qubit is fine
+        with pytest.raises(sv.SVError) as e:
+            sv.apply_fused(h, (1, 1), np.eye(4), "c64")
+        assert e.value.code == sv.SV_EINVAL
+        with pytest.raises(sv.SVError) as e:
+            sv.permute_qubits(h, [0, 1, 2, 3, 4, 5, 6, 6])
+        assert e.value.code == sv.SV_EINVAL
+        with pytest.raises(sv.SVError) as e:
+            sv.gather_amplitudes(h, np.array([256], dtype=np.uint64))
+        assert e.value.code == sv.SV_EINVAL
+        a = sv.gather_amplitudes(h, np.array([0, 1], dtype=np.uint64))
+        assert abs(a[0] - 1) == 0 and a[1] == 0
+    finally:
+        sv.destroy_state(h)

@@ -1,0 +1,101 @@
+"""CPU-only checks of the host logic: the planner (fusion and diagonal
+extraction are exact re-associations, checked on the oracle), and that the
+C-ABI library loads and exports every function include/sv.h declares."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import oracle as orc
+from paper_1910_09534_amd import planner
+from paper_1910_09534_amd import workload as W
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def apply_ops_on_oracle(n, ops):
+    psi = orc.zero_state(n)
+    for o in ops:
+        if o.kind == "dense":
+            orc.apply_dense(psi, o.qubits, o.matrix)
+        elif o.kind == "diag":
+            orc.apply_diag(psi, o.qubits, o.matrix)
+        else:
+            raise AssertionError("unexpected op")
+    return psi
+
+
+@pytest.mark.parametrize("kmax", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("fold", [False, True])
+def test_fusion_equals_sequential(kmax, fold):
+    c = W.sycamore_circuit(12, 8, seed=31)
+    ops = planner.fuse(c.gates, kmax if kmax >= 2 else 2, fold_diag=fold)
+    for o in ops:
+        if o.kind == "dense":
+            assert len(o.qubits) <= max(kmax, 2)
+    ref = orc.simulate(c)
+    got = apply_ops_on_oracle(12, ops)
+    assert np.abs(got - ref).max() < 1e-13
+    assert sum(o.ngates for o in ops) == len(c.gates)
+
+
+def test_fusion_generic_asymmetric_gates():
+    c = W.random_generic_circuit(9, 60, seed=4, max_arity=3)
+    for kmax in (3, 4, 5):
+        ops = planner.fuse(c.gates, kmax)
+        assert np.abs(apply_ops_on_oracle(9, ops) - orc.simulate(c)).max() < 1e-13
+
+
+def test_split_eq1_is_exact():
+    f = W.fsim()
+    d, x = planner.split_eq1(f)
+    assert np.abs(np.diag(d) @ x - f).max() == 0
+    assert np.abs(x @ np.diag(d) - f).max() == 0        # the factors commute
+    assert planner.split_eq1(W.random_unitary(4, np.random.default_rng(1))) is None
+
+
+def test_embed_in_matches_oracle():
+    rng = np.random.default_rng(2)
+    g = W.random_unitary(4, rng)
+    block = [5, 2, 7]
+    e = planner.embed_in(block, (7, 5), g)
+    psi = W.random_state(8, rng)
+    a = orc.apply_dense(psi.copy(), block, e)
+    b = orc.apply_dense(psi.copy(), (7, 5), g)
+    assert np.abs(a - b).max() < 1e-14
+
+
+def test_cfg2_plan_counts():
+    c = W.config_circuit(2)
+    ops = planner.fuse(c.gates, 5)
+    st = planner.stats(ops)
+    assert sum(o.ngates for o in ops) == 621
+    assert max(st["k_hist"]) <= 5
+    # aggregation must cut the sweep count well below the gate count
+    assert st["dense"] < 621 // 4
+
+
+def _declared_functions():
+    names = []
+    for f in os.listdir(os.path.join(ROOT, "include")):
+        if f.endswith(".h"):
+            src = open(os.path.join(ROOT, "include", f)).read()
+            src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+            names += re.findall(r"^\s*(?:int|const char\*)\s+(\w+)\s*\(", src, flags=re.M)
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    so = os.path.join(ROOT, "paper_1910_09534_amd", "libsv.so")
+    if not os.path.exists(so):
+        from paper_1910_09534_amd import build
+        build.build()
+    lib = ctypes.CDLL(so)
+    names = _declared_functions()
+    assert len(names) >= 10
+    for n in names:
+        assert hasattr(lib, n), f"libsv.so does not export {n}"
+    from paper_1910_09534_amd import sv
+    assert set(sv.EXPORTS) == set(names)
