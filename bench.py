@@ -1,0 +1,161 @@
+#!/usr/bin/env python3
+"""Benchmark: amplitude-updates/s of the sliced state-vector path on one MI355X.
+
+Workload (default): the 30-qubit 5x6-grid ABCDCDAB random circuit of depth 14
+(621 gates: 450 single-qubit + 171 fSim), complex64 state of 2^30
+amplitudes (8 GiB, resident in HBM), gates aggregated into dense blocks of
+at most 5 qubits, output = norm + amplitudes of 2^16 seeded bitstrings with
+FP64 cross-entropy sums.
+
+One step = reset the state to |0...0> (init kernel) + every fused sweep of
+the planned circuit + the FP64 gather / norm / cross-entropy reduction,
+with the circuit already planned (host planning is not timed) and the state
+already allocated in HBM.
+
+value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
+un-aggregated work over aggregated time).
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = ("amp-updates/s & % HBM peak, 30q d14 complex64; served circuits/s + p99 latency")
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def cpu_baseline(circuit, budget_s: float = 15.0):
+    """The oracle as it stands (plain per-gate complex128 simulation, OpenMP
+    over all host cores) on a bounded sample of the same workload: the first
+    gates of the same circuit on the full 2^n state, until `budget_s`."""
+    from oracle import oracle as orc
+    n = circuit.n
+    psi = orc.zero_state(n)
+    done = 0
+    t0 = time.perf_counter()
+    for g in circuit.gates:
+        orc.apply_dense(psi, g.qubits, g.matrix)
+        done += 1
+        if time.perf_counter() - t0 > budget_s:
+            break
+    t = time.perf_counter() - t0
+    del psi
+    return {"value": done * float(1 << n) / t, "unit": "amp-updates/s", "cores": orc.threads(),
+            "kind": "oracle",
+            "sample": f"first {done} of {len(circuit.gates)} gates of the same {n}-qubit circuit "
+                      f"on the full 2^{n} complex128 state ({t:.1f} s)"}
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--kmax", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    args = ap.parse_args(argv)
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
+              "sharding of this path is a design only.", file=sys.stderr)
+        return 2
+
+    import torch
+    from paper_1910_09534_amd import planner, sv
+    from paper_1910_09534_amd import workload as W
+
+    circ = W.config_circuit(2)
+    bits = W.config_bitstrings(2)
+    n = circ.n
+    ops = planner.plan(circ.gates, args.kmax)
+    for o in ops:                                 # pre-cast once (host, untimed)
+        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+    pst = planner.stats(ops)
+    ndense = pst["dense"]
+
+    torch.cuda.set_device(0)
+    buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    h = sv.create_state_ext(n, 0, "c64", stream, buf.data_ptr(), buf.numel() * 8)
+
+    def step():
+        sv.reset(h)
+        planner.enqueue(h, ops, sv.SV_C64)
+        return sv.reduce_slices(h, bits)
+
+    for _ in range(args.warmup):
+        step()
+    sv.sweep_time(h)                               # clear
+    sv.set_option(h, sv.SV_OPT_TIMING, 1)          # HIP events around every dense sweep
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        amps, stats = step()
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    ms_per_step = 1e3 * t / args.steps
+    gates = len(circ.gates)
+    value = gates * float(1 << n) * args.steps / t
+
+    # dominant kernel: the fused dense sweep, every launch of the timed steps
+    # bracketed by HIP events on the stream the kernels run on
+    sweep_ms, nswept = sv.sweep_time(h)
+    sv.set_option(h, sv.SV_OPT_TIMING, 0)
+    avg_ms = sweep_ms / max(nswept, 1)
+    bytes_per_sweep = 16.0 * (1 << n)              # read + write of complex64
+    flops_per_step = pst["flops_per_amp"] * float(1 << n) * args.steps
+    gbs = bytes_per_sweep / (avg_ms * 1e-3) / 1e9
+    tflops = flops_per_step / (sweep_ms * 1e-3) / 1e12
+    hbm_frac = gbs / HBM_PEAK_GBS
+    alu_frac = tflops / FP32_PEAK_TFLOPS
+    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(hbm_frac, 4), "traffic": None,
+            "kernel": "k_dense (fused dense sweep), all launches of the timed steps",
+            "avg_launch_ms": round(avg_ms, 4), "launches": nswept,
+            "alu": {"achieved_tflops": round(tflops, 2), "peak_tflops": FP32_PEAK_TFLOPS,
+                    "frac": round(alu_frac, 4)}}
+    if alu_frac > hbm_frac:
+        roof.update({"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": round(alu_frac, 4),
+                     "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(hbm_frac, 4)}})
+    run_hbm_frac = ndense * bytes_per_sweep / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+
+    sv.destroy_state(h)
+    del buf
+    torch.cuda.empty_cache()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(circ, args.cpu_budget)
+
+    line = {
+        "metric": METRIC, "value": value, "unit": "amp-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": "30-qubit 5x6 ABCDCDAB random circuit, depth 14, complex64, "
+                               "fusion k<=%d, norm + 2^16 bitstrings" % args.kmax,
+                   "n": n, "depth": circ.depth, "gates": gates, "kmax": args.kmax,
+                   "bitstrings": int(bits.size), "sweeps": ndense, "k_hist": pst["k_hist"]},
+        "hbm_frac_run": round(run_hbm_frac, 4),
+        "norm": stats[0],
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -153,6 +153,11 @@ int reduce_slices(sv_handle h, const void* trailing_c128, int64_t count,
 /* sync_state -- run everything queued and wait for it.  */
 int sync_state(sv_handle h);
 
+/* sv_reset -- drop queued operations and set the state back to |0...0>
+   (the layout is kept; |0...0> is index 0 in every layout).  Reuses the
+   handle's memory: nothing is allocated.  */
+int sv_reset(sv_handle h);
+
 /* last_error -- text of the most recent failure on h (or of the last failed
    create when h is NULL).  Valid until the next call on the same handle. */
 const char* last_error(sv_handle h);
@@ -168,7 +173,8 @@ int sv_device_buffer(sv_handle h, void** dev, size_t* bytes);
 
 enum {
     SV_OPT_TIMING = 1,     /* 1: time every dense sweep with HIP events on the handle's stream */
-    SV_OPT_MFMA = 2,       /* 0: never use the MFMA kernel for k=5 (c64); 1 (default): use it */
+    SV_OPT_MFMA = 2,       /* smallest k (4..6) whose complex64 blocks run on the matrix
+                              cores (default 4); 0 or > 6: never */
     SV_OPT_FOLD_DIAG = 3,  /* 1 (default): fold a diagonal op into the preceding dense sweep */
     SV_OPT_SLOTS = 4       /* tier: number of device slice slots (>= 2) */
 };

@@ -81,7 +81,8 @@ struct sv_state {
     void* d_small = nullptr;              // 8 doubles
 
     // options and accounting
-    bool timing = false, mfma = true, fold = true;
+    bool timing = false, fold = true;
+    int mfma_min_k = 4;
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;
     size_t tev_used = 0;
@@ -224,7 +225,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 TRY(h, hipEventRecord(e0, st));
             }
             TRY(h, launch_dense(st, *psi, h->dtype, nloc, op.k, op.pos, dbase + op.off, fp,
-                                idx_offset, h->mfma));
+                                idx_offset, h->mfma_min_k));
             if (h->timing) TRY(h, hipEventRecord(e1, st));
             h->counters[0] += 1;
             h->counters[3] += (int64_t)1 << nloc;
@@ -830,6 +831,29 @@ int sync_state(sv_handle h)
     return SV_OK;
 }
 
+int sv_reset(sv_handle h)
+{
+    CHECK_HANDLE(h);
+    h->ops.clear();
+    h->arena.clear();
+    if (!h->tier) {
+        TRY(h, launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << h->n, true));
+        return SV_OK;
+    }
+    TRY(h, hipStreamSynchronize(h->stream));
+    TRY(h, hipStreamSynchronize(h->s_in));
+    TRY(h, hipStreamSynchronize(h->s_out));
+    const size_t fb = file_amps(h) * h->amp;
+    for (void* f : h->files) std::memset(f, 0, fb);
+    if (h->dtype) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
+    else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
+    // |0...0> sits in slice 0, file 0 only if index 0 maps there: it does in
+    // every layout (all bits zero)
+    std::fill(h->slice_zero.begin(), h->slice_zero.end(), (uint8_t)1);
+    h->slice_zero[0] = 0;
+    return SV_OK;
+}
+
 const char* last_error(sv_handle h)
 {
     if (!h) return g_create_error.c_str();
@@ -856,7 +880,7 @@ int sv_set_option(sv_handle h, int option, int64_t value)
     CHECK_HANDLE(h);
     switch (option) {
         case SV_OPT_TIMING: h->timing = value != 0; return SV_OK;
-        case SV_OPT_MFMA: h->mfma = value != 0; return SV_OK;
+        case SV_OPT_MFMA: h->mfma_min_k = (int)value; return SV_OK;
         case SV_OPT_FOLD_DIAG: h->fold = value != 0; return SV_OK;
         case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
     }

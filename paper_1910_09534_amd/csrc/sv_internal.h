@@ -38,7 +38,11 @@ hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, boo
 // range's first element (feeds fold's bits above nloc).
 hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
                         const void* mat, const DiagSpec* fold, uint64_t idx_offset,
-                        bool allow_mfma);
+                        int mfma_min_k);
+
+// Matrix-core form of the dense sweep (complex64, 4 <= k <= 6, nloc >= k + 4).
+hipError_t launch_dense_mfma(hipStream_t st, void* psi, int nloc, int k, const int* pos,
+                             const void* mat, const DiagSpec* fold, uint64_t idx_offset);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
 hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,

@@ -114,6 +114,7 @@ struct DenseK {
     uint64_t idx_offset;
     uint64_t lowmask[kMaxDense];       // (1 << p) - 1 for target positions, ascending
     uint64_t off[1 << kMaxDense];      // offset of local index c (matrix order)
+    int tpos[kMaxDense];               // target positions, matrix-bit order
     int fold_m;
     int fold_pos[kMaxDiag];
     uint32_t fold_map[1 << kMaxDense]; // fold-table bits contributed by local index c
@@ -135,15 +136,27 @@ __global__ __launch_bounds__(256) void k_dense(typename Vec2<R>::T* __restrict__
             const uint64_t low = base & a.lowmask[j];
             base = ((base ^ low) << 1) | low;
         }
+        uint64_t bitv[K];                      // 2^(target position j)
+#pragma unroll
+        for (int j = 0; j < K; ++j) bitv[j] = 1ull << a.tpos[j];
         V x[D];
 #pragma unroll
-        for (int c = 0; c < D; ++c) x[c] = psi[base + a.off[c]];
+        for (int c = 0; c < D; ++c) {
+            uint64_t o = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j)
+                if ((c >> j) & 1) o |= bitv[j];
+            x[c] = psi[base + o];
+        }
         uint32_t fb = 0;
         if (FOLD) {
             const uint64_t gi = base + a.idx_offset;
             for (int j = 0; j < a.fold_m; ++j) fb |= (uint32_t)((gi >> a.fold_pos[j]) & 1u) << j;
         }
-#pragma unroll
+        // One matrix row per iteration: the row is wave-uniform and is read
+        // with scalar loads; not unrolling the row loop keeps only one row
+        // (2^(k+1) values) live in SGPRs instead of the whole matrix.
+#pragma unroll 1
         for (int r = 0; r < D; ++r) {
             R re = 0, im = 0;
 #pragma unroll
@@ -154,13 +167,20 @@ __global__ __launch_bounds__(256) void k_dense(typename Vec2<R>::T* __restrict__
                 im = fma(m.x, x[c].y, im);
                 im = fma(m.y, x[c].x, im);
             }
+            // offset of row r computed from the target positions (a dynamic
+            // index into the kernel-argument table would spill SGPRs)
+            uint64_t orow = 0;
+#pragma unroll
+            for (int j = 0; j < K; ++j) orow |= ((r >> j) & 1) ? bitv[j] : 0ull;
             if (FOLD) {
-                const V p = ftab[fb | a.fold_map[r]];
+                uint32_t fr = 0;
+                for (int j = 0; j < a.fold_m; ++j) fr |= (uint32_t)((orow >> a.fold_pos[j]) & 1u) << j;
+                const V p = ftab[fb | fr];
                 const R t = re * p.x - im * p.y;
                 im = re * p.y + im * p.x;
                 re = t;
             }
-            psi[base + a.off[r]] = V{re, im};
+            psi[base + orow] = V{re, im};
         }
     }
 }
@@ -181,10 +201,11 @@ static hipError_t dense_dispatch(hipStream_t st, void* psi, const void* mat, con
 }
 
 hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
-                        const void* mat, const DiagSpec* fold, uint64_t idx_offset, bool allow_mfma)
+                        const void* mat, const DiagSpec* fold, uint64_t idx_offset, int mfma_min_k)
 {
-    (void)allow_mfma;
     if (k < 1 || k > kMaxDense || k > nloc) return hipErrorInvalidValue;
+    if (dtype == 0 && mfma_min_k >= 4 && k >= mfma_min_k && nloc >= k + 4)
+        return launch_dense_mfma(st, psi, nloc, k, pos, mat, fold, idx_offset);
     if (dtype && k > 5) return hipErrorInvalidValue;
     DenseK a{};
     a.groups = 1ull << (nloc - k);
@@ -196,6 +217,7 @@ hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, c
             const int t = sp[l]; sp[l] = sp[l - 1]; sp[l - 1] = t;
         }
     for (int j = 0; j < k; ++j) a.lowmask[j] = (1ull << sp[j]) - 1;
+    for (int j = 0; j < k; ++j) a.tpos[j] = pos[j];
     for (int c = 0; c < (1 << k); ++c) {
         uint64_t o = 0;
         for (int j = 0; j < k; ++j)

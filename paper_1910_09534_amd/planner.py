@@ -153,6 +153,104 @@ def fuse(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
     return ops
 
 
+def fuse_grow(gates, kmax: int, window: int = 4) -> List[Op]:
+    """Aggregation by growing qubit sets (Sec. 5 aggregate gates, clusters that
+    span several depths as in the appendix listing's cache rows).
+
+    Repeatedly: start from the qubits of the earliest pending gate, add one
+    qubit at a time (among the qubits of the pending gates that touch the
+    set; `window` next gates per qubit) choosing the one that lets the most
+    pending gates be applied inside
+    the set, up to kmax qubits; then emit one block holding every pending
+    gate that lies inside the set and whose predecessors on each of its
+    qubits are already applied (its causal closure within the set).  Per
+    qubit, gates keep their order, so the product is unchanged."""
+    ng = len(gates)
+    qs_of = [tuple(g.qubits) for g in gates]
+    per_q: Dict[int, List[int]] = {}
+    for i, qs in enumerate(qs_of):
+        for q in qs:
+            per_q.setdefault(q, []).append(i)
+    ptr = {q: 0 for q in per_q}                 # index into per_q[q] of the next pending gate
+    done = [False] * ng
+
+    def closure(Q):
+        """Pending gates applicable inside Q, in a valid order."""
+        loc = {q: ptr[q] for q in Q}
+        taken = []
+        progress = True
+        while progress:
+            progress = False
+            for q in Q:
+                lst = per_q.get(q, [])
+                while loc[q] < len(lst):
+                    gi = lst[loc[q]]
+                    qs = qs_of[gi]
+                    if any(x not in Q for x in qs):
+                        break
+                    if any(per_q[x][loc[x]] != gi for x in qs):
+                        break
+                    for x in qs:
+                        loc[x] += 1
+                    taken.append(gi)
+                    progress = True
+        return taken
+
+    ops: List[Op] = []
+    remaining = ng
+    while remaining:
+        first = min(per_q[q][ptr[q]] for q in per_q if ptr[q] < len(per_q[q]))
+        Q = list(qs_of[first])
+        best = closure(Q)
+        while len(Q) < kmax:
+            cands = set()
+            for q in Q:
+                lst = per_q[q]
+                for t in range(ptr[q], min(ptr[q] + window, len(lst))):
+                    cands.update(x for x in qs_of[lst[t]] if x not in Q)
+            if not cands:
+                break
+            scored = []
+            for c in sorted(cands):
+                cl = closure(Q + [c])
+                w = sum(len(qs_of[i]) for i in cl)
+                scored.append((w, -c, c, cl))
+            scored.sort(reverse=True)
+            w, _, c, cl = scored[0]
+            Q.append(c)
+            best = cl
+        # emit the block
+        qlist = []
+        for gi in best:
+            for q in qs_of[gi]:
+                if q not in qlist:
+                    qlist.append(q)
+        m = np.eye(1 << len(qlist), dtype=np.complex128)
+        for gi in best:
+            m = embed_in(qlist, qs_of[gi], np.asarray(gates[gi].matrix, dtype=np.complex128)) @ m
+            for q in qs_of[gi]:
+                ptr[q] += 1
+            done[gi] = True
+        remaining -= len(best)
+        ops.append(Op("dense", tuple(qlist), m, ngates=len(best)))
+    return ops
+
+
+def plan_cost(ops: Sequence[Op]) -> float:
+    """Relative cost of a plan: one unit per HBM sweep plus the block's
+    arithmetic (8 2^k flop per amplitude) in units of a 6-qubit block."""
+    return sum(1.0 + (8 << len(o.qubits)) / 4096.0 if o.kind == "dense" else 1.0 for o in ops)
+
+
+def plan(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
+    """Aggregate with every available heuristic and keep the cheapest plan."""
+    cands = [fuse(gates, kmax, fold_diag=fold_diag)]
+    if not fold_diag:
+        for w in (3, 4, 5, 6, 8):
+            cands.append(fuse_grow(gates, kmax, window=w))
+    return min(cands, key=plan_cost)
+
+
 def stats(ops: Sequence[Op]) -> Dict[str, object]:
     hist: Dict[int, int] = {}
     for o in ops:

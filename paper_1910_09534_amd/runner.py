@@ -18,15 +18,15 @@ from . import planner, sv
 
 
 def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: bool = False,
-             timing: bool = False, mfma: bool = True, stream=None) -> Dict[str, object]:
+             timing: bool = False, mfma: int = 4, stream=None) -> Dict[str, object]:
     t0 = time.perf_counter()
-    ops = planner.fuse(circuit.gates, kmax, fold_diag=fold_diag)
+    ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag)
     t_plan = time.perf_counter() - t0
     st = sv.State(circuit.n, 0, dtype, stream)
     try:
         if timing:
             sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
-        sv.set_option(st.h, sv.SV_OPT_MFMA, 1 if mfma else 0)
+        sv.set_option(st.h, sv.SV_OPT_MFMA, int(mfma))
         t1 = time.perf_counter()
         planner.enqueue(st.h, ops, st.dtype)
         amps, stats = st.reduce(bits)

@@ -24,7 +24,7 @@ ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_E
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
 
 EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "apply_diag",
-           "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "last_error",
+           "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time")
 
 
@@ -49,6 +49,7 @@ def load():
     L.gather_amplitudes.argtypes = [P, I64, P, P]
     L.reduce_slices.argtypes = [P, P, I64, P, P, P]
     L.sync_state.argtypes = [P]
+    L.sv_reset.argtypes = [P]
     L.last_error.argtypes = [P]
     L.last_error.restype = ctypes.c_char_p
     L.sv_get_order.argtypes = [P, P]
@@ -154,6 +155,10 @@ def reduce_slices(h, bitstrings: np.ndarray, trailing: Optional[np.ndarray] = No
 
 def sync_state(h) -> None:
     _check(lib().sync_state(h), h)
+
+
+def reset(h) -> None:
+    _check(lib().sv_reset(h), h)
 
 
 def last_error(h=None) -> str:

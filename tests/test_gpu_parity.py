@@ -47,18 +47,25 @@ def read_all(h, n):
 
 # ---- single operations on random states ---------------------------------------
 
+@pytest.mark.parametrize("mfma", [0, 4])
 @pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("qs", [(0,), (5,), (11,), (1, 0), (3, 9), (0, 6, 2), (7, 1, 10, 4),
-                                (2, 8, 0, 11, 5), (9, 3, 6, 0, 11, 1)])
-def test_dense_single_op(dtype, qs):
+                                (2, 8, 0, 11, 5), (9, 3, 6, 0, 11, 1), (13, 12, 4, 7),
+                                (1, 2, 3, 0, 13), (8, 9, 10, 11, 12, 13)])
+def test_dense_single_op(dtype, qs, mfma):
+    """One dense block on a random 14-qubit state, VALU (mfma=0) and matrix-core
+    (mfma=4, used for k >= 4 with complex64) kernels."""
     if dtype == "c128" and len(qs) > 5:
         pytest.skip("complex128 blocks stop at k=5")
-    n = 12
+    if mfma and (dtype == "c128" or len(qs) < 4):
+        pytest.skip("matrix-core kernel covers complex64, k >= 4")
+    n = 14
     rng = np.random.default_rng(len(qs) * 100 + qs[0])
     psi = W.random_state(n, rng)
     u = W.random_unitary(1 << len(qs), rng)
     h, t = state_from_numpy(psi, dtype)
     try:
+        sv.set_option(h, sv.SV_OPT_MFMA, mfma)
         sv.apply_fused(h, qs, u, dtype)
         got = read_all(h, n)
     finally:
@@ -129,11 +136,12 @@ def test_cfg1_all_amplitudes_c128():
 
 @pytest.mark.parametrize("kmax", [2, 3, 4, 5, 6])
 @pytest.mark.parametrize("fold", [False, True])
-def test_circuit_c64_vs_oracle(kmax, fold):
+@pytest.mark.parametrize("mfma", [0, 4])
+def test_circuit_c64_vs_oracle(kmax, fold, mfma):
     n, d = 20, 14
     c = W.sycamore_circuit(n, d, seed=2002)
     bits = W.bitstrings(n, 4096, seed=3)
-    res = runner.simulate(c, bits, dtype="c64", kmax=kmax, fold_diag=fold)
+    res = runner.simulate(c, bits, dtype="c64", kmax=kmax, fold_diag=fold, mfma=mfma)
     ref = orc.gather(orc.simulate(c), bits)
     assert orc.rel_l2(res["amps"], ref) <= TOL["c64"]
     assert abs(res["norm"] - 1) < 1e-4
