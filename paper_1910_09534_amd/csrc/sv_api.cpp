@@ -540,14 +540,14 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
     const uint64_t lim = h->n >= 64 ? ~0ull : ((1ull << h->n) - 1);
     for (int64_t j = 0; j < count; ++j)
         if (bits[j] > lim) return set_err(h, SV_EINVAL, "bitstring >= 2^n");
-    int rc = flush(h);
-    if (rc) return rc;
+    int rc;
     const int ns = 1 << h->s;
     const size_t cnt = (size_t)std::max<int64_t>(count, 1);
     if ((rc = ensure_dev(h, &h->d_bits, &h->d_bits_cap, cnt * 8))) return rc;
     if ((rc = ensure_dev(h, &h->d_acc, &h->d_acc_cap, cnt * 16))) return rc;
-    if ((rc = ensure_dev(h, &h->d_part, &h->d_part_cap, 4096 * 16 * sizeof(double)))) return rc;
-    if ((rc = ensure_dev(h, &h->d_tcol, &h->d_tcol_cap, (size_t)ns * 16))) return rc;
+    if ((rc = ensure_dev(h, &h->d_part, &h->d_part_cap, 4096 * 2 * sizeof(double)))) return rc;
+    // T (all columns, gathered per physical slice) + per-slice norms
+    if ((rc = ensure_dev(h, &h->d_tcol, &h->d_tcol_cap, (size_t)ns * ns * 16 + (size_t)ns * 8))) return rc;
     if ((rc = ensure_dev(h, &h->d_rowmap, &h->d_rowmap_cap, (size_t)ns * 4))) return rc;
 
     // logical bitstring -> physical index
@@ -565,59 +565,65 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
             if ((t >> (h->pos[sl[i]] - h->L)) & 1) r |= 1 << i;
         rowmap[t] = r;
     }
+    const double* T = (const double*)trailing;
+    // tcols[t][r] = T[r][rowmap[t]]: the column a physical slice t multiplies
+    std::vector<double> tcols;
+    if (T) {
+        tcols.assign((size_t)ns * ns * 2, 0.0);
+        for (int t = 0; t < ns; ++t)
+            for (int r = 0; r < ns; ++r) {
+                const size_t src = 2 * ((size_t)r * ns + rowmap[t]);
+                tcols[2 * ((size_t)t * ns + r)] = T[src];
+                tcols[2 * ((size_t)t * ns + r) + 1] = T[src + 1];
+            }
+    }
     hipStream_t st = h->stream;
+    double* d_snorm = (double*)((char*)h->d_tcol + (size_t)ns * ns * 16);
     if (count > 0) {
         TRY(h, hipMemcpyAsync(h->d_bits, bits, (size_t)count * 8, hipMemcpyHostToDevice, st));
         TRY(h, hipMemsetAsync(h->d_acc, 0, (size_t)count * 16, st));
     }
     TRY(h, hipMemcpyAsync(h->d_rowmap, rowmap.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
-    std::vector<double> tcol;
-    const double* T = (const double*)trailing;
-    auto set_col = [&](int t) -> int {
-        if (!T) return SV_OK;
-        tcol.assign((size_t)ns * 2, 0.0);
-        const int c = rowmap[t];
-        for (int r = 0; r < ns; ++r) {
-            tcol[2 * r] = T[2 * ((size_t)r * ns + c)];
-            tcol[2 * r + 1] = T[2 * ((size_t)r * ns + c) + 1];
-        }
-        // synchronous copy: tcol is reused for the next slice
-        TRY(h, hipMemcpyAsync(h->d_tcol, tcol.data(), (size_t)ns * 16, hipMemcpyHostToDevice, st));
-        TRY(h, hipStreamSynchronize(st));
-        return SV_OK;
-    };
-    double norm = 0.0;
-    std::vector<double> slice_norm(ns, 0.0);
+    if (T) TRY(h, hipMemcpyAsync(h->d_tcol, tcols.data(), tcols.size() * 8, hipMemcpyHostToDevice, st));
+    TRY(h, hipMemsetAsync(d_snorm, 0, (size_t)ns * 8, st));
+    // nothing below synchronises the host per slice: the tier pipeline keeps
+    // staging the next slice while this one is reduced
     auto visit = [&](int t, const void* slice_buf) -> int {
-        int r = set_col(t);
-        if (r) return r;
+        const void* tc = T ? (const void*)((const char*)h->d_tcol + (size_t)t * ns * 16) : nullptr;
         TRY(h, launch_accumulate(st, slice_buf, h->dtype, h->L, (uint64_t)t, l2p, count,
-                                 (const uint64_t*)h->d_bits, T ? h->d_tcol : nullptr,
-                                 (const int*)h->d_rowmap, (double*)h->d_acc));
+                                 (const uint64_t*)h->d_bits, tc, (const int*)h->d_rowmap,
+                                 (double*)h->d_acc));
         if (stats) {
             int nb = 0;
             TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)h->d_part, &nb));
-            r = finish_sum(h, st, nb, 1, &slice_norm[t]);
-            if (r) return r;
+            TRY(h, launch_finish_sum(st, (const double*)h->d_part, nb, 1, d_snorm + t));
         }
         return SV_OK;
     };
     if (!h->tier) {
-        if (!T && h->s == 0) {
-            rc = visit(0, h->dev);
-        } else {
-            for (int t = 0; t < ns && !rc; ++t)
-                rc = visit(t, (const char*)h->dev + ((size_t)t << h->L) * h->amp);
-        }
+        rc = flush(h);
+        if (rc) return rc;
+        for (int t = 0; t < ns && !rc; ++t)
+            rc = visit(t, (const char*)h->dev + ((size_t)t << h->L) * h->amp);
     } else {
-        rc = tier_pass(h, false, visit);
+        // one pass over the tier: pending ops, then the reduction, then write back
+        const bool pending = !h->ops.empty();
+        if (pending) {
+            rc = upload_arena(h);
+            if (rc) return rc;
+        }
+        rc = tier_pass(h, pending, visit);
+        if (rc) return rc;
+        h->ops.clear();
+        h->arena.clear();
+        if (h->timing) rc = collect_timing(h);
     }
     if (rc) return rc;
-    for (int t = 0; t < ns; ++t) norm += slice_norm[t];   // fixed slice order
-    if (count > 0) {
+    if (count > 0)
         TRY(h, hipMemcpyAsync(out, h->d_acc, (size_t)count * 16, hipMemcpyDeviceToHost, st));
-    }
     if (stats) {
+        std::vector<double> snorm(ns, 0.0);
+        TRY(h, hipMemcpyAsync(snorm.data(), d_snorm, (size_t)ns * 8, hipMemcpyDeviceToHost, st));
         double x[2] = {0.0, 0.0};
         if (count > 0) {
             int nb = 0;
@@ -626,6 +632,9 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
             rc = finish_sum(h, st, nb, 2, x);
             if (rc) return rc;
         }
+        TRY(h, hipStreamSynchronize(st));
+        double norm = 0.0;
+        for (int t = 0; t < ns; ++t) norm += snorm[t];    // fixed slice order
         stats[0] = norm;
         stats[1] = x[0];
         stats[2] = x[1];

@@ -251,6 +251,79 @@ def plan(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
     return min(cands, key=plan_cost)
 
 
+@dataclasses.dataclass
+class Phase:
+    sliced: Tuple[int, ...]          # qubits fixed (sliced) during the phase
+    order: List[int]                 # layout: order[p] = qubit at position p
+    gate_ids: List[int]              # circuit gates applied in the phase
+    ops: List[Op] = dataclasses.field(default_factory=list)
+
+
+@dataclasses.dataclass
+class SlicedPlan:
+    n: int
+    phases: List[Phase]
+    trailing_qubits: Tuple[int, ...]     # = the last phase's sliced set, ascending
+    trailing: Optional[np.ndarray]       # 2^s x 2^s over trailing_qubits, or None (identity)
+    trailing_gate_ids: List[int]
+
+
+def phase_layout(n: int, sliced: Sequence[int], other: Sequence[int]) -> List[int]:
+    """[qubits in neither set ascending] [other set] [sliced set]: the other
+    set sits in the top local ("file") positions, so switching the two sets
+    only relabels whole files (Sec. 4, logical files indexed by both sets)."""
+    both = set(sliced) | set(other)
+    inner = [q for q in range(n) if q not in both]
+    return inner + sorted(other) + sorted(sliced)
+
+
+def phase_schedule(circuit, set_a: Sequence[int], set_b: Sequence[int], kmax: int,
+                   max_phases: int = 64) -> SlicedPlan:
+    """Split the gate list into phases with alternating sliced sets (Sec. 4:
+    subcircuits 3, 5, 7, 9 slice one set and 4, 6, 8 the other).  A phase
+    applies, in order, every pending gate that touches no sliced qubit and
+    whose predecessors are applied (a light-cone scan).  When the pending
+    gates act only on the current sliced set they are multiplied into the
+    trailing operator that the cross-slice reduction applies."""
+    n = circuit.n
+    gates = circuit.gates
+    pending = list(range(len(gates)))
+    phases: List[Phase] = []
+    cur, nxt = tuple(sorted(set_a)), tuple(sorted(set_b))
+    trailing_ids: List[int] = []
+    stall = 0
+    while pending:
+        blocked = set(cur)
+        take, rest = [], []
+        for i in pending:
+            qs = set(gates[i].qubits)
+            if qs & blocked:
+                blocked |= qs
+                rest.append(i)
+            else:
+                take.append(i)
+        ph = Phase(cur, phase_layout(n, cur, nxt), take)
+        ph.ops = plan([gates[i] for i in take], kmax) if take else []
+        phases.append(ph)
+        stall = stall + 1 if not take else 0
+        if stall >= 2 or len(phases) > max_phases:
+            raise ValueError("phase schedule makes no progress (a gate spans both slice sets?)")
+        pending = rest
+        if pending and all(set(gates[i].qubits) <= set(cur) for i in pending):
+            trailing_ids = list(pending)        # only sliced qubits left: fold into T
+            pending = []
+            break
+        cur, nxt = nxt, cur
+    last = phases[-1].sliced
+    T = None
+    if trailing_ids:
+        ql = list(last)
+        T = np.eye(1 << len(ql), dtype=np.complex128)
+        for i in trailing_ids:
+            T = embed_in(ql, gates[i].qubits, np.asarray(gates[i].matrix, dtype=np.complex128)) @ T
+    return SlicedPlan(n, phases, tuple(last), T, trailing_ids)
+
+
 def stats(ops: Sequence[Op]) -> Dict[str, object]:
     hist: Dict[int, int] = {}
     for o in ops:

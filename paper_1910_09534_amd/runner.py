@@ -39,3 +39,48 @@ def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: b
         return out
     finally:
         st.close()
+
+
+def grid_slice_sets(n: int):
+    """Two disjoint 4-qubit slice sets on the near-square grid of n qubits:
+    the four corner sites and the 2 x 2 block at the centre."""
+    from .workload import grid_shape
+    rows, cols = grid_shape(n)
+    last_row_len = n - (rows - 1) * cols
+    corners = sorted({0, cols - 1, (rows - 1) * cols, (rows - 1) * cols + last_row_len - 1})
+    r0, c0 = (rows - 1) // 2, (cols - 1) // 2
+    centre = sorted({r0 * cols + c0, r0 * cols + c0 + 1, (r0 + 1) * cols + c0, (r0 + 1) * cols + c0 + 1})
+    assert not set(corners) & set(centre) and all(q < n for q in centre)
+    return tuple(corners), tuple(centre)
+
+
+def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: int = 5,
+                    tier: bool = False, timing: bool = False, sched=None) -> Dict[str, object]:
+    """Sliced evolution (Sec. 4): phases alternate the sliced set; each switch
+    is one permute_qubits; the trailing gates on the last sliced set are
+    applied by the FP64 cross-slice reduction."""
+    t0 = time.perf_counter()
+    if sched is None:
+        sched = planner.phase_schedule(circuit, set_a, set_b, kmax)
+    t_plan = time.perf_counter() - t0
+    n = circuit.n
+    mask = sum(1 << q for q in sched.phases[0].sliced)
+    st = sv.State(n, mask, dtype, tier=tier)
+    try:
+        if timing:
+            sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
+        t1 = time.perf_counter()
+        for ph in sched.phases:
+            sv.permute_qubits(st.h, ph.order)
+            planner.enqueue(st.h, ph.ops, st.dtype)
+        amps, stats = sv.reduce_slices(st.h, bits, sched.trailing)
+        t_run = time.perf_counter() - t1
+        out = {"amps": amps, "norm": stats[0], "xeb_sum": stats[1], "xeb_log_sum": stats[2],
+               "t_plan": t_plan, "t_run": t_run, "phases": len(sched.phases),
+               "trailing_gates": len(sched.trailing_gate_ids),
+               "sweeps": sum(len(p.ops) for p in sched.phases), "counters": sv.counters(st.h)}
+        if timing:
+            out["sweep_ms"], out["sweeps_timed"] = sv.sweep_time(st.h)
+        return out
+    finally:
+        st.close()
