@@ -15,7 +15,14 @@ already allocated in HBM.
 value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
 un-aggregated work over aggregated time).
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5]
+Other workloads (one JSON line each, same fields where they apply):
+  --config 3   sliced run through the pinned host tier: ABCDCDAB depth 20 on the
+               near-square grid of --n qubits (default 34: 16 slices of 2^30
+               amplitudes, 128 GiB of pinned host memory), slice sets = the
+               four corners and the central 2 x 2 block, alternating per
+               phase, FP64 reduction of 2^20 bitstrings.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5] [--config 2|3]
 """
 from __future__ import annotations
 
@@ -65,11 +72,17 @@ def main(argv=None) -> int:
     ap.add_argument("--kmax", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--pins", action="store_true", help="config 3: also run the mirror pin")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design only.", file=sys.stderr)
         return 2
+
+    if args.config == 3:
+        return bench_sliced(args)
 
     import torch
     from paper_1910_09534_amd import planner, sv
@@ -155,6 +168,84 @@ def main(argv=None) -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_sliced(args) -> int:
+    """Sliced evolution with slices staged through pinned host memory."""
+    import torch
+    from paper_1910_09534_amd import planner, runner, sv
+    from paper_1910_09534_amd import workload as W
+
+    n = args.n or 34
+    depth = 20
+    circ = W.sycamore_circuit(n, depth, seed=1003)
+    bits = W.bitstrings(n, 1 << 20, seed=2003)
+    A, B = runner.grid_slice_sets(n)
+    t0 = time.perf_counter()
+    sched = planner.phase_schedule(circ, A, B, args.kmax)
+    for ph in sched.phases:
+        for o in ph.ops:
+            o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+    t_plan = time.perf_counter() - t0
+    torch.cuda.set_device(0)
+    mask = sum(1 << q for q in sched.phases[0].sliced)
+    t0 = time.perf_counter()
+    st = sv.State(n, mask, "c64", tier=True)
+    t_alloc = time.perf_counter() - t0
+    print(f"# tier allocated in {t_alloc:.1f} s; {len(sched.phases)} phases", file=sys.stderr,
+          flush=True)
+    sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
+
+    def run(s):
+        for ph in s.phases:
+            sv.permute_qubits(st.h, ph.order)
+            planner.enqueue(st.h, ph.ops, sv.SV_C64)
+        return sv.reduce_slices(st.h, bits, s.trailing)
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    amps, stats = run(sched)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    cnt = sv.counters(st.h)
+    sweep_ms, nswept = sv.sweep_time(st.h)
+    p = (amps.real ** 2 + amps.imag ** 2) * float(1 << n)
+    gates = len(circ.gates)
+    line = {
+        "metric": "sliced host-tier run: amp-updates/s, host-link GB/s", "value": gates * float(1 << n) / t,
+        "unit": "amp-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * t, 1),
+        "higher_is_better": True, "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"{n}-qubit ABCDCDAB depth {depth}, complex64, 4 sliced qubits "
+                               f"(16 slices of 2^{n - 4}), pinned host tier, 2^20 bitstrings",
+                   "n": n, "gates": gates, "slice_sets": [list(A), list(B)],
+                   "phases": len(sched.phases), "sweeps_per_slice": sum(len(p_.ops) for p_ in sched.phases),
+                   "trailing_gates": len(sched.trailing_gate_ids)},
+        "host_link_GBps": round((cnt["bytes_h2d"] + cnt["bytes_d2h"]) / t / 1e9, 2),
+        "bytes_h2d": cnt["bytes_h2d"], "bytes_d2h": cnt["bytes_d2h"],
+        "zero_slices_skipped": cnt["zero_slices_skipped"],
+        "dense_sweep_ms_total": round(sweep_ms, 1), "dense_sweeps": nswept,
+        "t_alloc_s": round(t_alloc, 1), "t_plan_s": round(t_plan, 2),
+        "norm": stats[0], "mean_Np": float(p.mean()), "mean_Np2": float((p ** 2).mean()),
+    }
+    if args.pins:
+        inv = [W.Gate(g.qubits, g.matrix.conj().T) for g in reversed(circ.gates)]
+        mirror = W.Circuit(n, circ.gates + inv, 2 * depth)
+        sv.reset(st.h)
+        ms = planner.phase_schedule(mirror, A, B, args.kmax)
+        mb = np.concatenate([np.zeros(1, np.uint64), bits[:4095]])
+        ma, _ = run_pins(st, ms, mb, planner, sv)
+        line["mirror_abs_amp0"] = float(abs(ma[0]))
+        line["mirror_max_other"] = float(np.abs(ma[1:]).max())
+    st.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def run_pins(st, sched, bits, planner, sv):
+    for ph in sched.phases:
+        sv.permute_qubits(st.h, ph.order)
+        planner.enqueue(st.h, ph.ops, sv.SV_C64)
+    return sv.reduce_slices(st.h, bits, sched.trailing)
 
 
 if __name__ == "__main__":

@@ -62,7 +62,9 @@ enum { SV_C64 = 0, SV_C128 = 1 };
 
 /* Flags OR-ed into the dtype argument of create_state. */
 enum {
-    SV_FLAG_TIER = 0x100   /* keep slices in the pinned host tier even if they fit in HBM */
+    SV_FLAG_TIER = 0x100,     /* keep slices in the host tier even if they fit in HBM */
+    SV_FLAG_PAGEABLE = 0x400  /* host tier in pageable memory even if it would fit the
+                                 pinned budget (48 GiB; larger tiers are pageable) */
 };
 
 typedef struct sv_state* sv_handle;
@@ -75,8 +77,9 @@ typedef struct sv_state* sv_handle;
  * dtype: SV_C64 or SV_C128, optionally | SV_FLAG_TIER.  hip_stream: a
  * hipStream_t to run on, or NULL for a stream owned by the handle.
  * If the whole state fits in device memory all slices are resident in one
- * HBM buffer; otherwise (or with SV_FLAG_TIER) slices live in pinned host
- * memory and are staged through device slots.  n in [1, 40], s <= 12.
+ * HBM buffer; otherwise (or with SV_FLAG_TIER) slices live in host memory
+ * (pinned up to 48 GiB, pageable beyond) and are staged through device
+ * slots.  n in [1, 40], s <= 12; the tier needs n >= 2s.
  * Errors: SV_EINVAL, SV_ENOMEM, SV_EDEVICE.  *out is set only on success.
  */
 int create_state(int n, uint64_t slice_mask, int dtype, void* hip_stream, sv_handle* out);

@@ -10,6 +10,7 @@
 // whole): slice t is 2^s files of 2^(L - s) amplitudes, and re-choosing the
 // sliced qubits among the 2s top positions only relabels files.
 #include <hip/hip_runtime.h>
+#include <sys/mman.h>
 
 #include <algorithm>
 #include <new>
@@ -56,7 +57,8 @@ struct sv_state {
     void* scratch = nullptr;              // permute target (resident)
 
     // host tier
-    std::vector<void*> files;             // [t * 2^s + u], pinned, 2^(L-s) amplitudes each
+    std::vector<void*> files;             // [t * 2^s + u], 2^(L-s) amplitudes each
+    bool pinned_tier = true;              // files pinned (hipHostMalloc) or pageable (mmap)
     std::vector<uint8_t> slice_zero;      // slice known to be all zero
     std::vector<void*> slots;             // device slice buffers
     void* pslot = nullptr;                // device buffer for local permutes
@@ -381,8 +383,12 @@ void release(sv_state* h)
     if (h->s_out) (void)hipStreamSynchronize(h->s_out);
     if (h->own_dev && h->dev) (void)hipFree(h->dev);
     if (h->scratch) (void)hipFree(h->scratch);
-    for (void* p : h->files)
-        if (p) (void)hipHostFree(p);
+    const size_t fbytes = h->files.empty() ? 0 : ((size_t)1 << (h->L - h->s)) * h->amp;
+    for (void* p : h->files) {
+        if (!p) continue;
+        if (h->pinned_tier) (void)hipHostFree(p);
+        else munmap(p, fbytes);
+    }
     for (void* p : h->slots)
         if (p) (void)hipFree(p);
     if (h->pslot) (void)hipFree(h->pslot);
@@ -469,14 +475,38 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         const int ns = 1 << s;
         const size_t fb = file_amps(h) * h->amp;
         h->files.assign((size_t)ns * ns, nullptr);
-        for (auto& f : h->files) {
-            if (hipHostMalloc(&f, fb, hipHostMallocDefault) != hipSuccess) {
-                f = nullptr;
-                (void)hipGetLastError();
-                release(h);
-                return set_err(nullptr, SV_ENOMEM, "pinned host tier allocation failed");
+        // Pinned memory is scarce (the driver caps it well below host RAM):
+        // the tier is pinned up to kPinnedBudget and pageable beyond that
+        // (or when pinning fails); pageable files are anonymous mappings whose
+        // pages stay unbacked until written.
+        const size_t kPinnedBudget = (size_t)48 << 30;
+        h->pinned_tier = (fb * h->files.size() <= kPinnedBudget) && !(dtype & SV_FLAG_PAGEABLE);
+        if (h->pinned_tier) {
+            for (auto& f : h->files) {
+                if (hipHostMalloc(&f, fb, hipHostMallocDefault) != hipSuccess) {
+                    f = nullptr;
+                    (void)hipGetLastError();
+                    h->pinned_tier = false;
+                    break;
+                }
+                std::memset(f, 0, fb);
             }
-            std::memset(f, 0, fb);
+            if (!h->pinned_tier)
+                for (auto& f : h->files) {
+                    if (f) (void)hipHostFree(f);
+                    f = nullptr;
+                }
+        }
+        if (!h->pinned_tier) {
+            for (auto& f : h->files) {
+                void* p = mmap(nullptr, fb, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
+                if (p == MAP_FAILED) {
+                    f = nullptr;
+                    release(h);
+                    return set_err(nullptr, SV_ENOMEM, "host tier allocation failed");
+                }
+                f = p;
+            }
         }
         // |0...0>: amplitude 0 lives in file (t = 0, u = 0)
         if (base) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
@@ -853,7 +883,10 @@ int sv_reset(sv_handle h)
     TRY(h, hipStreamSynchronize(h->s_in));
     TRY(h, hipStreamSynchronize(h->s_out));
     const size_t fb = file_amps(h) * h->amp;
-    for (void* f : h->files) std::memset(f, 0, fb);
+    for (void* f : h->files) {
+        if (h->pinned_tier) std::memset(f, 0, fb);
+        else (void)madvise(f, fb, MADV_DONTNEED);      // pages read back as zero
+    }
     if (h->dtype) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
     else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
     // |0...0> sits in slice 0, file 0 only if index 0 maps there: it does in

@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, -2, -3, -4, -5, -6
 SV_C64, SV_C128 = 0, 1
-SV_FLAG_TIER, SV_FLAG_KEEP = 0x100, 0x200
+SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE = 0x100, 0x200, 0x400
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS = 1, 2, 3, 4
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
@@ -94,10 +94,11 @@ def np_dtype(code: int):
     return np.complex64 if code == SV_C64 else np.complex128
 
 
-def create_state(n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False):
+def create_state(n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False,
+                 pageable: bool = False):
     """Returns an opaque handle (int)."""
     h = ctypes.c_void_p()
-    code = _dtype_code(dtype) | (SV_FLAG_TIER if tier else 0)
+    code = _dtype_code(dtype) | (SV_FLAG_TIER if tier else 0) | (SV_FLAG_PAGEABLE if pageable else 0)
     _check(lib().create_state(n, slice_mask, code, stream, ctypes.byref(h)))
     return h.value
 
@@ -201,9 +202,10 @@ def sweep_time(h):
 class State:
     """Owning wrapper around a handle (context manager)."""
 
-    def __init__(self, n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False):
+    def __init__(self, n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False,
+                 pageable: bool = False):
         self.n, self.slice_mask, self.dtype = n, slice_mask, _dtype_code(dtype)
-        self.h = create_state(n, slice_mask, dtype, stream, tier)
+        self.h = create_state(n, slice_mask, dtype, stream, tier, pageable)
 
     def fused(self, qubits, matrix):
         apply_fused(self.h, qubits, matrix, self.dtype)

@@ -37,7 +37,7 @@ def test_sliced_circuit_vs_oracle(n, depth, dtype, tier):
         assert res["counters"]["bytes_h2d"] > 0 and res["counters"]["bytes_d2h"] > 0
 
 
-@pytest.mark.parametrize("tier", [False, True])
+@pytest.mark.parametrize("tier", [False, True, "pageable"])
 def test_random_permutes_and_gates(tier):
     """Random gates on the unsliced qubits between random re-layouts that
     change 0..s of the sliced qubits; every amplitude checked (complex128)."""
@@ -45,7 +45,7 @@ def test_random_permutes_and_gates(tier):
     n, S = 12, (1, 6, 10)
     rng = np.random.default_rng(77)
     mask = sum(1 << q for q in S)
-    st = sv.State(n, mask, "c128", tier=tier)
+    st = sv.State(n, mask, "c128", tier=bool(tier), pageable=(tier == "pageable"))
     psi = orc.zero_state(n)
     order = st.order()
     try:
@@ -104,7 +104,7 @@ def product_amplitudes(circuit, rows, cols, bits):
     return out
 
 
-@pytest.mark.parametrize("tier", [False, True])
+@pytest.mark.parametrize("tier", [False, True, "pageable"])
 def test_product_circuit_30q_sliced(tier):
     """30 qubits (5 x 6 grid), depth 14, horizontal couplings only, sliced on
     the corners / centre with 16 slices: amplitudes equal products of
@@ -117,7 +117,8 @@ def test_product_circuit_30q_sliced(tier):
     c = W.Circuit(n, keep, 14)
     A, B = runner.grid_slice_sets(n)
     bits = W.bitstrings(n, 1 << 14, seed=99)
-    res = runner.simulate_sliced(c, bits, A, B, dtype="c64", kmax=5, tier=tier)
+    res = runner.simulate_sliced(c, bits, A, B, dtype="c64", kmax=5, tier=bool(tier),
+                                 pageable=(tier == "pageable"))
     ref = product_amplitudes(c, rows, cols, bits)
     assert orc.rel_l2(res["amps"], ref) <= TOL["c64"]
     assert abs(res["norm"] - 1) < 1e-4
