@@ -22,7 +22,12 @@ Other workloads (one JSON line each, same fields where they apply):
                four corners and the central 2 x 2 block, alternating per
                phase, FP64 reduction of 2^20 bitstrings.
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5] [--config 2|3]
+  --config 4   batch of 256 independent ABCDCDAB circuits (n ~ U{20..28},
+               depth ~ U{10..20}, complex64) recorded as one graph-captured
+               batch; fusion width and kernel form autotuned per qubit count;
+               1024 bitstrings per circuit; compared with the complex128 batch.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5] [--config 2|3|4]
 """
 from __future__ import annotations
 
@@ -83,6 +88,8 @@ def main(argv=None) -> int:
 
     if args.config == 3:
         return bench_sliced(args)
+    if args.config == 4:
+        return bench_batch(args)
 
     import torch
     from paper_1910_09534_amd import planner, sv
@@ -237,6 +244,70 @@ def bench_sliced(args) -> int:
         line["mirror_abs_amp0"] = float(abs(ma[0]))
         line["mirror_max_other"] = float(np.abs(ma[1:]).max())
     st.close()
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def bench_batch(args) -> int:
+    """256 independent circuits, one graph-captured batch per step."""
+    import torch
+    from oracle import oracle as orc
+    from paper_1910_09534_amd import autotune, planner, runner, sv
+    from paper_1910_09534_amd import workload as W
+
+    torch.cuda.set_device(0)
+    count = args.n or 256
+    specs = W.batch_specs(count)
+    circs = [W.sycamore_circuit(s["n"], s["depth"], s["seed"]) for s in specs]
+    bits = [W.bitstrings(s["n"], 1024, s["bit_seed"]) for s in specs]
+    t0 = time.perf_counter()
+    tuned = autotune.tune(sorted({c.n for c in circs}))
+    t_tune = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    plans = [planner.plan(c.gates, tuned["kmax"][c.n]) for c in circs]
+    for p in plans:
+        for o in p:
+            o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+    t_plan = time.perf_counter() - t0
+    res = runner.run_batch(circs, bits, "c64", kmax=tuned["kmax"], mfma_min_k=tuned["mfma_min_k"],
+                           graph=True, repeats=args.warmup + args.steps, plans=plans)
+    times = res["times"][args.warmup:]
+    t = sum(times) / len(times)
+    gate_amps = sum(len(c.gates) * float(1 << c.n) for c in circs)
+    swept = res["info"]["amps_swept"]
+    # complex128 batch on the same GPU (two halves: 227 GiB at once is too close to HBM size)
+    err = []
+    half = (count + 1) // 2
+    t128 = 0.0
+    for lo in (0, half):
+        sub = slice(lo, min(lo + half, count))
+        r = runner.run_batch(circs[sub], bits[sub], "c128", kmax=4, graph=True)
+        t128 += r["times"][-1]
+        for a64, a128 in zip(res["amps"][sub], r["amps"]):
+            err.append(orc.rel_l2(a64, a128))
+    # oracle on a stratified subset: the first circuit of each n <= 22
+    oracle_err = {}
+    for nq in sorted({c.n for c in circs}):
+        if nq > 22:
+            continue
+        j = next(i for i, c in enumerate(circs) if c.n == nq)
+        oracle_err[nq] = orc.rel_l2(res["amps"][j], orc.gather(orc.simulate(circs[j]), bits[j]))
+    line = {
+        "metric": "batch: circuits/s and amp-updates/s, one graph-captured batch",
+        "value": count / t, "unit": "circuits/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(1e3 * t, 2), "higher_is_better": True,
+        "dtype": "c64", "data": "synthetic",
+        "config": {"workload": f"{count} ABCDCDAB circuits, n ~ U{{20..28}}, depth ~ U{{10..20}}, "
+                               "complex64, 1024 bitstrings each",
+                   "circuits": count, "gates": sum(len(c.gates) for c in circs),
+                   "sweeps": sum(res["sweeps"]), "launches_per_batch": res["info"]["launches"]},
+        "amp_updates_per_s": gate_amps / t,
+        "hbm_GBps_sweeps": 16.0 * swept / t / 1e9,
+        "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"],
+        "t_tune_s": round(t_tune, 2), "t_plan_s": round(t_plan, 2),
+        "c128_batch_s": round(t128, 3),
+        "rel_l2_vs_c128_max": max(err), "rel_l2_vs_oracle_by_n": oracle_err,
+    }
     print(json.dumps(line), flush=True)
     return 0
 

@@ -194,6 +194,38 @@ int sv_set_option(sv_handle h, int option, int64_t value);
 int sv_counters(sv_handle h, int64_t counters[8]);
 int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
 
+/* ---- batches of independent states ----------------------------------------
+ * Many circuits of different qubit counts run as one recorded execution: the
+ * queued operations of each state (its plan) are taken over, sweep r of every
+ * state goes into round r, and each round is one launch per kernel form
+ * (matrix-core / VALU), block width k and fold flag, whose workgroups are
+ * divided among the states in proportion to their size.  With
+ * SV_BATCH_GRAPH all rounds are captured into one HIP graph, so a batch is
+ * one graph launch and can be replayed (e.g. after sv_reset of every state).
+ * A state's own operation order is kept; results are bitwise identical to
+ * running the same operations on the state alone.
+ *
+ * sv_batch_prepare -- handles: `count` distinct resident states of one dtype
+ *   (HBM, not tiered) with no queued permutes; their queues are emptied.
+ *   hip_stream: stream for the batch (NULL: owned).  The states must outlive
+ *   the batch.  Errors: SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESTATE.
+ * sv_batch_launch  -- enqueue the batch after the work already queued on the
+ *   states' streams; later work on those streams waits for it.  Asynchronous.
+ * sv_batch_sync    -- wait for the last launch.
+ * sv_batch_info    -- [0] launches per run, [1] sweeps per run, [2]
+ *   amplitudes swept per run, [3] 1 if captured in a graph.
+ * sv_batch_destroy -- free the batch (not the states).
+ * sv_batch_error   -- text of the last batch failure (b may be NULL).
+ */
+typedef struct sv_batch_s* sv_batch;
+enum { SV_BATCH_GRAPH = 1 };
+int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream, sv_batch* out);
+int sv_batch_launch(sv_batch b);
+int sv_batch_sync(sv_batch b);
+int sv_batch_info(sv_batch b, int64_t info[4]);
+int sv_batch_destroy(sv_batch b);
+const char* sv_batch_error(sv_batch b);
+
 #ifdef __cplusplus
 }
 #endif

@@ -1,0 +1,320 @@
+// Batch executor: many resident states, their queued operations applied
+// round by round with one launch per (kernel form, k, fold) per round, all
+// rounds optionally captured into one HIP graph (see sv_batch_prepare in
+// include/sv.h).
+//
+// Sweep r of every state goes into round r.  Within a round the sweeps of
+// different states touch different buffers, so they share a launch; rounds
+// are ordered on one stream, which keeps every state's own op order.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/sv.h"
+#include "sv_internal.h"
+#include "sv_state.h"
+
+using namespace sv;
+
+namespace {
+
+struct Launch {
+    int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal (one item)
+    int dtype, k;
+    bool fold;
+    size_t first;      // index of the first Sweep item
+    int nitems;
+    uint64_t blocks;
+    // diagonal launches
+    void* psi;
+    int nloc;
+    DiagSpec diag;
+};
+
+}  // namespace
+
+struct sv_batch_s {
+    std::vector<sv_state*> states;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    void* d_arena = nullptr;
+    void* d_items = nullptr;
+    std::vector<Launch> launches;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    hipEvent_t ev_done = nullptr;
+    std::vector<hipEvent_t> ev_in;
+    int64_t sweeps = 0;
+    double amps_swept = 0;
+    std::string err;
+};
+
+namespace {
+
+thread_local std::string g_batch_error;
+
+int berr(sv_batch_s* b, int code, const std::string& m)
+{
+    if (b) b->err = m;
+    else g_batch_error = m;
+    return code;
+}
+
+void free_batch(sv_batch_s* b)
+{
+    if (!b) return;
+    if (b->stream) (void)hipStreamSynchronize(b->stream);
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->d_arena) (void)hipFree(b->d_arena);
+    if (b->d_items) (void)hipFree(b->d_items);
+    if (b->ev_done) (void)hipEventDestroy(b->ev_done);
+    for (hipEvent_t e : b->ev_in) (void)hipEventDestroy(e);
+    if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
+    delete b;
+}
+
+hipError_t enqueue_all(sv_batch_s* b)
+{
+    const Sweep* items = (const Sweep*)b->d_items;
+    for (const Launch& L : b->launches) {
+        hipError_t e = hipSuccess;
+        if (L.kind == 0)
+            e = launch_dense_batch(b->stream, L.dtype, L.k, L.fold, items + L.first, L.nitems, L.blocks);
+        else if (L.kind == 1)
+            e = launch_dense_mfma_batch(b->stream, L.k, L.fold, items + L.first, L.nitems, L.blocks);
+        else
+            e = launch_diag(b->stream, L.psi, L.dtype, L.nloc, 0, L.diag);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace
+
+extern "C" {
+
+int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream, sv_batch* out)
+{
+    if (!out || !handles || count < 1) return berr(nullptr, SV_EINVAL, "bad batch arguments");
+    const int dtype = handles[0] ? handles[0]->dtype : -1;
+    for (int i = 0; i < count; ++i) {
+        sv_state* h = handles[i];
+        if (!h) return berr(nullptr, SV_EINVAL, "NULL handle in batch");
+        if (h->poisoned) return SV_ESTATE;
+        if (h->tier) return berr(nullptr, SV_EINVAL, "batched states must be resident in HBM");
+        if (h->dtype != dtype) return berr(nullptr, SV_EINVAL, "batched states must share a dtype");
+        for (int j = 0; j < i; ++j)
+            if (handles[j] == h) return berr(nullptr, SV_EINVAL, "duplicate handle in batch");
+        for (const auto& op : h->ops)
+            if (op.kind == OP_LPERM) return berr(nullptr, SV_EINVAL, "queued permute in a batched state");
+    }
+    sv_batch_s* b = new (std::nothrow) sv_batch_s();
+    if (!b) return berr(nullptr, SV_ENOMEM, "host allocation failed");
+    b->states.assign(handles, handles + count);
+    hipError_t e;
+    if (hip_stream) {
+        b->stream = (hipStream_t)hip_stream;
+    } else {
+        e = hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) { free_batch(b); return berr(nullptr, SV_EDEVICE, "stream creation failed"); }
+        b->own_stream = true;
+    }
+
+    // one device arena holding every state's matrices and tables
+    std::vector<size_t> abase(count);
+    size_t atot = 0;
+    for (int i = 0; i < count; ++i) {
+        abase[i] = atot;
+        atot += (handles[i]->arena.size() + 255) & ~(size_t)255;
+    }
+    if (atot) {
+        if (hipMalloc(&b->d_arena, atot) != hipSuccess) {
+            (void)hipGetLastError();
+            free_batch(b);
+            return berr(nullptr, SV_ENOMEM, "device allocation of the batch arena failed");
+        }
+        for (int i = 0; i < count; ++i)
+            if (!handles[i]->arena.empty()) {
+                e = hipMemcpy((char*)b->d_arena + abase[i], handles[i]->arena.data(),
+                              handles[i]->arena.size(), hipMemcpyHostToDevice);
+                if (e != hipSuccess) { free_batch(b); return berr(nullptr, SV_EDEVICE, "arena upload failed"); }
+            }
+    }
+
+    // per state: its sweeps (dense + folded diagonal, or diagonal alone)
+    struct Sw { int kind; const Op* op; const Op* fold; };
+    std::vector<std::vector<Sw>> sweeps(count);
+    size_t rounds = 0;
+    for (int i = 0; i < count; ++i) {
+        sv_state* h = handles[i];
+        const auto& ops = h->ops;
+        for (size_t j = 0; j < ops.size(); ++j) {
+            if (ops[j].kind == OP_DENSE) {
+                const Op* f = nullptr;
+                if (h->fold && j + 1 < ops.size() && ops[j + 1].kind == OP_DIAG) f = &ops[++j];
+                sweeps[i].push_back({0, &ops[j - (f ? 1 : 0)], f});
+            } else {
+                sweeps[i].push_back({2, &ops[j], nullptr});
+            }
+        }
+        rounds = std::max(rounds, sweeps[i].size());
+    }
+
+    std::vector<Sweep> items;
+    for (size_t r = 0; r < rounds; ++r) {
+        // (form, k, fold) -> item indices of this round, in state order
+        std::map<std::tuple<int, int, int>, std::vector<Sweep>> groups;
+        for (int i = 0; i < count; ++i) {
+            if (r >= sweeps[i].size()) continue;
+            sv_state* h = handles[i];
+            const Sw& w = sweeps[i][r];
+            const char* ab = (const char*)b->d_arena + abase[i];
+            b->sweeps += 1;
+            b->amps_swept += (double)((uint64_t)1 << h->n);
+            if (w.kind == 2) {
+                Launch L{};
+                L.kind = 2;
+                L.dtype = h->dtype;
+                L.psi = h->dev;
+                L.nloc = h->n;
+                L.diag.m = w.op->k;
+                for (int t = 0; t < w.op->k; ++t) L.diag.pos[t] = w.op->pos[t];
+                L.diag.table = ab + w.op->off;
+                b->launches.push_back(L);
+                h->counters[1] += 1;
+                h->counters[3] += (int64_t)1 << h->n;
+                continue;
+            }
+            DiagSpec fd;
+            if (w.fold) {
+                fd.m = w.fold->k;
+                for (int t = 0; t < w.fold->k; ++t) fd.pos[t] = w.fold->pos[t];
+                fd.table = ab + w.fold->off;
+            }
+            const int k = w.op->k;
+            Sweep s = make_sweep(h->dev, h->n, k, w.op->pos, ab + w.op->off, w.fold ? &fd : nullptr, 0);
+            const bool mf = h->dtype == 0 && h->mfma_min_k >= 4 && k >= h->mfma_min_k && h->n >= k + 4;
+            groups[std::make_tuple(mf ? 1 : 0, k, w.fold ? 1 : 0)].push_back(s);
+            h->counters[0] += 1;
+            h->counters[3] += (int64_t)1 << h->n;
+        }
+        for (auto& kv : groups) {
+            Launch L{};
+            L.kind = std::get<0>(kv.first);
+            L.k = std::get<1>(kv.first);
+            L.fold = std::get<2>(kv.first) != 0;
+            L.dtype = dtype;
+            L.first = items.size();
+            L.nitems = (int)kv.second.size();
+            uint64_t blk = 0;
+            for (Sweep& s : kv.second) {
+                s.block0 = blk;
+                blk += L.kind == 1 ? mfma_batch_blocks(s.groups) : (s.groups + 255) / 256;
+                items.push_back(s);
+            }
+            L.blocks = blk;
+            if (blk > 0x7fffffffull) { free_batch(b); return berr(nullptr, SV_EINVAL, "batch round too large"); }
+            b->launches.push_back(L);
+        }
+    }
+    if (!items.empty()) {
+        if (hipMalloc(&b->d_items, items.size() * sizeof(Sweep)) != hipSuccess) {
+            (void)hipGetLastError();
+            free_batch(b);
+            return berr(nullptr, SV_ENOMEM, "device allocation of the batch table failed");
+        }
+        e = hipMemcpy(b->d_items, items.data(), items.size() * sizeof(Sweep), hipMemcpyHostToDevice);
+        if (e != hipSuccess) { free_batch(b); return berr(nullptr, SV_EDEVICE, "batch table upload failed"); }
+    }
+    for (int i = 0; i < count; ++i) {
+        handles[i]->ops.clear();
+        handles[i]->arena.clear();
+    }
+    e = hipEventCreateWithFlags(&b->ev_done, hipEventDisableTiming);
+    if (e != hipSuccess) { free_batch(b); return berr(nullptr, SV_EDEVICE, "event creation failed"); }
+    b->ev_in.assign(count, nullptr);
+    for (auto& ev : b->ev_in)
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            free_batch(b);
+            return berr(nullptr, SV_EDEVICE, "event creation failed");
+        }
+    if (flags & SV_BATCH_GRAPH) {
+        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = enqueue_all(b);
+            e = hipStreamEndCapture(b->stream, &b->graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            free_batch(b);
+            return berr(nullptr, SV_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
+        }
+    }
+    *out = b;
+    return SV_OK;
+}
+
+int sv_batch_launch(sv_batch b)
+{
+    if (!b) return berr(nullptr, SV_EINVAL, "NULL batch");
+    // order after everything already queued on the states' own streams
+    for (size_t i = 0; i < b->states.size(); ++i) {
+        sv_state* h = b->states[i];
+        if (h->poisoned) return SV_ESTATE;
+        if (!h->ops.empty()) return berr(b, SV_EINVAL, "state has operations queued after the batch was prepared");
+        if (hipEventRecord(b->ev_in[i], h->stream) != hipSuccess ||
+            hipStreamWaitEvent(b->stream, b->ev_in[i], 0) != hipSuccess)
+            return berr(b, SV_EDEVICE, "stream ordering failed");
+    }
+    hipError_t e = b->exec ? hipGraphLaunch(b->exec, b->stream) : enqueue_all(b);
+    if (e != hipSuccess) {
+        for (sv_state* h : b->states) { h->poisoned = true; h->err = "batch launch failed"; }
+        return berr(b, SV_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+    }
+    if (hipEventRecord(b->ev_done, b->stream) != hipSuccess) return berr(b, SV_EDEVICE, "event record failed");
+    for (sv_state* h : b->states)
+        if (hipStreamWaitEvent(h->stream, b->ev_done, 0) != hipSuccess)
+            return berr(b, SV_EDEVICE, "stream ordering failed");
+    return SV_OK;
+}
+
+int sv_batch_sync(sv_batch b)
+{
+    if (!b) return berr(nullptr, SV_EINVAL, "NULL batch");
+    hipError_t e = hipStreamSynchronize(b->stream);
+    if (e != hipSuccess) {
+        for (sv_state* h : b->states) { h->poisoned = true; h->err = "batch execution failed"; }
+        return berr(b, SV_EDEVICE, std::string("batch execution failed: ") + hipGetErrorString(e));
+    }
+    return SV_OK;
+}
+
+int sv_batch_info(sv_batch b, int64_t info[4])
+{
+    if (!b || !info) return SV_EINVAL;
+    info[0] = (int64_t)b->launches.size();
+    info[1] = b->sweeps;
+    info[2] = (int64_t)b->amps_swept;
+    info[3] = b->exec ? 1 : 0;
+    return SV_OK;
+}
+
+int sv_batch_destroy(sv_batch b)
+{
+    free_batch(b);
+    return SV_OK;
+}
+
+const char* sv_batch_error(sv_batch b)
+{
+    return b ? b->err.c_str() : g_batch_error.c_str();
+}
+
+}  // extern "C"

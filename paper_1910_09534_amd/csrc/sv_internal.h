@@ -26,6 +26,26 @@ struct BitRuns {
     int shift[kMaxRuns] = {};      // > 0 left shift, < 0 right shift
 };
 
+// One dense sweep: a 2^k x 2^k block on positions tpos of the amplitude
+// range psi[0, 2^nloc), optionally followed (same sweep) by a diagonal table.
+struct Sweep {
+    void* psi;
+    const void* mat;               // row-major 2^k x 2^k, state dtype
+    const void* ftab;              // folded diagonal table or nullptr
+    uint64_t groups;               // 2^(nloc - k)
+    uint64_t idx_offset;           // global index of psi[0] (bits of sliced positions)
+    uint64_t lowmask[kMaxDense];   // (1 << p) - 1 for the target positions, ascending
+    uint64_t block0;               // batched launches: first block of this sweep
+    int tpos[kMaxDense];           // target positions in matrix-bit order
+    int k;
+    int fold_m;
+    int fold_pos[kMaxDiag];
+};
+
+// Fill a Sweep for positions pos[0..k) over 2^nloc amplitudes.
+Sweep make_sweep(void* psi, int nloc, int k, const int* pos, const void* mat, const DiagSpec* fold,
+                 uint64_t idx_offset);
+
 // Build runs for "value at bit from[p] goes to bit to[p]" for p < nbits.
 BitRuns make_runs(int nbits, const int* from, const int* to);
 
@@ -43,6 +63,17 @@ hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, c
 // Matrix-core form of the dense sweep (complex64, 4 <= k <= 6, nloc >= k + 4).
 hipError_t launch_dense_mfma(hipStream_t st, void* psi, int nloc, int k, const int* pos,
                              const void* mat, const DiagSpec* fold, uint64_t idx_offset);
+
+// Batched dense sweeps: many states, one launch (same dtype, k and fold
+// flag).  d_items: device array of Sweep descriptors whose
+// block0 fields partition [0, total_blocks).  VALU form: one group per lane,
+// 256 lanes per workgroup.  MFMA form (complex64, k >= 4): blocks per sweep
+// from mfma_batch_blocks.
+hipError_t launch_dense_batch(hipStream_t st, int dtype, int k, bool fold, const Sweep* d_items,
+                              int nitems, uint64_t total_blocks);
+hipError_t launch_dense_mfma_batch(hipStream_t st, int k, bool fold, const Sweep* d_items, int nitems,
+                                   uint64_t total_blocks);
+uint64_t mfma_batch_blocks(uint64_t groups);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
 hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,

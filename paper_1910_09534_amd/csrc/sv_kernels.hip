@@ -14,13 +14,9 @@
 // base + l); the group counter is spread over the non-target bit positions
 // in ascending order, so for targets above bit 5 the 64 lanes of one load
 // instruction read 64 consecutive amplitudes (512 B for complex64).
-#include "sv_internal.h"
+#include "sv_device.h"
 
 namespace sv {
-
-template <typename R> struct Vec2;
-template <> struct Vec2<float> { using T = float2; };
-template <> struct Vec2<double> { using T = double2; };
 
 struct RunsK {
     int count;
@@ -107,107 +103,39 @@ hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, boo
 }
 
 // ---------------------------------------------------------------------------
-// fused dense block
+// fused dense block (VALU form; the body is dense_group in sv_device.h)
 // ---------------------------------------------------------------------------
-struct DenseK {
-    uint64_t groups;
-    uint64_t idx_offset;
-    uint64_t lowmask[kMaxDense];       // (1 << p) - 1 for target positions, ascending
-    uint64_t off[1 << kMaxDense];      // offset of local index c (matrix order)
-    int tpos[kMaxDense];               // target positions, matrix-bit order
-    int fold_m;
-    int fold_pos[kMaxDiag];
-    uint32_t fold_map[1 << kMaxDense]; // fold-table bits contributed by local index c
-};
-
 template <typename R, int K, bool FOLD>
-__global__ __launch_bounds__(256) void k_dense(typename Vec2<R>::T* __restrict__ psi,
-                                               const typename Vec2<R>::T* __restrict__ mat,
-                                               const typename Vec2<R>::T* __restrict__ ftab,
-                                               DenseK a)
+__global__ __launch_bounds__(256) void k_dense(Sweep a)
 {
-    using V = typename Vec2<R>::T;
-    constexpr int D = 1 << K;
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.groups; g += stride) {
-        uint64_t base = g;
-#pragma unroll
-        for (int j = 0; j < K; ++j) {
-            const uint64_t low = base & a.lowmask[j];
-            base = ((base ^ low) << 1) | low;
-        }
-        uint64_t bitv[K];                      // 2^(target position j)
-#pragma unroll
-        for (int j = 0; j < K; ++j) bitv[j] = 1ull << a.tpos[j];
-        V x[D];
-#pragma unroll
-        for (int c = 0; c < D; ++c) {
-            uint64_t o = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j)
-                if ((c >> j) & 1) o |= bitv[j];
-            x[c] = psi[base + o];
-        }
-        uint32_t fb = 0;
-        if (FOLD) {
-            const uint64_t gi = base + a.idx_offset;
-            for (int j = 0; j < a.fold_m; ++j) fb |= (uint32_t)((gi >> a.fold_pos[j]) & 1u) << j;
-        }
-        // One matrix row per iteration: the row is wave-uniform and is read
-        // with scalar loads; not unrolling the row loop keeps only one row
-        // (2^(k+1) values) live in SGPRs instead of the whole matrix.
-#pragma unroll 1
-        for (int r = 0; r < D; ++r) {
-            R re = 0, im = 0;
-#pragma unroll
-            for (int c = 0; c < D; ++c) {
-                const V m = mat[r * D + c];
-                re = fma(m.x, x[c].x, re);
-                re = fma(-m.y, x[c].y, re);
-                im = fma(m.x, x[c].y, im);
-                im = fma(m.y, x[c].x, im);
-            }
-            // offset of row r computed from the target positions (a dynamic
-            // index into the kernel-argument table would spill SGPRs)
-            uint64_t orow = 0;
-#pragma unroll
-            for (int j = 0; j < K; ++j) orow |= ((r >> j) & 1) ? bitv[j] : 0ull;
-            if (FOLD) {
-                uint32_t fr = 0;
-                for (int j = 0; j < a.fold_m; ++j) fr |= (uint32_t)((orow >> a.fold_pos[j]) & 1u) << j;
-                const V p = ftab[fb | fr];
-                const R t = re * p.x - im * p.y;
-                im = re * p.y + im * p.x;
-                re = t;
-            }
-            psi[base + orow] = V{re, im};
-        }
+    for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.groups; g += stride)
+        dense_group<R, K, FOLD>(a, g);
+}
+
+// Batched: workgroup b serves sweep i with items[i].block0 <= b < items[i+1].block0,
+// one group per lane.
+template <typename R, int K, bool FOLD>
+__global__ __launch_bounds__(256) void k_dense_batch(const Sweep* __restrict__ items, int nitems)
+{
+    int lo = 0, hi = nitems - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[mid].block0 <= blockIdx.x) lo = mid;
+        else hi = mid - 1;
     }
+    const Sweep& a = items[lo];
+    const uint64_t g = ((uint64_t)blockIdx.x - a.block0) * blockDim.x + threadIdx.x;
+    if (g < a.groups) dense_group<R, K, FOLD>(a, g);
 }
 
-template <typename R, int K>
-static hipError_t dense_dispatch(hipStream_t st, void* psi, const void* mat, const void* ftab,
-                                 const DenseK& a, bool fold)
+Sweep make_sweep(void* psi, int nloc, int k, const int* pos, const void* mat, const DiagSpec* fold,
+                 uint64_t idx_offset)
 {
-    using V = typename Vec2<R>::T;
-    const dim3 grid(grid_for(a.groups, 256)), block(256);
-    if (fold)
-        hipLaunchKernelGGL((k_dense<R, K, true>), grid, block, 0, st, (V*)psi, (const V*)mat,
-                           (const V*)ftab, a);
-    else
-        hipLaunchKernelGGL((k_dense<R, K, false>), grid, block, 0, st, (V*)psi, (const V*)mat,
-                           (const V*)ftab, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
-                        const void* mat, const DiagSpec* fold, uint64_t idx_offset, int mfma_min_k)
-{
-    if (k < 1 || k > kMaxDense || k > nloc) return hipErrorInvalidValue;
-    if (dtype == 0 && mfma_min_k >= 4 && k >= mfma_min_k && nloc >= k + 4)
-        return launch_dense_mfma(st, psi, nloc, k, pos, mat, fold, idx_offset);
-    if (dtype && k > 5) return hipErrorInvalidValue;
-    DenseK a{};
+    Sweep a{};
+    a.psi = psi;
+    a.mat = mat;
+    a.k = k;
     a.groups = 1ull << (nloc - k);
     a.idx_offset = idx_offset;
     int sp[kMaxDense];
@@ -218,43 +146,80 @@ hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, c
         }
     for (int j = 0; j < k; ++j) a.lowmask[j] = (1ull << sp[j]) - 1;
     for (int j = 0; j < k; ++j) a.tpos[j] = pos[j];
-    for (int c = 0; c < (1 << k); ++c) {
-        uint64_t o = 0;
-        for (int j = 0; j < k; ++j)
-            if ((c >> j) & 1) o |= 1ull << pos[j];
-        a.off[c] = o;
-    }
-    const bool do_fold = fold && fold->m > 0;
-    if (do_fold) {
+    if (fold && fold->m > 0) {
+        a.ftab = fold->table;
         a.fold_m = fold->m;
         for (int j = 0; j < fold->m; ++j) a.fold_pos[j] = fold->pos[j];
-        for (int c = 0; c < (1 << k); ++c) {
-            uint32_t b = 0;
-            for (int j = 0; j < fold->m; ++j)
-                if ((a.off[c] >> fold->pos[j]) & 1) b |= 1u << j;
-            a.fold_map[c] = b;
-        }
     }
-    const void* ft = do_fold ? fold->table : nullptr;
+    return a;
+}
+
+template <typename R, int K>
+static hipError_t dense_dispatch(hipStream_t st, const Sweep& a)
+{
+    const dim3 grid(grid_for(a.groups, 256)), block(256);
+    if (a.ftab) hipLaunchKernelGGL((k_dense<R, K, true>), grid, block, 0, st, a);
+    else hipLaunchKernelGGL((k_dense<R, K, false>), grid, block, 0, st, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, const int* pos,
+                        const void* mat, const DiagSpec* fold, uint64_t idx_offset, int mfma_min_k)
+{
+    if (k < 1 || k > kMaxDense || k > nloc) return hipErrorInvalidValue;
+    if (dtype && k > 5) return hipErrorInvalidValue;
+    if (dtype == 0 && mfma_min_k >= 4 && k >= mfma_min_k && nloc >= k + 4)
+        return launch_dense_mfma(st, psi, nloc, k, pos, mat, fold, idx_offset);
+    const Sweep a = make_sweep(psi, nloc, k, pos, mat, fold, idx_offset);
     if (dtype == 0) {
         switch (k) {
-            case 1: return dense_dispatch<float, 1>(st, psi, mat, ft, a, do_fold);
-            case 2: return dense_dispatch<float, 2>(st, psi, mat, ft, a, do_fold);
-            case 3: return dense_dispatch<float, 3>(st, psi, mat, ft, a, do_fold);
-            case 4: return dense_dispatch<float, 4>(st, psi, mat, ft, a, do_fold);
-            case 5: return dense_dispatch<float, 5>(st, psi, mat, ft, a, do_fold);
-            case 6: return dense_dispatch<float, 6>(st, psi, mat, ft, a, do_fold);
+            case 1: return dense_dispatch<float, 1>(st, a);
+            case 2: return dense_dispatch<float, 2>(st, a);
+            case 3: return dense_dispatch<float, 3>(st, a);
+            case 4: return dense_dispatch<float, 4>(st, a);
+            case 5: return dense_dispatch<float, 5>(st, a);
+            case 6: return dense_dispatch<float, 6>(st, a);
         }
     } else {
         switch (k) {
-            case 1: return dense_dispatch<double, 1>(st, psi, mat, ft, a, do_fold);
-            case 2: return dense_dispatch<double, 2>(st, psi, mat, ft, a, do_fold);
-            case 3: return dense_dispatch<double, 3>(st, psi, mat, ft, a, do_fold);
-            case 4: return dense_dispatch<double, 4>(st, psi, mat, ft, a, do_fold);
-            case 5: return dense_dispatch<double, 5>(st, psi, mat, ft, a, do_fold);
+            case 1: return dense_dispatch<double, 1>(st, a);
+            case 2: return dense_dispatch<double, 2>(st, a);
+            case 3: return dense_dispatch<double, 3>(st, a);
+            case 4: return dense_dispatch<double, 4>(st, a);
+            case 5: return dense_dispatch<double, 5>(st, a);
         }
     }
     return hipErrorInvalidValue;
+}
+
+hipError_t launch_dense_batch(hipStream_t st, int dtype, int k, bool fold, const Sweep* d_items,
+                              int nitems, uint64_t total_blocks)
+{
+    if (nitems <= 0) return hipSuccess;
+    if (total_blocks == 0 || total_blocks > 0x7fffffffull) return hipErrorInvalidValue;
+    if (k < 1 || k > kMaxDense || (dtype && k > 5)) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)total_blocks), block(256);
+#define SV_DB(RR, KK)                                                                              if (fold)                                                                                          hipLaunchKernelGGL((k_dense_batch<RR, KK, true>), grid, block, 0, st, d_items, nitems);       else                                                                                               hipLaunchKernelGGL((k_dense_batch<RR, KK, false>), grid, block, 0, st, d_items, nitems);
+    if (dtype == 0) {
+        switch (k) {
+            case 1: SV_DB(float, 1) break;
+            case 2: SV_DB(float, 2) break;
+            case 3: SV_DB(float, 3) break;
+            case 4: SV_DB(float, 4) break;
+            case 5: SV_DB(float, 5) break;
+            case 6: SV_DB(float, 6) break;
+        }
+    } else {
+        switch (k) {
+            case 1: SV_DB(double, 1) break;
+            case 2: SV_DB(double, 2) break;
+            case 3: SV_DB(double, 3) break;
+            case 4: SV_DB(double, 4) break;
+            case 5: SV_DB(double, 5) break;
+        }
+    }
+#undef SV_DB
+    return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,83 @@
+// Internal: the state handle behind the C-ABI's sv_handle (shared by the
+// single-state executor and the batch executor).  Not installed.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "sv_internal.h"
+
+namespace sv {
+
+enum OpKind { OP_DENSE = 0, OP_DIAG = 1, OP_LPERM = 2 };
+
+struct Op {
+    int kind = OP_DENSE;
+    int k = 0;                 // dense: qubit count; diag: m
+    int pos[kMaxDiag] = {};    // physical positions at queue time
+    size_t off = 0;            // arena offset of matrix / table
+    BitRuns runs;              // OP_LPERM: destination -> source over local bits
+};
+
+}  // namespace sv
+
+struct sv_state {
+    using Op = sv::Op;
+    int n = 0, s = 0, L = 0, dtype = 0;
+    size_t amp = 8;
+    uint64_t slice_mask = 0;
+    std::vector<int> order, pos;          // order[p] = logical at p; pos[q] = position of q
+
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    bool tier = false;
+
+    // resident storage
+    void* dev = nullptr;
+    size_t dev_bytes = 0;
+    bool own_dev = false;
+    void* scratch = nullptr;              // permute target (resident)
+
+    // host tier
+    std::vector<void*> files;             // [t * 2^s + u], 2^(L-s) amplitudes each
+    bool pinned_tier = true;              // files pinned (hipHostMalloc) or pageable (mmap)
+    std::vector<uint8_t> slice_zero;      // slice known to be all zero
+    std::vector<void*> slots;             // device slice buffers
+    void* pslot = nullptr;                // device buffer for local permutes
+    hipStream_t s_in = nullptr, s_out = nullptr;
+    std::vector<hipEvent_t> ev_in, ev_comp, ev_out;
+
+    // operation queue
+    std::vector<Op> ops;
+    std::vector<uint8_t> arena;
+    void* d_arena = nullptr;
+    size_t d_arena_cap = 0;
+    void* h_arena = nullptr;
+    size_t h_arena_cap = 0;
+    hipEvent_t ev_arena = nullptr;
+
+    // reduction work buffers
+    void* d_bits = nullptr;  size_t d_bits_cap = 0;
+    void* d_acc = nullptr;   size_t d_acc_cap = 0;
+    void* d_part = nullptr;  size_t d_part_cap = 0;
+    void* d_tcol = nullptr;  size_t d_tcol_cap = 0;
+    void* d_rowmap = nullptr; size_t d_rowmap_cap = 0;
+    void* d_small = nullptr;              // 8 doubles
+
+    // options and accounting
+    bool timing = false, fold = true;
+    int mfma_min_k = 4;
+    int nslots = 3;
+    std::vector<hipEvent_t> tev_pool;
+    size_t tev_used = 0;
+    double t_ms = 0.0;
+    int64_t t_count = 0;
+    int64_t counters[8] = {};
+
+    bool poisoned = false;
+    std::string err;
+};
+

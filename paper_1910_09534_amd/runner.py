@@ -85,3 +85,48 @@ def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: 
         return out
     finally:
         st.close()
+
+
+def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: bool = True,
+              repeats: int = 1, plans=None) -> Dict[str, object]:
+    """Many independent circuits as one batched execution (one graph launch
+    per run).  kmax / mfma_min_k: an int, or a dict n -> value (autotuned).
+    Each repeat resets every state and replays the batch; the returned
+    amplitudes are those of the last repeat."""
+    kof = (lambda n: kmax[n]) if isinstance(kmax, dict) else (lambda n: kmax)
+    mof = (lambda n: mfma_min_k[n]) if isinstance(mfma_min_k, dict) else (lambda n: mfma_min_k)
+    t0 = time.perf_counter()
+    if plans is None:
+        plans = [planner.plan(c.gates, kof(c.n)) for c in circuits]
+    t_plan = time.perf_counter() - t0
+    states = []
+    b = None
+    try:
+        for c in circuits:
+            st = sv.State(c.n, 0, dtype)
+            sv.set_option(st.h, sv.SV_OPT_MFMA, int(mof(c.n)))
+            states.append(st)
+        for st, ops in zip(states, plans):
+            planner.enqueue(st.h, ops, st.dtype)
+        b = sv.batch_prepare([st.h for st in states], graph=graph)
+        times = []
+        outs = None
+        for rep in range(repeats):
+            if rep:
+                for st in states:
+                    sv.reset(st.h)
+            for st in states:
+                sv.sync_state(st.h)
+            t1 = time.perf_counter()
+            sv.batch_launch(b)
+            outs = [sv.reduce_slices(st.h, bits) for st, bits in zip(states, bits_list)]
+            times.append(time.perf_counter() - t1)
+        info = sv.batch_info(b)
+        return {"amps": [o[0] for o in outs], "stats": [o[1] for o in outs], "times": times,
+                "t_plan": t_plan, "info": info,
+                "sweeps": [sum(1 for o in p if o.kind == "dense") for p in plans]}
+    finally:
+        if b is not None:
+            sv.batch_destroy(b)
+        for st in states:
+            st.close()

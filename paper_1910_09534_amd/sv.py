@@ -25,7 +25,10 @@ ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_E
 
 EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "apply_diag",
            "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
-           "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time")
+           "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
+           "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
+           "sv_batch_destroy", "sv_batch_error")
+SV_BATCH_GRAPH = 1
 
 
 class SVError(RuntimeError):
@@ -57,8 +60,15 @@ def load():
     L.sv_set_option.argtypes = [P, I, I64]
     L.sv_counters.argtypes = [P, P]
     L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+    L.sv_batch_prepare.argtypes = [I, P, I, P, ctypes.POINTER(P)]
+    L.sv_batch_launch.argtypes = [P]
+    L.sv_batch_sync.argtypes = [P]
+    L.sv_batch_info.argtypes = [P, P]
+    L.sv_batch_destroy.argtypes = [P]
+    L.sv_batch_error.argtypes = [P]
     for name in EXPORTS:
-        getattr(L, name).restype = ctypes.c_char_p if name == "last_error" else ctypes.c_int
+        text = name in ("last_error", "sv_batch_error")
+        getattr(L, name).restype = ctypes.c_char_p if text else ctypes.c_int
     return L
 
 
@@ -197,6 +207,40 @@ def sweep_time(h):
     cnt = ctypes.c_int64()
     _check(lib().sv_sweep_time(h, ctypes.byref(ms), ctypes.byref(cnt)), h)
     return ms.value, cnt.value
+
+
+def _bcheck(rc: int, b=None):
+    if rc != SV_OK:
+        msg = lib().sv_batch_error(b)
+        raise SVError(rc, msg.decode() if msg else "")
+
+
+def batch_prepare(handles, graph: bool = True, stream=None):
+    """Record the queued operations of `handles` as one batch (handle list of
+    resident states, same dtype).  Returns an opaque batch pointer."""
+    arr = (ctypes.c_void_p * len(handles))(*handles)
+    b = ctypes.c_void_p()
+    _bcheck(lib().sv_batch_prepare(len(handles), arr, SV_BATCH_GRAPH if graph else 0, stream,
+                                   ctypes.byref(b)))
+    return b.value
+
+
+def batch_launch(b) -> None:
+    _bcheck(lib().sv_batch_launch(b), b)
+
+
+def batch_sync(b) -> None:
+    _bcheck(lib().sv_batch_sync(b), b)
+
+
+def batch_info(b) -> dict:
+    i = np.zeros(4, dtype=np.int64)
+    _bcheck(lib().sv_batch_info(b, _ptr(i)), b)
+    return {"launches": int(i[0]), "sweeps": int(i[1]), "amps_swept": int(i[2]), "graph": bool(i[3])}
+
+
+def batch_destroy(b) -> None:
+    lib().sv_batch_destroy(b)
 
 
 class State:
