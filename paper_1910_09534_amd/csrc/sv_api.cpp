@@ -76,17 +76,14 @@ int ensure_dev(sv_state* h, void** p, size_t* cap, size_t need)
     if (*p) {
         hipError_t e = hipStreamSynchronize(h->stream);
         if (e != hipSuccess) return fail_dev(h, "hipStreamSynchronize", e);
-        (void)hipFree(*p);
+        pool_free(*p, *cap, false);
         *p = nullptr;
         *cap = 0;
     }
-    size_t want = std::max(need, (size_t)4096);
-    if (hipMalloc(p, want) != hipSuccess) {
-        *p = nullptr;
-        (void)hipGetLastError();
-        return set_err(h, SV_ENOMEM, "device allocation of work buffer failed");
-    }
-    *cap = want;
+    size_t got = 0;
+    *p = pool_alloc(std::max(need, (size_t)4096), false, &got);
+    if (!*p) return set_err(h, SV_ENOMEM, "device allocation of work buffer failed");
+    *cap = got;
     return SV_OK;
 }
 
@@ -190,16 +187,13 @@ int upload_arena(sv_state* h)
     if (bytes == 0) return SV_OK;
     if (h->ev_arena) TRY(h, hipEventSynchronize(h->ev_arena));   // pinned staging reusable
     if (h->h_arena_cap < bytes) {
-        if (h->h_arena) (void)hipHostFree(h->h_arena);
+        if (h->h_arena) pool_free(h->h_arena, h->h_arena_cap, true);
         h->h_arena = nullptr;
         h->h_arena_cap = 0;
-        size_t want = std::max(bytes * 2, (size_t)1 << 20);
-        if (hipHostMalloc(&h->h_arena, want, hipHostMallocDefault) != hipSuccess) {
-            h->h_arena = nullptr;
-            (void)hipGetLastError();
-            return set_err(h, SV_ENOMEM, "pinned staging allocation failed");
-        }
-        h->h_arena_cap = want;
+        size_t got = 0;
+        h->h_arena = pool_alloc(std::max(bytes * 2, (size_t)1 << 20), true, &got);
+        if (!h->h_arena) return set_err(h, SV_ENOMEM, "pinned staging allocation failed");
+        h->h_arena_cap = got;
     }
     int rc = ensure_dev(h, &h->d_arena, &h->d_arena_cap, std::max(bytes * 2, (size_t)1 << 20));
     if (rc) return rc;
@@ -327,10 +321,13 @@ void release(sv_state* h)
     for (void* p : h->slots)
         if (p) (void)hipFree(p);
     if (h->pslot) (void)hipFree(h->pslot);
-    for (void** p : {&h->d_arena, &h->d_bits, &h->d_acc, &h->d_part, &h->d_tcol, &h->d_rowmap,
-                     &h->d_small})
-        if (*p) (void)hipFree(*p);
-    if (h->h_arena) (void)hipHostFree(h->h_arena);
+    const std::pair<void*, size_t> work[] = {{h->d_arena, h->d_arena_cap}, {h->d_bits, h->d_bits_cap},
+                                             {h->d_acc, h->d_acc_cap}, {h->d_part, h->d_part_cap},
+                                             {h->d_tcol, h->d_tcol_cap}, {h->d_rowmap, h->d_rowmap_cap},
+                                             {h->d_small, 64}};
+    for (const auto& w : work)
+        if (w.first) pool_free(w.first, w.second, false);
+    if (h->h_arena) pool_free(h->h_arena, h->h_arena_cap, true);
     for (auto* v : {&h->ev_in, &h->ev_comp, &h->ev_out, &h->tev_pool})
         for (hipEvent_t e : *v) (void)hipEventDestroy(e);
     if (h->ev_arena) (void)hipEventDestroy(h->ev_arena);
@@ -479,8 +476,8 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         e = launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << n, true);
         if (e != hipSuccess) { release(h); return fail_dev(nullptr, "init kernel", e); }
     }
-    if (hipMalloc(&h->d_small, 64) != hipSuccess) {
-        (void)hipGetLastError();
+    h->d_small = pool_alloc(64, false, nullptr);
+    if (!h->d_small) {
         release(h);
         return set_err(nullptr, SV_ENOMEM, "device allocation failed");
     }

@@ -49,6 +49,11 @@ Sweep make_sweep(void* psi, int nloc, int k, const int* pos, const void* mat, co
 // Build runs for "value at bit from[p] goes to bit to[p]" for p < nbits.
 BitRuns make_runs(int nbits, const int* from, const int* to);
 
+// Pooled allocation of small work buffers (device, or pinned host).  *got
+// receives the usable size (a power of two >= bytes).  nullptr on failure.
+void* pool_alloc(size_t bytes, bool pinned_host, size_t* got);
+void pool_free(void* p, size_t bytes, bool pinned_host);
+
 // Zero-fill count amplitudes, then set element 0 to 1 if one_at_zero.
 hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, bool one_at_zero);
 
