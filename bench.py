@@ -53,6 +53,47 @@ HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
 
 
+KERNEL_SOURCES = ("paper_1910_09534_amd/csrc/sv_device.h", "paper_1910_09534_amd/csrc/sv_kernels.hip",
+                  "paper_1910_09534_amd/csrc/sv_mfma.hip", "paper_1910_09534_amd/csrc/sv_internal.h")
+TRAFFIC_FILE = "profiles/dense_sweep_30q_d14_traffic.json"
+
+
+def kernel_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def counter_traffic(kmax: int):
+    """HBM bytes per dense-sweep launch from the committed counter runs
+    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
+    when the kernels changed since the counters were taken."""
+    path = os.path.join(ROOT, TRAFFIC_FILE)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("kernel_hash") != kernel_hash() or d.get("kmax") != kmax:
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def calibrate_copy() -> int:
+    import torch
+    torch.cuda.set_device(0)
+    nbytes = 4 << 30
+    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    torch.cuda.synchronize()
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": nbytes, "copy_bytes_written": nbytes}), flush=True)
+    return 0
+
+
 def cpu_baseline(circuit, budget_s: float = 15.0):
     """The oracle as it stands (plain per-gate complex128 simulation, OpenMP
     over all host cores) on a bounded sample of the same workload: the first
@@ -86,7 +127,11 @@ def main(argv=None) -> int:
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--pins", action="store_true", help="config 3: also run the mirror pin")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run only a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args(argv)
+    if args.calibrate_copy:
+        return calibrate_copy()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design only.", file=sys.stderr)
@@ -148,7 +193,7 @@ def main(argv=None) -> int:
     hbm_frac = gbs / HBM_PEAK_GBS
     alu_frac = tflops / FP32_PEAK_TFLOPS
     roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(hbm_frac, 4), "traffic": None,
+            "frac": round(hbm_frac, 4), "traffic": counter_traffic(args.kmax),
             "kernel": "k_dense (fused dense sweep), all launches of the timed steps",
             "avg_launch_ms": round(avg_ms, 4), "launches": nswept,
             "alu": {"achieved_tflops": round(tflops, 2), "peak_tflops": FP32_PEAK_TFLOPS,
