@@ -645,7 +645,34 @@ int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix)
     op.kind = OP_DENSE;
     op.k = k;
     for (int j = 0; j < k; ++j) op.pos[j] = h->pos[qubits[j]];
-    op.off = push_arena(h, matrix, ((size_t)1 << (2 * k)) * h->amp);
+    int minp = 64;
+    for (int j = 0; j < k; ++j) minp = std::min(minp, op.pos[j]);
+    if (h->dtype == 0 && h->mfma_min_k == 4 && k < 4 && minp < 4 && h->L >= 8) {
+        // A small block whose targets sit among the lowest four positions
+        // reads and writes partial cache lines on the VALU path.  Widen it
+        // to four qubits with identity on the lowest free positions (M' = I
+        // (x) M, extra bits on top) so it runs as an address-ordered staged
+        // matrix-core sweep over whole cache lines.
+        const int D = 1 << k;
+        for (int p = 0; op.k < 4; ++p) {
+            bool used = false;
+            for (int j = 0; j < op.k; ++j) used = used || (op.pos[j] == p);
+            if (!used) op.pos[op.k++] = p;
+        }
+        const int D4 = 16;
+        std::vector<float> big((size_t)D4 * D4 * 2, 0.0f);
+        const float* m = (const float*)matrix;
+        for (int hi = 0; hi < D4 / D; ++hi)
+            for (int r = 0; r < D; ++r)
+                for (int c = 0; c < D; ++c) {
+                    const size_t dst = ((size_t)(hi * D + r) * D4 + (hi * D + c)) * 2;
+                    big[dst] = m[2 * (r * D + c)];
+                    big[dst + 1] = m[2 * (r * D + c) + 1];
+                }
+        op.off = push_arena(h, big.data(), big.size() * sizeof(float));
+    } else {
+        op.off = push_arena(h, matrix, ((size_t)1 << (2 * k)) * h->amp);
+    }
     h->ops.push_back(op);
     if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
     return SV_OK;

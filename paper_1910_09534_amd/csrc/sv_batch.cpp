@@ -27,6 +27,7 @@ struct Launch {
     int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal (one item)
     int dtype, k;
     bool fold;
+    bool staged;       // MFMA: address-ordered LDS staging
     size_t first;      // index of the first Sweep item
     int nitems;
     uint64_t blocks;
@@ -87,7 +88,8 @@ hipError_t enqueue_all(sv_batch_s* b)
         if (L.kind == 0)
             e = launch_dense_batch(b->stream, L.dtype, L.k, L.fold, items + L.first, L.nitems, L.blocks);
         else if (L.kind == 1)
-            e = launch_dense_mfma_batch(b->stream, L.k, L.fold, items + L.first, L.nitems, L.blocks);
+            e = launch_dense_mfma_batch(b->stream, L.k, L.fold, L.staged, items + L.first, L.nitems,
+                                        L.blocks);
         else
             e = launch_diag(b->stream, L.psi, L.dtype, L.nloc, 0, L.diag);
         if (e != hipSuccess) return e;
@@ -200,13 +202,15 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             const int k = w.op->k;
             Sweep s = make_sweep(h->dev, h->n, k, w.op->pos, ab + w.op->off, w.fold ? &fd : nullptr, 0);
             const bool mf = h->dtype == 0 && h->mfma_min_k >= 4 && k >= h->mfma_min_k && h->n >= k + 4;
-            groups[std::make_tuple(mf ? 1 : 0, k, w.fold ? 1 : 0)].push_back(s);
+            // form: 0 VALU, 1 MFMA direct, 3 MFMA staged
+            groups[std::make_tuple(mf ? (s.staged ? 3 : 1) : 0, k, w.fold ? 1 : 0)].push_back(s);
             h->counters[0] += 1;
             h->counters[3] += (int64_t)1 << h->n;
         }
         for (auto& kv : groups) {
             Launch L{};
-            L.kind = std::get<0>(kv.first);
+            L.kind = std::get<0>(kv.first) == 3 ? 1 : std::get<0>(kv.first);
+            L.staged = std::get<0>(kv.first) == 3;
             L.k = std::get<1>(kv.first);
             L.fold = std::get<2>(kv.first) != 0;
             L.dtype = dtype;

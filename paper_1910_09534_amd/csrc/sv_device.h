@@ -35,13 +35,16 @@ __device__ __forceinline__ uint32_t fold_index(const Sweep& a, uint64_t idx)
 // VALU form: one lane owns one group and its 2^k amplitudes.  The matrix is
 // wave-uniform and read one row per iteration with scalar loads; the row
 // loop is not unrolled so only one row (2^(k+1) values) is live in SGPRs.
-template <typename R, int K, bool FOLD>
-__device__ __forceinline__ void dense_group(const Sweep& a, uint64_t g)
+//
+// psi and mat are separate restrict parameters: the matrix must be known not
+// to alias the amplitudes, or its rows cannot stay in scalar loads across the
+// stores of earlier rows.
+template <typename R, int K, bool FOLD, typename PT, typename MT>
+__device__ __forceinline__ void dense_group(PT __restrict__ psi, MT __restrict__ mat, const Sweep& a,
+                                            uint64_t g)
 {
     using V = typename Vec2<R>::T;
     constexpr int D = 1 << K;
-    V* __restrict__ psi = (V*)a.psi;
-    const V* __restrict__ mat = (const V*)a.mat;
     const uint64_t base = group_base<K>(a, g);
     uint64_t bitv[K];
 #pragma unroll
@@ -86,25 +89,33 @@ __device__ __forceinline__ void dense_group(const Sweep& a, uint64_t g)
 // ---------------------------------------------------------------------------
 // Matrix-core form (complex64, k = 4..6), v_mfma_f32_16x16x4f32.
 //
-// y = M x is the real product [yr; yi] = [[Mr, -Mi], [Mi, Mr]] [xr; xi] of a
-// (2D x 2D) matrix A (D = 2^k) with one 2D-vector per group; sixteen groups
-// are the 16 columns of the B operand.  Operand layouts (wave64): lane l
-// supplies A[l % 16][l / 16] and B[l / 16][l % 16]; its 4 results are
-// D[4 (l / 16) + v][l % 16].  So lane l = j + 16 h works on group j:
-//   * the K index of k-step s for lane h is (amplitude 4 (s >> 1) + h, part
-//     s & 1): the lane loads the D/4 complete amplitudes c = 4 m + h of its
-//     group and feeds re / im on alternate k-steps;
-//   * output row R = 16 rb + 4 h + v is (amplitude R >> 1, part R & 1): the
-//     lane ends with complete (re, im) pairs of amplitudes 8 rb + 2 h + {0, 1}.
-// A is staged in LDS in operand order: one ds_read_b128 gives a lane its A
-// operands for four consecutive k-steps.
+// y = M x for sixteen groups at once, as three real D x D products (D = 2^k)
+// on a D x 16 block whose columns are the groups (the 3-multiplication form
+// of a complex product):
+//     P1 = Mr Xr,  P2 = Mi Xi,  P3 = (Mr + Mi)(Xr + Xi),
+//     Yr = P1 - P2,  Yi = P3 - P1 - P2.
+// Operand layouts (wave64): lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16]; its 4 results are D[4 (l / 16) + v][l % 16].  So lane
+// l = j + 16 h works on group j: at k-step s it supplies amplitude 4 s + h,
+// and it ends with amplitudes 16 rb + 4 h + v (v = 0..3) of row block rb.
+// The three real matrices are staged once per workgroup in LDS in operand
+// order: one ds_read_b128 gives a lane its A operands for four k-steps.
+//
+// Loads and stores: direct (each lane reads its own amplitudes; 16 lanes
+// cover 16 consecutive groups) or, when target bits sit among the lowest
+// four positions, staged through LDS in address order: the tile's 16 D
+// amplitudes are read as 64-lane runs of ascending addresses, parked in a
+// per-wave LDS block (row = amplitude index within the group, column =
+// group, one column of padding), and then read in operand order.
 // ---------------------------------------------------------------------------
 template <int K>
 struct MfmaShape {
     static constexpr int D = 1 << K;
-    static constexpr int RB = 2 * D / 16;    // 16-row blocks of A
-    static constexpr int KQ = 2 * D / 16;    // groups of four k-steps
-    static constexpr int NA = RB * KQ * 256; // floats of A
+    static constexpr int RB = D / 16;            // 16-row blocks per product
+    static constexpr int KS = D / 4;             // k-steps
+    static constexpr int KQ = KS / 4;            // groups of four k-steps
+    static constexpr int NA = 3 * RB * KQ * 256; // floats of the three matrices
+    static constexpr int XS = D * 17;            // float2 per wave for staging
 };
 
 template <int K>
@@ -113,23 +124,22 @@ __device__ __forceinline__ void mfma_stage_matrix(f4* As, const float2* __restri
     using S = MfmaShape<K>;
     for (int i = threadIdx.x; i < S::NA; i += blockDim.x) {
         const int s4 = i & 3, l = (i >> 2) & 63, blk = i >> 8;
-        const int sq = blk % S::KQ, rb = blk / S::KQ;
-        const int s = 4 * sq + s4;
+        const int sq = blk % S::KQ, rb = (blk / S::KQ) % S::RB, p = blk / (S::KQ * S::RB);
         const int R = 16 * rb + (l & 15);
-        const int c = 4 * (s >> 1) + (l >> 4), p = s & 1;
-        const int r = R >> 1, q = R & 1;
-        const float2 m = mat[r * S::D + c];
-        ((float*)As)[i] = (q == 0) ? (p == 0 ? m.x : -m.y) : (p == 0 ? m.y : m.x);
+        const int C = 4 * (4 * sq + s4) + (l >> 4);
+        const float2 m = mat[R * S::D + C];
+        ((float*)As)[i] = p == 0 ? m.x : (p == 1 ? m.y : m.x + m.y);
     }
 }
 
 // Tiles [t0, t_end) with stride `step` of one sweep, for the calling wave.
-template <int K, bool FOLD>
-__device__ __forceinline__ void mfma_tiles(const Sweep& a, const f4* As, uint64_t t0, uint64_t step,
-                                           uint64_t t_end)
+// Xs: this wave's staging block (STAGED only).
+template <int K, bool FOLD, bool STAGED>
+__device__ __forceinline__ void mfma_tiles(const Sweep& a, const f4* As, float2* Xs, uint64_t t0,
+                                           uint64_t step, uint64_t t_end)
 {
     using S = MfmaShape<K>;
-    constexpr int D = S::D, RB = S::RB, KQ = S::KQ;
+    constexpr int D = S::D, RB = S::RB, KQ = S::KQ, NE = D / 4;
     float2* __restrict__ psi = (float2*)a.psi;
     const int lane = threadIdx.x & 63;
     const int j = lane & 15, h = lane >> 4;
@@ -137,72 +147,114 @@ __device__ __forceinline__ void mfma_tiles(const Sweep& a, const f4* As, uint64_
 #pragma unroll
     for (int t = 0; t < K; ++t) bitv[t] = 1ull << a.tpos[t];
 
-    auto load_tile = [&](uint64_t t, float2* xx, uint64_t& b) {
-        b = group_base<K>(a, t * 16 + j);
+    // staged: this lane's part of the address / LDS slot of element 64 i + lane
+    uint64_t addr_lane = 0;
+    int slot_lane = 0;
+    if (STAGED) {
 #pragma unroll
-        for (int m = 0; m < D / 4; ++m) {
-            uint64_t o = (h & 1) ? bitv[0] : 0ull;
-            o |= (h & 2) ? bitv[1] : 0ull;
+        for (int b = 0; b < 6; ++b)
+            if ((lane >> b) & 1) {
+                addr_lane |= a.st_addr_bit[b];
+                slot_lane += a.st_slot_bit[b];
+            }
+    }
+
+    auto load_tile = [&](uint64_t t, float2* xx) {
+        if (STAGED) {
+            const uint64_t b0 = group_base<K>(a, t * 16);
 #pragma unroll
-            for (int u = 2; u < K; ++u)
-                if (((4 * m) >> u) & 1) o |= bitv[u];
-            xx[m] = psi[b + o];
+            for (int i = 0; i < NE; ++i) xx[i] = psi[b0 + addr_lane + a.st_addr_i[i]];
+        } else {
+            const uint64_t b = group_base<K>(a, t * 16 + j);
+#pragma unroll
+            for (int m = 0; m < NE; ++m) {
+                uint64_t o = (h & 1) ? bitv[0] : 0ull;
+                o |= (h & 2) ? bitv[1] : 0ull;
+#pragma unroll
+                for (int u = 2; u < K; ++u)
+                    if ((m >> (u - 2)) & 1) o |= bitv[u];
+                xx[m] = psi[b + o];
+            }
         }
     };
 
     // software pipeline: the next tile's loads are in flight while the
     // matrix cores work on the current one (tiles touch disjoint amplitudes)
-    float2 xn[D / 4];
-    uint64_t base_n = 0;
-    if (t0 < t_end) load_tile(t0, xn, base_n);
+    float2 xn[NE];
+    if (t0 < t_end) load_tile(t0, xn);
     for (uint64_t tile = t0; tile < t_end; tile += step) {
-        float2 x[D / 4];
+        float2 x[NE];
+        if (STAGED) {
 #pragma unroll
-        for (int m = 0; m < D / 4; ++m) x[m] = xn[m];
-        const uint64_t base = base_n;
-        if (tile + step < t_end) load_tile(tile + step, xn, base_n);
-        f4 acc[RB];
+            for (int i = 0; i < NE; ++i) Xs[slot_lane + a.st_slot_i[i]] = xn[i];
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
-        for (int rb = 0; rb < RB; ++rb) acc[rb] = f4{0.f, 0.f, 0.f, 0.f};
+            for (int s = 0; s < NE; ++s) x[s] = Xs[(4 * s + h) * 17 + j];
+        } else {
+#pragma unroll
+            for (int s = 0; s < NE; ++s) x[s] = xn[s];
+        }
+        if (tile + step < t_end) load_tile(tile + step, xn);
+        f4 acc[3][RB];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[p][rb] = f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int sq = 0; sq < KQ; ++sq) {
-            f4 av[RB];
+            f4 av[3][RB];
 #pragma unroll
-            for (int rb = 0; rb < RB; ++rb) av[rb] = As[(rb * KQ + sq) * 64 + lane];
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) av[p][rb] = As[((p * RB + rb) * KQ + sq) * 64 + lane];
 #pragma unroll
             for (int s4 = 0; s4 < 4; ++s4) {
-                const int s = 4 * sq + s4;
-                const float b = (s & 1) ? x[s >> 1].y : x[s >> 1].x;
+                const float2 xv = x[4 * sq + s4];
+                const float bs = xv.x + xv.y;
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb)
-                    acc[rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[rb][s4], b, acc[rb], 0, 0, 0);
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][rb][s4], xv.x, acc[0][rb], 0, 0, 0);
+                    acc[1][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][rb][s4], xv.y, acc[1][rb], 0, 0, 0);
+                    acc[2][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][rb][s4], bs, acc[2][rb], 0, 0, 0);
+                }
             }
-            // keep the next group's LDS operand reads from being hoisted:
-            // with k = 6 hoisting all of them exceeds the register file
+            // keep later LDS operand reads from being hoisted: with k = 6
+            // hoisting all of them exceeds the register file
             if (K == 6) __builtin_amdgcn_sched_barrier(0);
         }
+        const uint64_t base = group_base<K>(a, tile * 16 + j);
         uint32_t fb = 0;
         if (FOLD) fb = fold_index(a, base + a.idx_offset);
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) {
 #pragma unroll
-            for (int pr = 0; pr < 2; ++pr) {
-                // amplitude r = 8 rb + 2 h + pr: bit 0 = pr, bits 1-2 = h, bits 3.. = rb
-                uint64_t o = pr ? bitv[0] : 0ull;
-                o |= (h & 1) ? bitv[1] : 0ull;
-                o |= (h & 2) ? bitv[2] : 0ull;
+            for (int v = 0; v < 4; ++v) {
+                // amplitude r = 16 rb + 4 h + v: bits 0-1 = v, bits 2-3 = h, bits 4.. = rb
+                uint64_t o = (v & 1) ? bitv[0] : 0ull;
+                o |= (v & 2) ? bitv[1] : 0ull;
+                o |= (h & 1) ? bitv[2] : 0ull;
+                o |= (h & 2) ? bitv[3] : 0ull;
 #pragma unroll
-                for (int t = 3; t < K; ++t)
-                    if ((rb >> (t - 3)) & 1) o |= bitv[t];
-                float re = acc[rb][2 * pr], im = acc[rb][2 * pr + 1];
+                for (int t = 4; t < K; ++t)
+                    if ((rb >> (t - 4)) & 1) o |= bitv[t];
+                const float p1 = acc[0][rb][v], p2 = acc[1][rb][v], p3 = acc[2][rb][v];
+                float re = p1 - p2, im = p3 - p1 - p2;
                 if (FOLD) {
                     const float2 ph = ((const float2*)a.ftab)[fb | fold_index(a, o)];
                     const float tr = re * ph.x - im * ph.y;
                     im = re * ph.y + im * ph.x;
                     re = tr;
                 }
-                psi[base + o] = float2{re, im};
+                if (STAGED) Xs[(16 * rb + 4 * h + v) * 17 + j] = float2{re, im};
+                else psi[base + o] = float2{re, im};
             }
+        }
+        if (STAGED) {
+            __builtin_amdgcn_wave_barrier();
+            const uint64_t b0 = group_base<K>(a, tile * 16);
+#pragma unroll
+            for (int i = 0; i < NE; ++i) psi[b0 + addr_lane + a.st_addr_i[i]] = Xs[slot_lane + a.st_slot_i[i]];
+            __builtin_amdgcn_wave_barrier();
         }
     }
 }

@@ -40,6 +40,15 @@ struct Sweep {
     int k;
     int fold_m;
     int fold_pos[kMaxDiag];
+    // matrix-core sweeps staged through LDS in address order (targets among
+    // the lowest four positions): element e = 64 i + lane of a 16-group tile
+    // sits at tile base + st_addr_bit(lane bits) + st_addr_i[i] and goes to
+    // LDS slot st_slot_bit(lane bits) + st_slot_i[i] (slot = group + 17 amp)
+    int staged;
+    uint64_t st_addr_bit[6];
+    uint64_t st_addr_i[16];
+    int st_slot_bit[6];
+    int st_slot_i[16];
 };
 
 // Fill a Sweep for positions pos[0..k) over 2^nloc amplitudes.
@@ -76,8 +85,8 @@ hipError_t launch_dense_mfma(hipStream_t st, void* psi, int nloc, int k, const i
 // from mfma_batch_blocks.
 hipError_t launch_dense_batch(hipStream_t st, int dtype, int k, bool fold, const Sweep* d_items,
                               int nitems, uint64_t total_blocks);
-hipError_t launch_dense_mfma_batch(hipStream_t st, int k, bool fold, const Sweep* d_items, int nitems,
-                                   uint64_t total_blocks);
+hipError_t launch_dense_mfma_batch(hipStream_t st, int k, bool fold, bool staged, const Sweep* d_items,
+                                   int nitems, uint64_t total_blocks);
 uint64_t mfma_batch_blocks(uint64_t groups);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].

@@ -106,18 +106,24 @@ hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, boo
 // fused dense block (VALU form; the body is dense_group in sv_device.h)
 // ---------------------------------------------------------------------------
 template <typename R, int K, bool FOLD>
-__global__ __launch_bounds__(256) void k_dense(Sweep a)
+__global__ __launch_bounds__(256) void k_dense(typename Vec2<R>::T* __restrict__ psi,
+                                               const typename Vec2<R>::T* __restrict__ mat, Sweep a)
 {
     const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
     for (uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; g < a.groups; g += stride)
-        dense_group<R, K, FOLD>(a, g);
+        dense_group<R, K, FOLD>(psi, mat, a, g);
 }
 
 // Batched: workgroup b serves sweep i with items[i].block0 <= b < items[i+1].block0,
-// one group per lane.
+// one group per lane.  The sweep's matrix is staged in LDS once per
+// workgroup and its wave-uniform rows are read from there (the pointers in
+// the descriptor table are generic, which rules out scalar global loads).
 template <typename R, int K, bool FOLD>
 __global__ __launch_bounds__(256) void k_dense_batch(const Sweep* __restrict__ items, int nitems)
 {
+    using V = typename Vec2<R>::T;
+    constexpr int D = 1 << K;
+    __shared__ V Ms[D * D];
     int lo = 0, hi = nitems - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
@@ -125,8 +131,11 @@ __global__ __launch_bounds__(256) void k_dense_batch(const Sweep* __restrict__ i
         else hi = mid - 1;
     }
     const Sweep& a = items[lo];
+    const V* __restrict__ mat = (const V*)a.mat;
+    for (int i = threadIdx.x; i < D * D; i += blockDim.x) Ms[i] = mat[i];
+    __syncthreads();
     const uint64_t g = ((uint64_t)blockIdx.x - a.block0) * blockDim.x + threadIdx.x;
-    if (g < a.groups) dense_group<R, K, FOLD>(a, g);
+    if (g < a.groups) dense_group<R, K, FOLD>((V*)a.psi, (const V*)Ms, a, g);
 }
 
 Sweep make_sweep(void* psi, int nloc, int k, const int* pos, const void* mat, const DiagSpec* fold,
@@ -151,15 +160,58 @@ Sweep make_sweep(void* psi, int nloc, int k, const int* pos, const void* mat, co
         a.fold_m = fold->m;
         for (int j = 0; j < fold->m; ++j) a.fold_pos[j] = fold->pos[j];
     }
+    // staged matrix-core loads when a target sits in the lowest four positions
+    // (k = 4, 5 and at least 16 groups): address order over the tile's
+    // involved positions = the four group positions below + the targets
+    a.staged = (k >= 4 && k <= 5 && nloc >= k + 4 && sp[0] < 4) ? 1 : 0;
+    if (a.staged) {
+        int jpos[4], nj = 0;
+        for (int p = 0; p < 64 && nj < 4; ++p) {
+            bool tgt = false;
+            for (int j = 0; j < k; ++j) tgt = tgt || (pos[j] == p);
+            if (!tgt) jpos[nj++] = p;
+        }
+        int inv[kMaxDense + 4], nv = 0;          // involved positions, ascending
+        for (int p = 0; p < 64 && nv < k + 4; ++p) {
+            bool in = false;
+            for (int q = 0; q < 4; ++q) in = in || (jpos[q] == p);
+            for (int j = 0; j < k; ++j) in = in || (pos[j] == p);
+            if (in) inv[nv++] = p;
+        }
+        int slot_of[kMaxDense + 4];
+        for (int b = 0; b < nv; ++b) {
+            slot_of[b] = 0;
+            for (int q = 0; q < 4; ++q)
+                if (jpos[q] == inv[b]) slot_of[b] = 1 << q;          // group bit q
+            for (int j = 0; j < k; ++j)
+                if (pos[j] == inv[b]) slot_of[b] = 17 * (1 << j);    // amplitude bit j
+        }
+        for (int b = 0; b < 6; ++b) {
+            a.st_addr_bit[b] = 1ull << inv[b];
+            a.st_slot_bit[b] = slot_of[b];
+        }
+        for (int i = 0; i < (1 << (k - 2)); ++i) {
+            uint64_t ad = 0;
+            int sl = 0;
+            for (int b = 6; b < nv; ++b)
+                if ((i >> (b - 6)) & 1) {
+                    ad |= 1ull << inv[b];
+                    sl += slot_of[b];
+                }
+            a.st_addr_i[i] = ad;
+            a.st_slot_i[i] = sl;
+        }
+    }
     return a;
 }
 
 template <typename R, int K>
 static hipError_t dense_dispatch(hipStream_t st, const Sweep& a)
 {
+    using V = typename Vec2<R>::T;
     const dim3 grid(grid_for(a.groups, 256)), block(256);
-    if (a.ftab) hipLaunchKernelGGL((k_dense<R, K, true>), grid, block, 0, st, a);
-    else hipLaunchKernelGGL((k_dense<R, K, false>), grid, block, 0, st, a);
+    if (a.ftab) hipLaunchKernelGGL((k_dense<R, K, true>), grid, block, 0, st, (V*)a.psi, (const V*)a.mat, a);
+    else hipLaunchKernelGGL((k_dense<R, K, false>), grid, block, 0, st, (V*)a.psi, (const V*)a.mat, a);
     return hipGetLastError();
 }
 

@@ -57,8 +57,11 @@ def test_dense_single_op(dtype, qs, mfma):
     (mfma=4, used for k >= 4 with complex64) kernels."""
     if dtype == "c128" and len(qs) > 5:
         pytest.skip("complex128 blocks stop at k=5")
-    if mfma and (dtype == "c128" or len(qs) < 4):
-        pytest.skip("matrix-core kernel covers complex64, k >= 4")
+    if mfma and dtype == "c128":
+        pytest.skip("matrix-core kernel covers complex64")
+    # complex64 with mfma=4: k >= 4 runs on the matrix cores (staged through
+    # LDS when a target is below position 4); k < 4 blocks with a target
+    # below position 4 are widened to k = 4 and take the staged path too
     n = 14
     rng = np.random.default_rng(len(qs) * 100 + qs[0])
     psi = W.random_state(n, rng)
