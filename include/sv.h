@@ -179,15 +179,19 @@ enum {
     SV_OPT_MFMA = 2,       /* smallest k (4..6) whose complex64 blocks run on the matrix
                               cores (default 4); 0 or > 6: never */
     SV_OPT_FOLD_DIAG = 3,  /* 1 (default): fold a diagonal op into the preceding dense sweep */
-    SV_OPT_SLOTS = 4       /* tier: number of device slice slots (>= 2) */
+    SV_OPT_SLOTS = 4,      /* tier: number of device slice slots (>= 2) */
+    SV_OPT_STAGE = 5       /* widest LDS tile (9..12 positions, default 12) for running a
+                              run of consecutive 4/5-qubit complex64 blocks in one pass
+                              over HBM; 0: one pass per block */
 };
 int sv_set_option(sv_handle h, int option, int64_t value);
 
 /*
- * sv_counters -- work done since creation: [0] dense sweeps, [1] diagonal
- * sweeps, [2] permute sweeps, [3] amplitudes touched by sweeps, [4] bytes
- * staged host->device, [5] bytes staged device->host, [6] slices skipped
- * because they are known to be zero.
+ * sv_counters -- work done since creation: [0] dense sweeps (HBM passes),
+ * [1] diagonal sweeps, [2] permute sweeps, [3] amplitudes touched by sweeps,
+ * [4] bytes staged host->device, [5] bytes staged device->host, [6] slices
+ * skipped because they are known to be zero, [7] blocks applied in staged
+ * multi-block passes.
  * sv_sweep_time -- with SV_OPT_TIMING: total milliseconds and count of timed
  * dense sweeps (HIP events on the handle's stream), reset by the call.
  */

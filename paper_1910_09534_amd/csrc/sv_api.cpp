@@ -133,6 +133,9 @@ int collect_timing(sv_state* h)
 }
 
 // ---- running the queue over one range of amplitudes ----------------------
+// Staged multi-block passes are formed only from blocks below this position.
+constexpr int kStageMaxPos = 20;
+
 // psi: 2^nloc amplitudes whose global index starts at idx_offset.
 int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset)
 {
@@ -140,6 +143,58 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
     const size_t nops = h->ops.size();
     for (size_t i = 0; i < nops; ++i) {
         const Op& op = h->ops[i];
+        // a run of consecutive 4/5-qubit complex64 blocks whose targets fit in
+        // one LDS tile goes through a single staged HBM pass
+        if (op.kind == OP_DENSE && h->dtype == 0 && h->stage_t >= 9 && h->mfma_min_k == 4 &&
+            (op.k == 4 || op.k == 5)) {
+            int ks[8];
+            const int* pp[8];
+            const void* mm[8];
+            bool in[64] = {};
+            for (int p = 0; p < 4; ++p) in[p] = true;
+            int cnt = 0;
+            size_t j = i;
+            while (j < nops && cnt < 8) {
+                const Op& q = h->ops[j];
+                if (q.kind != OP_DENSE || (q.k != 4 && q.k != 5)) break;
+                if (h->fold && j + 1 < nops && h->ops[j + 1].kind == OP_DIAG) break;
+                // a tile spread over widely separated addresses (positions >= 20,
+                // i.e. beyond an 8 MB window) streams worse than separate sweeps
+                int maxp = 0;
+                for (int u = 0; u < q.k; ++u) maxp = std::max(maxp, q.pos[u]);
+                if (maxp >= kStageMaxPos) break;
+                bool in2[64];
+                for (int p = 0; p < 64; ++p) in2[p] = in[p];
+                for (int u = 0; u < q.k; ++u) in2[q.pos[u]] = true;
+                int t = 0;
+                for (int p = 0; p < 64; ++p) t += in2[p];
+                if (t < 9) t = 9;
+                ks[cnt] = q.k;
+                if (t > h->stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
+                for (int p = 0; p < 64; ++p) in[p] = in2[p];
+                pp[cnt] = q.pos;
+                mm[cnt] = dbase + q.off;
+                ++cnt;
+                ++j;
+            }
+            if (cnt >= 2) {
+                hipEvent_t e0 = nullptr, e1 = nullptr;
+                if (h->timing) {
+                    e0 = next_event(h);
+                    e1 = next_event(h);
+                    if (!e0 || !e1) return set_err(h, SV_EDEVICE, "event creation failed");
+                    TRY(h, hipEventRecord(e0, st));
+                }
+                int tused = 0;
+                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, &tused));
+                if (h->timing) TRY(h, hipEventRecord(e1, st));
+                h->counters[0] += 1;
+                h->counters[3] += (int64_t)1 << nloc;
+                h->counters[7] += cnt;
+                i = j - 1;
+                continue;
+            }
+        }
         if (op.kind == OP_DENSE) {
             DiagSpec fold;
             const DiagSpec* fp = nullptr;
@@ -884,6 +939,7 @@ int sv_set_option(sv_handle h, int option, int64_t value)
         case SV_OPT_MFMA: h->mfma_min_k = (int)value; return SV_OK;
         case SV_OPT_FOLD_DIAG: h->fold = value != 0; return SV_OK;
         case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
+        case SV_OPT_STAGE: h->stage_t = (int)value; return SV_OK;
     }
     return set_err(h, SV_EINVAL, "unknown option");
 }

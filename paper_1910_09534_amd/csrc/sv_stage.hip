@@ -1,0 +1,269 @@
+// Staged sweep: several dense blocks applied in one pass over HBM (cache
+// blocking of aggregate gates, as in the appendix's description of 5-qubit
+// aggregate gates built with cache blocking).
+//
+// A stage is a run of consecutive dense blocks (k = 4 or 5, complex64) whose
+// target positions, together with positions 0..3, fit in t <= 12 tile
+// positions P[0] < ... < P[t-1] (P[0..3] = 0..3).  A tile is the 2^t
+// amplitudes whose other bits equal the tile id.  A persistent workgroup
+// (256 lanes) loops over tiles:
+//   1. the tile (held in registers since the previous iteration) is parked
+//      in LDS; the next tile's loads are issued;
+//   2. each block runs on the LDS tile: 16-group units (one per wave at a
+//      time) through the three real products of the matrix-core form
+//      (v_mfma_f32_16x16x4f32, same operand layout as the single sweep),
+//      reading and writing LDS, with a workgroup barrier between blocks;
+//   3. the tile is written back.
+// The blocks' matrices are staged in LDS once per workgroup.  Every
+// workgroup runs the same number of tile iterations, so the barriers are
+// reached uniformly.
+#include "sv_device.h"
+
+namespace sv {
+
+constexpr int kStageMaxOps = 8;
+constexpr int kStageMaxT = 12;
+constexpr int kStageMaxLds = 80 * 1024;     // two workgroups per CU
+
+struct StageK {
+    uint64_t tiles;                          // 2^(nloc - t)
+    uint64_t tile_lowmask[kStageMaxT];       // (1 << P[b]) - 1, ascending (tile-id spreading)
+    uint64_t dep_lane[8];                    // global offset of element bit b (lane bits, b < 8)
+    uint64_t dep_i[16];                      // global offset of element bits 8.. (i = e >> 8)
+    int t;
+    int nops;
+    int op_k[kStageMaxOps];
+    int op_bits[kStageMaxOps][kMaxDense];    // tile-local bit of matrix bit j
+    int op_lowmask_bits[kStageMaxOps][kMaxDense];  // the same bits, ascending
+    int op_aoff[kStageMaxOps];               // float offset of the op's operand matrices in LDS
+    const float2* op_mat[kStageMaxOps];      // row-major complex matrices (device)
+};
+
+// tile-local index -> LDS slot (one pad element per 16)
+__device__ __forceinline__ int lslot(int i) { return i + (i >> 4); }
+
+template <int K>
+__device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __restrict__ As,
+                                            float2* __restrict__ T)
+{
+    using S = MfmaShape<K>;
+    constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int j = lane & 15, h = lane >> 4;
+    int bit[K], low[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        bit[u] = 1 << a.op_bits[o][u];
+        low[u] = (1 << a.op_lowmask_bits[o][u]) - 1;
+    }
+    const int units = 1 << (a.t - K - 4);
+    for (int unit = wave; unit < units; unit += nw) {
+        int base = unit * 16 + j;                      // group index -> tile-local base
+#pragma unroll
+        for (int u = 0; u < K; ++u) {
+            const int lw = base & low[u];
+            base = ((base ^ lw) << 1) | lw;
+        }
+        float2 x[NE];
+#pragma unroll
+        for (int m = 0; m < NE; ++m) {
+            int off = (h & 1) ? bit[0] : 0;
+            off |= (h & 2) ? bit[1] : 0;
+#pragma unroll
+            for (int u = 2; u < K; ++u)
+                if ((m >> (u - 2)) & 1) off |= bit[u];
+            x[m] = T[lslot(base + off)];
+        }
+        f4 acc[3][RB];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[p][rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int sq = 0; sq < KQ; ++sq) {
+            f4 av[3][RB];
+#pragma unroll
+            for (int p = 0; p < 3; ++p)
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) av[p][rb] = As[((p * RB + rb) * KQ + sq) * 64 + lane];
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const float2 xv = x[4 * sq + s4];
+                const float bs = xv.x + xv.y;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][rb][s4], xv.x, acc[0][rb], 0, 0, 0);
+                    acc[1][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][rb][s4], xv.y, acc[1][rb], 0, 0, 0);
+                    acc[2][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][rb][s4], bs, acc[2][rb], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                // amplitude r = 16 rb + 4 h + v
+                int off = (v & 1) ? bit[0] : 0;
+                off |= (v & 2) ? bit[1] : 0;
+                off |= (h & 1) ? bit[2] : 0;
+                off |= (h & 2) ? bit[3] : 0;
+#pragma unroll
+                for (int u = 4; u < K; ++u)
+                    if ((rb >> (u - 4)) & 1) off |= bit[u];
+                const float p1 = acc[0][rb][v], p2 = acc[1][rb][v], p3 = acc[2][rb][v];
+                T[lslot(base + off)] = float2{p1 - p2, p3 - p1 - p2};
+            }
+        }
+    }
+}
+
+__global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK a)
+{
+    extern __shared__ f4 smem[];
+    float2* T = (float2*)smem;                                   // tile, padded
+    const int tsz = 1 << a.t;
+    f4* Abase = smem + ((lslot(tsz) * 8 + 15) / 16);              // operand matrices
+    // stage every block's three real matrices in operand order
+    for (int o = 0; o < a.nops; ++o) {
+        const int k = a.op_k[o];
+        const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 3 * RB * KQ * 256;
+        float* dst = (float*)(Abase) + a.op_aoff[o];
+        const float2* mat = a.op_mat[o];
+        for (int i = threadIdx.x; i < NA; i += blockDim.x) {
+            const int s4 = i & 3, l = (i >> 2) & 63, blk = i >> 8;
+            const int sq = blk % KQ, rb = (blk / KQ) % RB, p = blk / (KQ * RB);
+            const int R = 16 * rb + (l & 15);
+            const int C = 4 * (4 * sq + s4) + (l >> 4);
+            const float2 m = mat[R * D + C];
+            dst[i] = p == 0 ? m.x : (p == 1 ? m.y : m.x + m.y);
+        }
+    }
+    const int per = tsz / 256;                                   // elements per lane (<= 16)
+    uint64_t dl = 0;
+    for (int b = 0; b < 8; ++b)
+        if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
+    auto tile_base = [&](uint64_t tile) {
+        uint64_t base = tile;
+        for (int b = 0; b < a.t; ++b) {
+            const uint64_t lw = base & a.tile_lowmask[b];
+            base = ((base ^ lw) << 1) | lw;
+        }
+        return base;
+    };
+    // statically indexed (a runtime trip count would put xr in scratch)
+    float2 xr[16];
+    uint64_t tile = blockIdx.x;
+    if (tile < a.tiles) {
+        const uint64_t b0 = tile_base(tile) + dl;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < per) xr[i] = psi[b0 + a.dep_i[i]];
+    }
+    __syncthreads();
+    for (; tile < a.tiles; tile += gridDim.x) {
+        const uint64_t b0 = tile_base(tile) + dl;
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < per) T[lslot(threadIdx.x + 256 * i)] = xr[i];
+        __syncthreads();
+        const uint64_t nt = tile + gridDim.x;
+        if (nt < a.tiles) {
+            const uint64_t nb = tile_base(nt) + dl;
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (i < per) xr[i] = psi[nb + a.dep_i[i]];
+        }
+        for (int o = 0; o < a.nops; ++o) {
+            const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
+            if (a.op_k[o] == 5) stage_block<5>(a, o, As, T);
+            else stage_block<4>(a, o, As, T);
+            __syncthreads();
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (i < per) psi[b0 + a.dep_i[i]] = T[lslot(threadIdx.x + 256 * i)];
+        __syncthreads();
+    }
+}
+
+int stage_lds_bytes(int t, int nops, const int* ks)
+{
+    int floats = 0;
+    for (int o = 0; o < nops; ++o) floats += 3 * (1 << (2 * ks[o]));
+    const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16 + 1;
+    return tile_f4 * 16 + floats * 4;
+}
+
+hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
+                        const void* const* mats, int* t_out)
+{
+    if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
+    // tile positions: 0..3 plus every target, ascending
+    bool in[64] = {};
+    for (int p = 0; p < 4; ++p) in[p] = true;
+    for (int o = 0; o < nops; ++o) {
+        if (ks[o] < 4 || ks[o] > 5) return hipErrorInvalidValue;
+        for (int j = 0; j < ks[o]; ++j) in[pos[o][j]] = true;
+    }
+    int cnt = 0;
+    for (int p = 0; p < 64; ++p) cnt += in[p];
+    // at least 9 tile positions (a 16-group unit of a 5-qubit block, 256 lanes x 2)
+    for (int p = 0; p < nloc && cnt < 9; ++p)
+        if (!in[p]) { in[p] = true; ++cnt; }
+    int P[64], t = 0;
+    for (int p = 0; p < 64; ++p)
+        if (in[p]) P[t++] = p;
+    if (t > kStageMaxT || t < 9 || nloc < t) return hipErrorInvalidValue;
+    StageK a{};
+    a.t = t;
+    a.nops = nops;
+    a.tiles = 1ull << (nloc - t);
+    for (int b = 0; b < t; ++b) a.tile_lowmask[b] = (1ull << P[b]) - 1;
+    for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
+    for (int i = 0; i < (1 << (t - 8)); ++i) {
+        uint64_t d = 0;
+        for (int b = 8; b < t; ++b)
+            if ((i >> (b - 8)) & 1) d |= 1ull << P[b];
+        a.dep_i[i] = d;
+    }
+    int aoff = 0;
+    for (int o = 0; o < nops; ++o) {
+        a.op_k[o] = ks[o];
+        a.op_mat[o] = (const float2*)mats[o];
+        a.op_aoff[o] = aoff;
+        aoff += 3 * (1 << (2 * ks[o]));
+        int lb[kMaxDense];
+        for (int j = 0; j < ks[o]; ++j) {
+            int b = 0;
+            while (P[b] != pos[o][j]) ++b;
+            a.op_bits[o][j] = b;
+            lb[j] = b;
+        }
+        for (int j = 1; j < ks[o]; ++j)
+            for (int l = j; l > 0 && lb[l - 1] > lb[l]; --l) {
+                const int tmp = lb[l]; lb[l] = lb[l - 1]; lb[l - 1] = tmp;
+            }
+        for (int j = 0; j < ks[o]; ++j) a.op_lowmask_bits[o][j] = lb[j];
+    }
+    const int lds = stage_lds_bytes(t, nops, ks);
+    if (lds > kStageMaxLds) return hipErrorInvalidValue;
+    static bool attr_set = false;
+    if (!attr_set) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k_stage,
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    // persistent: as many workgroups as are resident (LDS-limited, at most 4 per CU)
+    int per_cu = (160 * 1024) / lds;
+    if (per_cu > 4) per_cu = 4;
+    if (per_cu < 1) per_cu = 1;
+    uint64_t grid = a.tiles;
+    const uint64_t cap = 256ull * per_cu;
+    if (grid > cap) grid = cap;
+    hipLaunchKernelGGL(k_stage, dim3((unsigned)grid), dim3(256), lds, st, (float2*)psi, a);
+    if (t_out) *t_out = t;
+    return hipGetLastError();
+}
+
+}  // namespace sv

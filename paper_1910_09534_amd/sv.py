@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, -2, -3, -4, -5, -6
 SV_C64, SV_C128 = 0, 1
 SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE = 0x100, 0x200, 0x400
-SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS = 1, 2, 3, 4
+SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE = 1, 2, 3, 4, 5
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
@@ -198,7 +198,7 @@ def counters(h) -> dict:
     c = np.zeros(8, dtype=np.int64)
     _check(lib().sv_counters(h, _ptr(c)))
     keys = ("dense_sweeps", "diag_sweeps", "perm_sweeps", "amps_swept", "bytes_h2d", "bytes_d2h",
-            "zero_slices_skipped", "reserved")
+            "zero_slices_skipped", "staged_blocks")
     return dict(zip(keys, (int(x) for x in c)))
 
 

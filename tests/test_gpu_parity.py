@@ -217,3 +217,36 @@ def test_dense_on_sliced_qubit_rejected():
         assert abs(a[0] - 1) == 0 and a[1] == 0
     finally:
         sv.destroy_state(h)
+
+
+@pytest.mark.parametrize("n", [12, 14, 18])
+def test_staged_multiblock_pass(n):
+    """Runs of 4/5-qubit blocks sharing an LDS tile go through one staged HBM
+    pass; the result equals one pass per block and the oracle."""
+    rng = np.random.default_rng(n)
+    psi = W.random_state(n, rng)
+    ops = []
+    for _ in range(12):
+        k = int(rng.choice([2, 4, 5]))
+        pool = list(range(min(n, 9)))          # overlapping sets: consecutive blocks share a tile
+        qs = [int(x) for x in rng.choice(pool, size=k, replace=False)]
+        ops.append((qs, W.random_unitary(1 << k, rng)))
+    outs = {}
+    for stage in (12, 0):
+        h, t = state_from_numpy(psi, "c64")
+        try:
+            sv.set_option(h, sv.SV_OPT_STAGE, stage)
+            for qs, u in ops:
+                sv.apply_fused(h, qs, u, "c64")
+            outs[stage] = read_all(h, n)
+            cnt = sv.counters(h)
+        finally:
+            sv.destroy_state(h)
+        if stage:
+            assert cnt["staged_blocks"] >= 2, "no staged pass was formed"
+    ref = psi.copy()
+    for qs, u in ops:
+        orc.apply_dense(ref, qs, u)
+    assert orc.rel_l2(outs[12], ref) <= 1e-5
+    assert orc.rel_l2(outs[0], ref) <= 1e-5
+    assert orc.rel_l2(outs[12], outs[0]) <= 1e-6
