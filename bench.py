@@ -256,11 +256,18 @@ def bench_sliced(args) -> int:
           flush=True)
     sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
 
-    def run(s):
-        for ph in s.phases:
-            sv.permute_qubits(st.h, ph.order)
+    def run(s, label=""):
+        t_start = time.perf_counter()
+        for i, ph in enumerate(s.phases):
+            sv.permute_qubits(st.h, ph.order)      # returns once the previous phase's pass is done
+            if i:
+                print(f"# {label}phase {i} done at {time.perf_counter() - t_start:.1f} s", file=sys.stderr,
+                      flush=True)
             planner.enqueue(st.h, ph.ops, sv.SV_C64)
-        return sv.reduce_slices(st.h, bits, s.trailing)
+        out = sv.reduce_slices(st.h, bits, s.trailing)
+        print(f"# {label}last phase + reduction done at {time.perf_counter() - t_start:.1f} s",
+              file=sys.stderr, flush=True)
+        return out
 
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -276,11 +283,12 @@ def bench_sliced(args) -> int:
         "unit": "amp-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * t, 1),
         "higher_is_better": True, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"{n}-qubit ABCDCDAB depth {depth}, complex64, 4 sliced qubits "
-                               f"(16 slices of 2^{n - 4}), pinned host tier, 2^20 bitstrings",
+                               f"(16 slices of 2^{n - 4}) in a host-memory tier, 2^20 bitstrings",
                    "n": n, "gates": gates, "slice_sets": [list(A), list(B)],
                    "phases": len(sched.phases), "sweeps_per_slice": sum(len(p_.ops) for p_ in sched.phases),
                    "trailing_gates": len(sched.trailing_gate_ids)},
         "host_link_GBps": round((cnt["bytes_h2d"] + cnt["bytes_d2h"]) / t / 1e9, 2),
+        "tier": "pinned" if (1 << n) * 8 <= (48 << 30) else "pageable + pinned bounce buffers",
         "bytes_h2d": cnt["bytes_h2d"], "bytes_d2h": cnt["bytes_d2h"],
         "zero_slices_skipped": cnt["zero_slices_skipped"],
         "dense_sweep_ms_total": round(sweep_ms, 1), "dense_sweeps": nswept,
@@ -294,6 +302,7 @@ def bench_sliced(args) -> int:
         ms = planner.phase_schedule(mirror, A, B, args.kmax)
         mb = np.concatenate([np.zeros(1, np.uint64), bits[:4095]])
         ma, _ = run_pins(st, ms, mb, planner, sv)
+        print("# mirror pin done", file=sys.stderr, flush=True)
         line["mirror_abs_amp0"] = float(abs(ma[0]))
         line["mirror_max_other"] = float(np.abs(ma[1:]).max())
     st.close()

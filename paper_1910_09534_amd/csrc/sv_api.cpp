@@ -13,7 +13,9 @@
 #include <sys/mman.h>
 
 #include <algorithm>
+#include <deque>
 #include <new>
+#include <thread>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -291,7 +293,7 @@ int stage_out(sv_state* h, hipStream_t st, uint64_t t, const void* slot)
 // over the device slots.  visit (optional) runs on the compute stream after
 // the ops of each slice, with the slice's buffer.
 template <typename F>
-int tier_pass(sv_state* h, bool write_back, F&& visit)
+int tier_pass_pinned(sv_state* h, bool write_back, F&& visit)
 {
     const int ns = 1 << h->s;
     const int R = (int)h->slots.size();
@@ -335,6 +337,243 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
     TRY(h, hipStreamSynchronize(h->stream));
     TRY(h, hipStreamSynchronize(h->s_out));
     return SV_OK;
+}
+
+// ---- pageable tier: pinned bounce buffers -----------------------------------
+// Pageable files cannot be the source or target of asynchronous DMA, so
+// every chunk (<= kChunk bytes) goes through a pinned bounce buffer: host
+// threads copy file <-> bounce, the copy streams move bounce <-> slot.  One
+// host thread drives both directions chunk by chunk, so the host-to-device
+// and device-to-host links and the host copies overlap with each other and
+// with the kernels of the slice in between.
+constexpr size_t kChunk = (size_t)64 << 20;
+constexpr int kBounce = 4;
+constexpr int kCopyThreads = 8;
+
+void par_memcpy(void* dst, const void* src, size_t bytes)
+{
+    if (bytes < ((size_t)4 << 20)) {
+        std::memcpy(dst, src, bytes);
+        return;
+    }
+    std::thread th[kCopyThreads];
+    const size_t part = (bytes / kCopyThreads + 4095) & ~(size_t)4095;
+    for (int i = 0; i < kCopyThreads; ++i) {
+        const size_t lo = std::min(bytes, part * i), hi = std::min(bytes, part * (i + 1));
+        th[i] = std::thread([=] { if (hi > lo) std::memcpy((char*)dst + lo, (const char*)src + lo, hi - lo); });
+    }
+    for (auto& t : th) t.join();
+}
+
+struct OutChunk {
+    const char* src;   // device
+    char* dst;         // pageable file memory
+    size_t bytes;
+    int slice_idx;
+    int slot;          // device slot the slice occupies
+    bool last;         // last chunk of its slice: releases the slot
+};
+
+struct BouncePipe {
+    sv_state* h;
+    void* bin[kBounce] = {};
+    void* bout[kBounce] = {};
+    hipEvent_t ev_bin[kBounce] = {}, ev_bout[kBounce] = {};
+    int next_in = 0;
+    std::deque<OutChunk> pending;                    // not issued yet
+    std::deque<std::pair<int, OutChunk>> inflight;   // (bounce index, chunk) issued D2H
+    int free_out[kBounce];
+    int nfree_out = 0;
+    int err = SV_OK;
+
+    int init()
+    {
+        for (int b = 0; b < kBounce; ++b) {
+            size_t got = 0;
+            bin[b] = pool_alloc(kChunk, true, &got);
+            bout[b] = pool_alloc(kChunk, true, &got);
+            if (!bin[b] || !bout[b]) return set_err(h, SV_ENOMEM, "pinned bounce buffer allocation failed");
+            TRY(h, hipEventCreateWithFlags(&ev_bin[b], hipEventDisableTiming));
+            TRY(h, hipEventCreateWithFlags(&ev_bout[b], hipEventDisableTiming));
+            TRY(h, hipEventRecord(ev_bin[b], h->s_in));
+            free_out[nfree_out++] = b;
+        }
+        return SV_OK;
+    }
+    ~BouncePipe()
+    {
+        for (int b = 0; b < kBounce; ++b) {
+            if (ev_bin[b]) { (void)hipEventSynchronize(ev_bin[b]); (void)hipEventDestroy(ev_bin[b]); }
+            if (ev_bout[b]) { (void)hipEventSynchronize(ev_bout[b]); (void)hipEventDestroy(ev_bout[b]); }
+            pool_free(bin[b], kChunk, true);
+            pool_free(bout[b], kChunk, true);
+        }
+    }
+    // finish the oldest issued D2H chunk: wait for it, copy bounce -> file
+    int complete_one()
+    {
+        auto [b, c] = inflight.front();
+        inflight.pop_front();
+        TRY_IO(h, hipEventSynchronize(ev_bout[b]));
+        par_memcpy(c.dst, bout[b], c.bytes);
+        free_out[nfree_out++] = b;
+        return SV_OK;
+    }
+    // issue D2H chunks while bounce buffers are free; finish chunks whose
+    // copy is done (blocking only when `block` and nothing can be issued)
+    int pump(bool block)
+    {
+        for (;;) {
+            while (!pending.empty() && nfree_out > 0) {
+                const OutChunk c = pending.front();
+                pending.pop_front();
+                const int b = free_out[--nfree_out];
+                TRY_IO(h, hipMemcpyAsync(bout[b], c.src, c.bytes, hipMemcpyDeviceToHost, h->s_out));
+                TRY_IO(h, hipEventRecord(ev_bout[b], h->s_out));
+                if (c.last) TRY_IO(h, hipEventRecord(h->ev_out[c.slot], h->s_out));
+                inflight.emplace_back(b, c);
+                h->counters[5] += (int64_t)c.bytes;
+            }
+            bool progressed = false;
+            while (!inflight.empty() && hipEventQuery(ev_bout[inflight.front().first]) == hipSuccess) {
+                int rc = complete_one();
+                if (rc) return rc;
+                progressed = true;
+            }
+            if (!block || (pending.empty() && inflight.empty())) return SV_OK;
+            if (!progressed) {
+                int rc = complete_one();
+                if (rc) return rc;
+            }
+        }
+    }
+    // every out-chunk of slices <= idx issued and finished
+    int drain_upto(int idx)
+    {
+        for (;;) {
+            bool any = false;
+            for (const auto& c : pending) any = any || c.slice_idx <= idx;
+            for (const auto& c : inflight) any = any || c.second.slice_idx <= idx;
+            if (!any) return SV_OK;
+            int rc = pump(false);
+            if (rc) return rc;
+            if (!inflight.empty()) {
+                rc = complete_one();
+                if (rc) return rc;
+            }
+        }
+    }
+    // stage a slice in: file chunk -> bounce (host) -> slot (s_in); out-chunks
+    // are pumped between chunks so both directions stay busy
+    int stage_in(uint64_t t, void* slot)
+    {
+        const size_t fb = file_amps(h) * h->amp;
+        const int nf = 1 << h->s;
+        for (int u = 0; u < nf; ++u)
+            for (size_t off = 0; off < fb; off += kChunk) {
+                const size_t n = std::min(kChunk, fb - off);
+                const int b = next_in;
+                next_in = (next_in + 1) % kBounce;
+                TRY_IO(h, hipEventSynchronize(ev_bin[b]));
+                par_memcpy(bin[b], (const char*)h->files[t * nf + u] + off, n);
+                TRY_IO(h, hipMemcpyAsync((char*)slot + (size_t)u * fb + off, bin[b], n,
+                                         hipMemcpyHostToDevice, h->s_in));
+                TRY_IO(h, hipEventRecord(ev_bin[b], h->s_in));
+                h->counters[4] += (int64_t)n;
+                int rc = pump(false);
+                if (rc) return rc;
+            }
+        return SV_OK;
+    }
+    void queue_out(uint64_t t, const void* slot, int idx, int k)
+    {
+        const size_t fb = file_amps(h) * h->amp;
+        const int nf = 1 << h->s;
+        for (int u = 0; u < nf; ++u)
+            for (size_t off = 0; off < fb; off += kChunk)
+                pending.push_back({(const char*)slot + (size_t)u * fb + off,
+                                   (char*)h->files[t * nf + u] + off, std::min(kChunk, fb - off), idx, k,
+                                   u == nf - 1 && off + kChunk >= fb});
+    }
+};
+
+template <typename F>
+int tier_pass_pageable(sv_state* h, bool write_back, F&& visit)
+{
+    const int ns = 1 << h->s;
+    const int R = (int)h->slots.size();
+    std::vector<int> act;
+    for (int t = 0; t < ns; ++t) {
+        if (h->slice_zero[t]) h->counters[6] += 1;
+        else act.push_back(t);
+    }
+    BouncePipe bp;
+    bp.h = h;
+    int rc = bp.init();
+    if (rc) return rc;
+    const int N = (int)act.size();
+    auto slot_of = [&](int idx) { return idx % R; };
+    // stage-in of idx into its slot, after the slot's previous slice left it
+    auto prefetch = [&](int idx) -> int {
+        const int k = slot_of(idx);
+        if (idx >= R) {
+            int r = bp.drain_upto(idx - R);
+            if (r) return r;
+            TRY(h, hipStreamWaitEvent(h->s_in, h->ev_out[k], 0));
+            TRY(h, hipStreamWaitEvent(h->s_in, h->ev_comp[k], 0));
+        }
+        int r = bp.stage_in((uint64_t)act[idx], h->slots[k]);
+        if (r) return r;
+        TRY(h, hipEventRecord(h->ev_in[k], h->s_in));
+        return SV_OK;
+    };
+    if (N > 0) {
+        rc = prefetch(0);
+        if (rc) return rc;
+    }
+    for (int idx = 0; idx < N; ++idx) {
+        const int k = slot_of(idx);
+        const int t = act[idx];
+        void* slot = h->slots[k];
+        TRY(h, hipStreamWaitEvent(h->stream, h->ev_in[k], 0));
+        void* cur = slot;
+        rc = run_ops(h, h->stream, &cur, h->pslot, h->L, (uint64_t)t << h->L);
+        if (rc) return rc;
+        if (cur != slot) {
+            h->slots[k] = cur;
+            h->pslot = slot;
+            slot = cur;
+        }
+        rc = visit(t, slot);
+        if (rc) return rc;
+        TRY(h, hipEventRecord(h->ev_comp[k], h->stream));
+        if (write_back) {
+            TRY(h, hipStreamWaitEvent(h->s_out, h->ev_comp[k], 0));
+            bp.queue_out((uint64_t)t, slot, idx, k);      // its last chunk records ev_out[k]
+        }
+        // the next slice streams in while this one computes and earlier ones
+        // stream out; a slot is reused only after its slice left it (prefetch
+        // drains that slice's chunks first)
+        if (idx + 1 < N) {
+            rc = prefetch(idx + 1);
+            if (rc) return rc;
+        }
+        rc = bp.pump(false);
+        if (rc) return rc;
+    }
+    rc = bp.pump(true);
+    if (rc) return rc;
+    TRY(h, hipStreamSynchronize(h->s_in));
+    TRY(h, hipStreamSynchronize(h->stream));
+    TRY(h, hipStreamSynchronize(h->s_out));
+    return SV_OK;
+}
+
+template <typename F>
+int tier_pass(sv_state* h, bool write_back, F&& visit)
+{
+    if (h->pinned_tier) return tier_pass_pinned(h, write_back, std::forward<F>(visit));
+    return tier_pass_pageable(h, write_back, std::forward<F>(visit));
 }
 
 int flush(sv_state* h)
@@ -492,6 +731,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
                     release(h);
                     return set_err(nullptr, SV_ENOMEM, "host tier allocation failed");
                 }
+                (void)madvise(p, fb, MADV_HUGEPAGE);     // fewer first-touch faults
                 f = p;
             }
         }
