@@ -264,12 +264,26 @@ int upload_arena(sv_state* h)
 // ---- tier staging ------------------------------------------------------------
 size_t file_amps(const sv_state* h) { return (size_t)1 << (h->L - h->s); }
 
+// failure injection: true when this transfer must fail (see SV_OPT_FAIL_IO)
+bool injected_io_failure(sv_state* h)
+{
+    if (h->fail_io_at <= 0) return false;
+    return --h->fail_io_at == 0;
+}
+
+#define CHECK_INJECTED_IO(h)                                                         \
+    do {                                                                             \
+        if (injected_io_failure(h))                                                  \
+            return fail_dev((h), "host-tier transfer (injected failure)", hipErrorUnknown, SV_EIO); \
+    } while (0)
+
 int stage_in(sv_state* h, hipStream_t st, uint64_t t, void* slot)
 {
     const size_t fa = file_amps(h), fb = fa * h->amp;
     const int nf = 1 << h->s;
     for (int u = 0; u < nf; ++u) {
         char* dst = (char*)slot + (size_t)u * fb;
+        CHECK_INJECTED_IO(h);
         TRY_IO(h, hipMemcpyAsync(dst, h->files[t * nf + u], fb, hipMemcpyHostToDevice, st));
         h->counters[4] += (int64_t)fb;
     }
@@ -282,6 +296,7 @@ int stage_out(sv_state* h, hipStream_t st, uint64_t t, const void* slot)
     const int nf = 1 << h->s;
     for (int u = 0; u < nf; ++u) {
         const char* src = (const char*)slot + (size_t)u * fb;
+        CHECK_INJECTED_IO(h);
         TRY_IO(h, hipMemcpyAsync(h->files[t * nf + u], src, fb, hipMemcpyDeviceToHost, st));
         h->counters[5] += (int64_t)fb;
     }
@@ -427,6 +442,7 @@ struct BouncePipe {
             while (!pending.empty() && nfree_out > 0) {
                 const OutChunk c = pending.front();
                 pending.pop_front();
+                CHECK_INJECTED_IO(h);
                 const int b = free_out[--nfree_out];
                 TRY_IO(h, hipMemcpyAsync(bout[b], c.src, c.bytes, hipMemcpyDeviceToHost, h->s_out));
                 TRY_IO(h, hipEventRecord(ev_bout[b], h->s_out));
@@ -475,6 +491,7 @@ struct BouncePipe {
                 const int b = next_in;
                 next_in = (next_in + 1) % kBounce;
                 TRY_IO(h, hipEventSynchronize(ev_bin[b]));
+                CHECK_INJECTED_IO(h);
                 par_memcpy(bin[b], (const char*)h->files[t * nf + u] + off, n);
                 TRY_IO(h, hipMemcpyAsync((char*)slot + (size_t)u * fb + off, bin[b], n,
                                          hipMemcpyHostToDevice, h->s_in));
@@ -1180,6 +1197,7 @@ int sv_set_option(sv_handle h, int option, int64_t value)
         case SV_OPT_FOLD_DIAG: h->fold = value != 0; return SV_OK;
         case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
         case SV_OPT_STAGE: h->stage_t = (int)value; return SV_OK;
+        case SV_OPT_FAIL_IO: h->fail_io_at = value; return SV_OK;
     }
     return set_err(h, SV_EINVAL, "unknown option");
 }

@@ -70,7 +70,8 @@ struct sv_state {
     // options and accounting
     bool timing = false, fold = true;
     int mfma_min_k = 4;
-    int stage_t = 12;                     // max tile width of staged multi-block sweeps (0: off)
+    int stage_t = 12;
+    int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;
     size_t tev_used = 0;

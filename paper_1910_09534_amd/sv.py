@@ -18,7 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, -2, -3, -4, -5, -6
 SV_C64, SV_C128 = 0, 1
 SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE = 0x100, 0x200, 0x400
-SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE = 1, 2, 3, 4, 5
+SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}

@@ -136,3 +136,33 @@ def test_mirror_circuit_30q_tier():
     res = runner.simulate_sliced(m, bits, A, B, dtype="c64", kmax=5, tier=True)
     assert abs(abs(res["amps"][0]) - 1) < 1e-4
     assert np.abs(res["amps"][1:]).max() < 1e-4
+
+
+@pytest.mark.parametrize("pageable", [False, True])
+@pytest.mark.parametrize("fail_at", [1, 3, 6])
+def test_injected_transfer_failure_poisons_handle(pageable, fail_at):
+    """A host-tier transfer that fails returns SV_EIO and poisons the handle:
+    every later call returns SV_ESTATE until destroy_state (forced from the
+    host; no kernel faults)."""
+    _gpu()
+    n = 12
+    st = sv.State(n, (1 << 2) | (1 << 7), "c64", tier=True, pageable=pageable)
+    try:
+        u = W.random_unitary(4, np.random.default_rng(2)).astype(np.complex64)
+        st.fused([0, 1], u)
+        st.sync()                                   # slice 0 only
+        assert st.order() == [0, 1, 3, 4, 5, 6, 8, 9, 10, 11, 2, 7]
+        sv.set_option(st.h, sv.SV_OPT_FAIL_IO, fail_at)
+        st.fused([3, 4], u)
+        with pytest.raises(sv.SVError) as e:
+            st.permute([2, 7, 0, 1, 3, 4, 5, 6, 8, 9, 10, 11])   # flushes: transfers happen
+            st.sync()
+        assert e.value.code == sv.SV_EIO
+        with pytest.raises(sv.SVError) as e2:
+            st.gather(np.arange(4, dtype=np.uint64))
+        assert e2.value.code == sv.SV_ESTATE
+        with pytest.raises(sv.SVError) as e3:
+            st.fused([3, 4], u)
+        assert e3.value.code == sv.SV_ESTATE
+    finally:
+        st.close()                                   # destroy accepts a poisoned handle

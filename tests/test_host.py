@@ -110,3 +110,67 @@ def test_library_exports_every_declared_symbol():
         assert hasattr(lib, n), f"libsv.so does not export {n}"
     from paper_1910_09534_amd import sv
     assert set(sv.EXPORTS) == set(names)
+
+
+@pytest.mark.parametrize("n,depth", [(16, 14), (20, 12)])
+def test_phase_schedule_is_a_reassociation(n, depth):
+    """Applying each phase's gates in phase order, then the trailing operator
+    on the last sliced set, gives the sequential circuit's state (Sec. 4: the
+    subcircuits are a re-association of the same product of gates)."""
+    from paper_1910_09534_amd import runner
+    c = W.sycamore_circuit(n, depth, seed=77 + n)
+    A, B = runner.grid_slice_sets(n)
+    sp = planner.phase_schedule(c, A, B, kmax=5)
+    ids = [i for ph in sp.phases for i in ph.gate_ids] + list(sp.trailing_gate_ids)
+    assert sorted(ids) == list(range(len(c.gates)))
+    for ph in sp.phases:
+        assert not any(set(c.gates[i].qubits) & set(ph.sliced) for i in ph.gate_ids)
+        assert sorted(ph.order) == list(range(n))
+        assert ph.order[-len(ph.sliced):] == sorted(ph.sliced)
+    # consecutive phases alternate between the two sets
+    for p, q in zip(sp.phases, sp.phases[1:]):
+        assert {p.sliced, q.sliced} == {tuple(A), tuple(B)}
+    psi = orc.zero_state(n)
+    for ph in sp.phases:
+        psi = orc.apply_gates(psi, [c.gates[i] for i in ph.gate_ids])
+    if sp.trailing is not None:
+        assert set(sp.trailing_qubits) >= {q for i in sp.trailing_gate_ids for q in c.gates[i].qubits}
+        psi = orc.apply_dense(psi, list(sp.trailing_qubits), sp.trailing)
+    ref = orc.simulate(c)
+    assert orc.rel_l2(psi, ref) < 1e-12
+
+
+def test_phase_schedule_order_matters_when_dependent():
+    """Control for the test above: swapping two dependent gates between phases
+    changes the state, so the re-association check can fail."""
+    from paper_1910_09534_amd import runner
+    n = 16
+    c = W.sycamore_circuit(n, 12, seed=91)
+    A, B = runner.grid_slice_sets(n)
+    sp = planner.phase_schedule(c, A, B, kmax=5)
+    first, second = sp.phases[0].gate_ids, sp.phases[1].gate_ids
+    psi = orc.zero_state(n)
+    psi = orc.apply_gates(psi, [c.gates[i] for i in second])
+    psi = orc.apply_gates(psi, [c.gates[i] for i in first])
+    for ph in sp.phases[2:]:
+        psi = orc.apply_gates(psi, [c.gates[i] for i in ph.gate_ids])
+    if sp.trailing is not None:
+        psi = orc.apply_dense(psi, list(sp.trailing_qubits), sp.trailing)
+    assert orc.rel_l2(psi, orc.simulate(c)) > 1e-3
+
+
+def test_sliced_36q_schedule_structure():
+    """The 36-qubit depth-20 sliced workload: every gate is scheduled once,
+    each phase leaves its sliced set untouched, and the four-qubit sets give
+    16 slices per phase."""
+    from paper_1910_09534_amd import runner
+    c = W.config_circuit(3)
+    A, B = runner.grid_slice_sets(c.n)
+    assert len(A) == len(B) == 4
+    sp = planner.phase_schedule(c, A, B, kmax=5)
+    ids = [i for ph in sp.phases for i in ph.gate_ids] + list(sp.trailing_gate_ids)
+    assert sorted(ids) == list(range(len(c.gates)))
+    assert 2 <= len(sp.phases) <= 16
+    for ph in sp.phases:
+        assert not any(set(c.gates[i].qubits) & set(ph.sliced) for i in ph.gate_ids)
+        assert all(max(o.qubits) < c.n and len(o.qubits) <= 5 for o in ph.ops)
