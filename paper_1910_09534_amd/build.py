@@ -4,7 +4,9 @@
 
 Every HIP source is compiled with packed-FP32 instructions disabled
 (-target-feature -packed-fp32-ops): the compiler then emits only scalar FP32
-VALU ops for complex64 arithmetic.
+VALU ops for complex64 arithmetic.  Matrix-core accumulators are kept in
+ordinary VGPRs (-amdgpu-mfma-vgpr-form): the epilogues then read results
+without accumulator-register moves and the kernels need fewer registers.
 """
 from __future__ import annotations
 
@@ -21,6 +23,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-result",
     "-I", os.path.join(ROOT, "include"),
 ]

@@ -135,9 +135,6 @@ int collect_timing(sv_state* h)
 }
 
 // ---- running the queue over one range of amplitudes ----------------------
-// Staged multi-block passes are formed only from blocks below this position.
-constexpr int kStageMaxPos = 20;
-
 // psi: 2^nloc amplitudes whose global index starts at idx_offset.
 int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset)
 {
@@ -160,11 +157,6 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 const Op& q = h->ops[j];
                 if (q.kind != OP_DENSE || (q.k != 4 && q.k != 5)) break;
                 if (h->fold && j + 1 < nops && h->ops[j + 1].kind == OP_DIAG) break;
-                // a tile spread over widely separated addresses (positions >= 20,
-                // i.e. beyond an 8 MB window) streams worse than separate sweeps
-                int maxp = 0;
-                for (int u = 0; u < q.k; ++u) maxp = std::max(maxp, q.pos[u]);
-                if (maxp >= kStageMaxPos) break;
                 bool in2[64];
                 for (int p = 0; p < 64; ++p) in2[p] = in[p];
                 for (int u = 0; u < q.k; ++u) in2[q.pos[u]] = true;
@@ -188,7 +180,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                     TRY(h, hipEventRecord(e0, st));
                 }
                 int tused = 0;
-                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, &tused));
+                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, &tused));
                 if (h->timing) TRY(h, hipEventRecord(e1, st));
                 h->counters[0] += 1;
                 h->counters[3] += (int64_t)1 << nloc;

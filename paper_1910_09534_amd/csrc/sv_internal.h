@@ -91,11 +91,13 @@ uint64_t mfma_batch_blocks(uint64_t groups);
 
 // Staged sweep: nops dense blocks (k = 4 or 5, complex64) applied to LDS
 // tiles in one HBM pass.  pos[o] / mats[o]: block o's positions and device
-// matrix.  Fails (hipErrorInvalidValue) when the tile would exceed 12
-// positions or the LDS budget; *t_out receives the tile width used.
+// matrix.  The tile (positions 0..3 and every target) is widened with free
+// low positions up to t_max (<= 12) within the LDS budget.  Fails
+// (hipErrorInvalidValue) when the targets alone exceed t_max positions or
+// the LDS budget; *t_out receives the tile width used.
 int stage_lds_bytes(int t, int nops, const int* ks);
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int* t_out);
+                        const void* const* mats, int t_max, int* t_out);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
 hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,

@@ -42,13 +42,83 @@ struct StageK {
 // tile-local index -> LDS slot (one pad element per 16)
 __device__ __forceinline__ int lslot(int i) { return i + (i >> 4); }
 
+// Group index -> tile-local index: zero bits inserted at the block's target
+// bits (low[u] = (1 << target_u) - 1, ascending).  The map acts bit by bit,
+// so spread(a | b) = spread(a) | spread(b) for disjoint a, b; likewise
+// lslot(a | b) = lslot(a) + lslot(b), which splits every LDS address into a
+// wave-uniform part (the unit) and per-lane constants of the block.
+template <int K>
+__device__ __forceinline__ int spread(int g, const int (&low)[K])
+{
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        const int lw = g & low[u];
+        g = ((g ^ lw) << 1) | lw;
+    }
+    return g;
+}
+
+// NU (1 or 2) 16-group units of one block on the LDS tile, processed together
+// by the calling wave: their loads are issued together and their 6 NU
+// accumulator chains interleave on the matrix core.  su: LDS slot of each
+// unit's first group (uniform); xa / ya: per-lane slot offsets of the
+// operand elements and of the results.
+template <int K, int NU>
+__device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][MfmaShape<K>::KQ],
+                                            const int (&xa)[MfmaShape<K>::D / 4],
+                                            const int (&ya)[MfmaShape<K>::D / 4], const int (&su)[2],
+                                            float2* __restrict__ T)
+{
+    using S = MfmaShape<K>;
+    constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
+    float2 x[NU][NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m)
+#pragma unroll
+        for (int q = 0; q < NU; ++q) x[q][m] = T[su[q] + xa[m]];
+    f4 acc[NU][3][RB];
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[q][p][rb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int sq = 0; sq < KQ; ++sq) {
+#pragma unroll
+        for (int s4 = 0; s4 < 4; ++s4) {
+#pragma unroll
+            for (int q = 0; q < NU; ++q) {
+                const float2 xv = x[q][4 * sq + s4];
+                const float bs = xv.x + xv.y;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[q][0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][rb][sq][s4], xv.x, acc[q][0][rb], 0, 0, 0);
+                    acc[q][1][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][rb][sq][s4], xv.y, acc[q][1][rb], 0, 0, 0);
+                    acc[q][2][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][rb][sq][s4], bs, acc[q][2][rb], 0, 0, 0);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int q = 0; q < NU; ++q) {
+                const float p1 = acc[q][0][rb][v], p2 = acc[q][1][rb][v], p3 = acc[q][2][rb][v];
+                T[su[q] + ya[4 * rb + v]] = float2{p1 - p2, p3 - p1 - p2};
+            }
+}
+
 template <int K>
 __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __restrict__ As,
                                             float2* __restrict__ T)
 {
     using S = MfmaShape<K>;
     constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int lane = threadIdx.x & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
     const int j = lane & 15, h = lane >> 4;
     int bit[K], low[K];
 #pragma unroll
@@ -56,64 +126,46 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
         bit[u] = 1 << a.op_bits[o][u];
         low[u] = (1 << a.op_lowmask_bits[o][u]) - 1;
     }
+    // this wave's operand fragments, read from LDS once per block and tile
+    f4 av[3][RB][KQ];
+#pragma unroll
+    for (int p = 0; p < 3; ++p)
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int sq = 0; sq < KQ; ++sq) av[p][rb][sq] = As[((p * RB + rb) * KQ + sq) * 64 + lane];
+    // per-lane slot offsets: group j of the unit, operand element m (matrix
+    // column 4 m + h) and result r = 16 rb + 4 h + v
+    const int lj = lslot(spread<K>(j, low));
+    int xa[NE], ya[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        int off = (h & 1) ? bit[0] : 0;
+        off |= (h & 2) ? bit[1] : 0;
+#pragma unroll
+        for (int u = 2; u < K; ++u)
+            if ((m >> (u - 2)) & 1) off |= bit[u];
+        xa[m] = lj + lslot(off);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int off = (v & 1) ? bit[0] : 0;
+            off |= (v & 2) ? bit[1] : 0;
+            off |= (h & 1) ? bit[2] : 0;
+            off |= (h & 2) ? bit[3] : 0;
+#pragma unroll
+            for (int u = 4; u < K; ++u)
+                if ((rb >> (u - 4)) & 1) off |= bit[u];
+            ya[4 * rb + v] = lj + lslot(off);
+        }
+    // units wave, wave + nw, ... in pairs (the wave's trip count is uniform)
     const int units = 1 << (a.t - K - 4);
-    for (int unit = wave; unit < units; unit += nw) {
-        int base = unit * 16 + j;                      // group index -> tile-local base
-#pragma unroll
-        for (int u = 0; u < K; ++u) {
-            const int lw = base & low[u];
-            base = ((base ^ lw) << 1) | lw;
-        }
-        float2 x[NE];
-#pragma unroll
-        for (int m = 0; m < NE; ++m) {
-            int off = (h & 1) ? bit[0] : 0;
-            off |= (h & 2) ? bit[1] : 0;
-#pragma unroll
-            for (int u = 2; u < K; ++u)
-                if ((m >> (u - 2)) & 1) off |= bit[u];
-            x[m] = T[lslot(base + off)];
-        }
-        f4 acc[3][RB];
-#pragma unroll
-        for (int p = 0; p < 3; ++p)
-#pragma unroll
-            for (int rb = 0; rb < RB; ++rb) acc[p][rb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int sq = 0; sq < KQ; ++sq) {
-            f4 av[3][RB];
-#pragma unroll
-            for (int p = 0; p < 3; ++p)
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) av[p][rb] = As[((p * RB + rb) * KQ + sq) * 64 + lane];
-#pragma unroll
-            for (int s4 = 0; s4 < 4; ++s4) {
-                const float2 xv = x[4 * sq + s4];
-                const float bs = xv.x + xv.y;
-#pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    acc[0][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[0][rb][s4], xv.x, acc[0][rb], 0, 0, 0);
-                    acc[1][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[1][rb][s4], xv.y, acc[1][rb], 0, 0, 0);
-                    acc[2][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(av[2][rb][s4], bs, acc[2][rb], 0, 0, 0);
-                }
-            }
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb) {
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-                // amplitude r = 16 rb + 4 h + v
-                int off = (v & 1) ? bit[0] : 0;
-                off |= (v & 2) ? bit[1] : 0;
-                off |= (h & 1) ? bit[2] : 0;
-                off |= (h & 2) ? bit[3] : 0;
-#pragma unroll
-                for (int u = 4; u < K; ++u)
-                    if ((rb >> (u - 4)) & 1) off |= bit[u];
-                const float p1 = acc[0][rb][v], p2 = acc[1][rb][v], p3 = acc[2][rb][v];
-                T[lslot(base + off)] = float2{p1 - p2, p3 - p1 - p2};
-            }
-        }
+    for (int unit = wave; unit < units; unit += 2 * nw) {
+        const int su[2] = {lslot(spread<K>(unit * 16, low)), lslot(spread<K>((unit + nw) * 16, low))};
+        if (unit + nw < units) stage_units<K, 2>(av, xa, ya, su, T);
+        else stage_units<K, 1>(av, xa, ya, su, T);
     }
 }
 
@@ -195,8 +247,9 @@ int stage_lds_bytes(int t, int nops, const int* ks)
 }
 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int* t_out)
+                        const void* const* mats, int t_max, int* t_out)
 {
+    if (t_max > kStageMaxT) t_max = kStageMaxT;
     if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
     // tile positions: 0..3 plus every target, ascending
     bool in[64] = {};
@@ -207,13 +260,20 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     }
     int cnt = 0;
     for (int p = 0; p < 64; ++p) cnt += in[p];
-    // at least 9 tile positions (a 16-group unit of a 5-qubit block, 256 lanes x 2)
-    for (int p = 0; p < nloc && cnt < 9; ++p)
-        if (!in[p]) { in[p] = true; ++cnt; }
+    // widen the tile with the lowest free positions up to t_max (or the LDS
+    // limit): a block has 2^(t-k-4) 16-group units per tile for the
+    // workgroup's four waves (8 for k = 5 at t = 12), and the tile's
+    // contiguous runs are longer
+    for (int p = 0; p < nloc && cnt < t_max; ++p) {
+        if (in[p]) continue;
+        if (stage_lds_bytes(cnt + 1, nops, ks) > kStageMaxLds) break;
+        in[p] = true;
+        ++cnt;
+    }
     int P[64], t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;
-    if (t > kStageMaxT || t < 9 || nloc < t) return hipErrorInvalidValue;
+    if (t > t_max || t < 9 || nloc < t) return hipErrorInvalidValue;
     StageK a{};
     a.t = t;
     a.nops = nops;

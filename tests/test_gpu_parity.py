@@ -250,3 +250,40 @@ def test_staged_multiblock_pass(n):
     assert orc.rel_l2(outs[12], ref) <= 1e-5
     assert orc.rel_l2(outs[0], ref) <= 1e-5
     assert orc.rel_l2(outs[12], outs[0]) <= 1e-6
+
+
+@pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12)])
+def test_staged_pass_any_positions(n, tmax):
+    """Staged passes over blocks whose targets lie anywhere (no position
+    limit), with tiles widened to the largest width allowed: equal to one
+    pass per block and to the oracle; the widened tile still holds every
+    block's targets."""
+    rng = np.random.default_rng(100 + n)
+    psi = W.random_state(n, rng)
+    ops = []
+    hi = list(range(4, n))
+    # at most tmax - 4 distinct positions outside 0..3, spread over the range
+    pool = [int(x) for x in rng.choice(hi, size=min(len(hi), tmax - 4), replace=False)] + [0, 1, 2, 3]
+    for _ in range(10):
+        k = int(rng.choice([4, 5]))
+        qs = [int(x) for x in rng.choice(pool, size=k, replace=False)]
+        ops.append((qs, W.random_unitary(1 << k, rng)))
+    outs = {}
+    for stage in (tmax, 0):
+        h, t = state_from_numpy(psi, "c64")
+        try:
+            sv.set_option(h, sv.SV_OPT_STAGE, stage)
+            for qs, u in ops:
+                sv.apply_fused(h, qs, u, "c64")
+            outs[stage] = read_all(h, n)
+            cnt = sv.counters(h)
+        finally:
+            sv.destroy_state(h)
+        if stage:
+            assert cnt["staged_blocks"] >= 2, "no staged pass was formed"
+    ref = psi.copy()
+    for qs, u in ops:
+        orc.apply_dense(ref, qs, u)
+    assert orc.rel_l2(outs[tmax], ref) <= 1e-5
+    assert orc.rel_l2(outs[0], ref) <= 1e-5
+    assert orc.rel_l2(outs[tmax], outs[0]) <= 1e-6
