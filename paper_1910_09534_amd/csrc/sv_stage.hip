@@ -4,19 +4,21 @@
 //
 // A stage is a run of consecutive dense blocks (k = 4 or 5, complex64) whose
 // target positions, together with positions 0..3, fit in t <= 12 tile
-// positions P[0] < ... < P[t-1] (P[0..3] = 0..3).  A tile is the 2^t
-// amplitudes whose other bits equal the tile id.  A persistent workgroup
-// (256 lanes) loops over tiles:
-//   1. the tile (held in registers since the previous iteration) is parked
-//      in LDS; the next tile's loads are issued;
-//   2. each block runs on the LDS tile: 16-group units (one per wave at a
-//      time) through the three real products of the matrix-core form
+// positions P[0] < ... < P[t-1] (P[0..3] = 0..3; free low positions widen
+// the tile to 12).  A tile is the 2^t amplitudes whose other bits equal the
+// tile id.  A persistent workgroup (256 lanes) loops over tiles:
+//   1. the next tile's loads are issued (into registers);
+//   2. each block runs on the LDS tile: pairs of 16-group units per wave
+//      through the three real products of the matrix-core form
 //      (v_mfma_f32_16x16x4f32, same operand layout as the single sweep),
 //      reading and writing LDS, with a workgroup barrier between blocks;
-//   3. the tile is written back.
-// The blocks' matrices are staged in LDS once per workgroup.  Every
-// workgroup runs the same number of tile iterations, so the barriers are
-// reached uniformly.
+//   3. the tile is written back, then the next tile is parked in LDS.
+// The next tile's loads precede this tile's stores, so parking never waits
+// for stores.  Re M and Im M of every block are staged in LDS once per
+// workgroup.  Every workgroup runs the same number of tile iterations, so
+// the barriers are reached uniformly.
+#include <atomic>
+
 #include "sv_device.h"
 
 namespace sv {
@@ -60,14 +62,15 @@ __device__ __forceinline__ int spread(int g, const int (&low)[K])
 
 // NU (1 or 2) 16-group units of one block on the LDS tile, processed together
 // by the calling wave: their loads are issued together and their 6 NU
-// accumulator chains interleave on the matrix core.  su: LDS slot of each
-// unit's first group (uniform); xa / ya: per-lane slot offsets of the
-// operand elements and of the results.
+// accumulator chains interleave on the matrix core.  The LDS slot of operand
+// element m (matrix column 4 m + h) of unit q is su[q] + sx[m] + cx and that
+// of result r = 16 rb + 4 h + v is su[q] + sy[4 rb + v] + cy: su, sx, sy are
+// wave-uniform, cx, cy per lane.
 template <int K, int NU>
 __device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][MfmaShape<K>::KQ],
-                                            const int (&xa)[MfmaShape<K>::D / 4],
-                                            const int (&ya)[MfmaShape<K>::D / 4], const int (&su)[2],
-                                            float2* __restrict__ T)
+                                            const int (&sx)[MfmaShape<K>::D / 4],
+                                            const int (&sy)[MfmaShape<K>::D / 4], int cx, int cy,
+                                            const int (&su)[2], float2* __restrict__ T)
 {
     using S = MfmaShape<K>;
     constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
@@ -75,7 +78,7 @@ __device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][
 #pragma unroll
     for (int m = 0; m < NE; ++m)
 #pragma unroll
-        for (int q = 0; q < NU; ++q) x[q][m] = T[su[q] + xa[m]];
+        for (int q = 0; q < NU; ++q) x[q][m] = T[(su[q] + sx[m]) + cx];
     f4 acc[NU][3][RB];
 #pragma unroll
     for (int q = 0; q < NU; ++q)
@@ -107,7 +110,7 @@ __device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][
 #pragma unroll
             for (int q = 0; q < NU; ++q) {
                 const float p1 = acc[q][0][rb][v], p2 = acc[q][1][rb][v], p3 = acc[q][2][rb][v];
-                T[su[q] + ya[4 * rb + v]] = float2{p1 - p2, p3 - p1 - p2};
+                T[(su[q] + sy[4 * rb + v]) + cy] = float2{p1 - p2, p3 - p1 - p2};
             }
 }
 
@@ -126,26 +129,33 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
         bit[u] = 1 << a.op_bits[o][u];
         low[u] = (1 << a.op_lowmask_bits[o][u]) - 1;
     }
-    // this wave's operand fragments, read from LDS once per block and tile
+    // this wave's operand fragments of Re M and Im M, read from LDS once per
+    // block and tile; the third operand Re M + Im M is formed here
     f4 av[3][RB][KQ];
 #pragma unroll
-    for (int p = 0; p < 3; ++p)
+    for (int p = 0; p < 2; ++p)
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
             for (int sq = 0; sq < KQ; ++sq) av[p][rb][sq] = As[((p * RB + rb) * KQ + sq) * 64 + lane];
-    // per-lane slot offsets: group j of the unit, operand element m (matrix
-    // column 4 m + h) and result r = 16 rb + 4 h + v
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int sq = 0; sq < KQ; ++sq) av[2][rb][sq] = av[0][rb][sq] + av[1][rb][sq];
+    // slot offsets: per lane, the unit's group j with the lane's h bits (h
+    // selects matrix bits 0, 1 of an operand and bits 2, 3 of a result);
+    // uniform, the remaining matrix bits of element m / result (rb, v)
     const int lj = lslot(spread<K>(j, low));
-    int xa[NE], ya[NE];
+    const int cx = lj + lslot(((h & 1) ? bit[0] : 0) | ((h & 2) ? bit[1] : 0));
+    const int cy = lj + lslot(((h & 1) ? bit[2] : 0) | ((h & 2) ? bit[3] : 0));
+    int sx[NE], sy[NE];
 #pragma unroll
     for (int m = 0; m < NE; ++m) {
-        int off = (h & 1) ? bit[0] : 0;
-        off |= (h & 2) ? bit[1] : 0;
+        int off = 0;
 #pragma unroll
         for (int u = 2; u < K; ++u)
             if ((m >> (u - 2)) & 1) off |= bit[u];
-        xa[m] = lj + lslot(off);
+        sx[m] = lslot(off);
     }
 #pragma unroll
     for (int rb = 0; rb < RB; ++rb)
@@ -153,32 +163,35 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
         for (int v = 0; v < 4; ++v) {
             int off = (v & 1) ? bit[0] : 0;
             off |= (v & 2) ? bit[1] : 0;
-            off |= (h & 1) ? bit[2] : 0;
-            off |= (h & 2) ? bit[3] : 0;
 #pragma unroll
             for (int u = 4; u < K; ++u)
                 if ((rb >> (u - 4)) & 1) off |= bit[u];
-            ya[4 * rb + v] = lj + lslot(off);
+            sy[4 * rb + v] = lslot(off);
         }
     // units wave, wave + nw, ... in pairs (the wave's trip count is uniform)
     const int units = 1 << (a.t - K - 4);
     for (int unit = wave; unit < units; unit += 2 * nw) {
         const int su[2] = {lslot(spread<K>(unit * 16, low)), lslot(spread<K>((unit + nw) * 16, low))};
-        if (unit + nw < units) stage_units<K, 2>(av, xa, ya, su, T);
-        else stage_units<K, 1>(av, xa, ya, su, T);
+        if (unit + nw < units) stage_units<K, 2>(av, sx, sy, cx, cy, su, T);
+        else stage_units<K, 1>(av, sx, sy, cx, cy, su, T);
     }
 }
 
+// TW: tile width t (9..12), PER = 2^(t-8) elements per lane.  WIDE: the
+// lane part of an element's address needs more than 32 bits of byte offset
+// (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
+// per-lane offset, so loads and stores take the scalar-base form).
+template <int TW, bool WIDE>
 __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK a)
 {
+    constexpr int PER = 1 << (TW - 8);
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
-    const int tsz = 1 << a.t;
-    f4* Abase = smem + ((lslot(tsz) * 8 + 15) / 16);              // operand matrices
+    f4* Abase = smem + ((lslot(1 << TW) * 8 + 15) / 16);          // operand matrices
     // stage every block's three real matrices in operand order
     for (int o = 0; o < a.nops; ++o) {
         const int k = a.op_k[o];
-        const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 3 * RB * KQ * 256;
+        const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 2 * RB * KQ * 256;
         float* dst = (float*)(Abase) + a.op_aoff[o];
         const float2* mat = a.op_mat[o];
         for (int i = threadIdx.x; i < NA; i += blockDim.x) {
@@ -187,43 +200,48 @@ __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK 
             const int R = 16 * rb + (l & 15);
             const int C = 4 * (4 * sq + s4) + (l >> 4);
             const float2 m = mat[R * D + C];
-            dst[i] = p == 0 ? m.x : (p == 1 ? m.y : m.x + m.y);
+            dst[i] = p == 0 ? m.x : m.y;
         }
     }
-    const int per = tsz / 256;                                   // elements per lane (<= 16)
     uint64_t dl = 0;
     for (int b = 0; b < 8; ++b)
         if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
+    const uint32_t dlb = (uint32_t)(dl * sizeof(float2));       // used when !WIDE
+    // element i of this lane in the tile at uniform index base tb
+    auto elem = [&](uint64_t tb, int i) -> float2* {
+        if (WIDE) return psi + (tb + dl + a.dep_i[i]);
+        return (float2*)((char*)(psi + (tb + a.dep_i[i])) + dlb);
+    };
     auto tile_base = [&](uint64_t tile) {
         uint64_t base = tile;
-        for (int b = 0; b < a.t; ++b) {
+        for (int b = 0; b < TW; ++b) {
             const uint64_t lw = base & a.tile_lowmask[b];
             base = ((base ^ lw) << 1) | lw;
         }
         return base;
     };
-    // statically indexed (a runtime trip count would put xr in scratch)
-    float2 xr[16];
+    const int ls = lslot(threadIdx.x);                          // + lslot(256 i) = 272 i
+    float2 xr[PER];
     uint64_t tile = blockIdx.x;
     if (tile < a.tiles) {
-        const uint64_t b0 = tile_base(tile) + dl;
+        const uint64_t tb = tile_base(tile);
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < per) xr[i] = psi[b0 + a.dep_i[i]];
+        for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
+#pragma unroll
+        for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
     }
     __syncthreads();
+    // Per tile: issue the next tile's loads, run the blocks on the LDS tile,
+    // store it, then park the next tile.  Its loads precede this tile's
+    // stores, so parking waits for the loads only, never for the stores.
     for (; tile < a.tiles; tile += gridDim.x) {
-        const uint64_t b0 = tile_base(tile) + dl;
-#pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < per) T[lslot(threadIdx.x + 256 * i)] = xr[i];
-        __syncthreads();
+        const uint64_t tb = tile_base(tile);
         const uint64_t nt = tile + gridDim.x;
-        if (nt < a.tiles) {
-            const uint64_t nb = tile_base(nt) + dl;
+        const bool next = nt < a.tiles;
+        if (next) {
+            const uint64_t nb = tile_base(nt);
 #pragma unroll
-            for (int i = 0; i < 16; ++i)
-                if (i < per) xr[i] = psi[nb + a.dep_i[i]];
+            for (int i = 0; i < PER; ++i) xr[i] = *elem(nb, i);
         }
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
@@ -232,16 +250,21 @@ __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK 
             __syncthreads();
         }
 #pragma unroll
-        for (int i = 0; i < 16; ++i)
-            if (i < per) psi[b0 + a.dep_i[i]] = T[lslot(threadIdx.x + 256 * i)];
+        for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + 272 * i];
+        __syncthreads();
+        if (next) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
+        }
         __syncthreads();
     }
 }
 
+
 int stage_lds_bytes(int t, int nops, const int* ks)
 {
     int floats = 0;
-    for (int o = 0; o < nops; ++o) floats += 3 * (1 << (2 * ks[o]));
+    for (int o = 0; o < nops; ++o) floats += 2 * (1 << (2 * ks[o]));
     const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16 + 1;
     return tile_f4 * 16 + floats * 4;
 }
@@ -291,7 +314,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
         a.op_k[o] = ks[o];
         a.op_mat[o] = (const float2*)mats[o];
         a.op_aoff[o] = aoff;
-        aoff += 3 * (1 << (2 * ks[o]));
+        aoff += 2 * (1 << (2 * ks[o]));
         int lb[kMaxDense];
         for (int j = 0; j < ks[o]; ++j) {
             int b = 0;
@@ -307,12 +330,29 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     }
     const int lds = stage_lds_bytes(t, nops, ks);
     if (lds > kStageMaxLds) return hipErrorInvalidValue;
-    static bool attr_set = false;
-    if (!attr_set) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k_stage,
+    // byte offset of the lane part of an element address
+    uint64_t dl_max = 0;
+    for (int b = 0; b < 8; ++b) dl_max |= a.dep_lane[b];
+    const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
+    void (*kern)(float2*, StageK) = nullptr;
+    switch (t * 2 + (wide ? 1 : 0)) {
+        case 18: kern = k_stage<9, false>; break;
+        case 19: kern = k_stage<9, true>; break;
+        case 20: kern = k_stage<10, false>; break;
+        case 21: kern = k_stage<10, true>; break;
+        case 22: kern = k_stage<11, false>; break;
+        case 23: kern = k_stage<11, true>; break;
+        case 24: kern = k_stage<12, false>; break;
+        case 25: kern = k_stage<12, true>; break;
+        default: return hipErrorInvalidValue;
+    }
+    static std::atomic<bool> attr_set[8];
+    const int ai = (t - 9) * 2 + (wide ? 1 : 0);
+    if (!attr_set[ai]) {
+        const hipError_t e = hipFuncSetAttribute((const void*)kern,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds);
         if (e != hipSuccess) return e;
-        attr_set = true;
+        attr_set[ai] = true;
     }
     // persistent: as many workgroups as are resident (LDS-limited, at most 4 per CU)
     int per_cu = (160 * 1024) / lds;
@@ -321,7 +361,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t grid = a.tiles;
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(k_stage, dim3((unsigned)grid), dim3(256), lds, st, (float2*)psi, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     return hipGetLastError();
 }

@@ -13,6 +13,12 @@
   |01>, |10> block.  With fold_diag the diagonal part is emitted as its own
   op right after the cluster holding the non-diagonal part, and the library
   folds it into that cluster's sweep as an element-wise phase.
+* Staged passes (cache blocking of aggregate gates, as in the appendix): the
+  device applies a run of consecutive 4/5-qubit blocks whose positions, with
+  positions 0..3, fit in one 12-position tile in a single HBM pass.
+  `order_for_staging` reorders commuting blocks so that such runs are
+  consecutive, and `plan` picks among aggregations by a cost model of
+  staged and single passes.
 * Slice phases (Sec. 4): `phase_schedule` splits the gate list into phases,
   each with a set of sliced qubits on which only diagonal work may happen,
   alternating between two slice sets like the paper's subcircuits 3..9.
@@ -236,19 +242,152 @@ def fuse_grow(gates, kmax: int, window: int = 4) -> List[Op]:
     return ops
 
 
+# Staged-pass formation on the device (mirrored here for planning): a run
+# holds at most STAGE_MAX_OPS 4/5-qubit blocks, the tile at most STAGE_T
+# positions (0..3 always), and the LDS budget covers the tile (2^t complex64
+# plus one pad per 16) and Re/Im of every block's matrix.
+STAGE_T = 12
+STAGE_MAX_OPS = 8
+STAGE_LDS = 80 * 1024
+
+
+def _stage_lds(t: int, ks: Sequence[int]) -> int:
+    tile = (((1 << t) + ((1 << t) >> 4)) * 8 // 16 + 1) * 16
+    return tile + sum(2 * (1 << (2 * k)) for k in ks) * 4
+
+
+def _stageable(o: "Op") -> bool:
+    return o.kind == "dense" and len(o.qubits) in (4, 5)
+
+
+def _fits(pos: set, ks: Sequence[int], tmax: int) -> bool:
+    t = max(9, len(pos))
+    return t <= tmax and len(ks) <= STAGE_MAX_OPS and _stage_lds(t, ks) <= STAGE_LDS
+
+
+def stage_runs(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> List[List[int]]:
+    """The runs the device forms from `ops` in this order (lists of indices;
+    a single-element list is a sweep of its own)."""
+    pos = (lambda q: q) if pos_of is None else pos_of
+    runs: List[List[int]] = []
+    i = 0
+    while i < len(ops):
+        if _stageable(ops[i]):
+            P, ks, j = set(range(4)), [], i
+            while j < len(ops) and _stageable(ops[j]):
+                P2 = P | {pos(q) for q in ops[j].qubits}
+                if not _fits(P2, ks + [len(ops[j].qubits)], tmax):
+                    break
+                P, ks, j = P2, ks + [len(ops[j].qubits)], j + 1
+            if j - i >= 2:
+                runs.append(list(range(i, j)))
+                i = j
+                continue
+        runs.append([i])
+        i += 1
+    return runs
+
+
+def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> List["Op"]:
+    """Reorder ops so that blocks which can share a staged pass are adjacent.
+
+    Ops are nodes of a dependency graph (an op depends on the last earlier op
+    sharing a qubit); only ops with no path between them change relative
+    order, so the product is unchanged (ops on disjoint qubits commute).
+    Greedy: take the earliest ready op; if it is a 4/5-qubit block, keep
+    adding the ready block that adds the fewest new tile positions (earliest
+    first) while the tile and LDS limits hold."""
+    pos = (lambda q: q) if pos_of is None else pos_of
+    n = len(ops)
+    npred = [0] * n
+    succ: List[List[int]] = [[] for _ in range(n)]
+    last: Dict[int, int] = {}
+    for i, o in enumerate(ops):
+        ps = {last[q] for q in o.qubits if q in last}
+        for p in ps:
+            succ[p].append(i)
+        npred[i] = len(ps)
+        for q in o.qubits:
+            last[q] = i
+    ready = {i for i in range(n) if npred[i] == 0}
+    out: List[Op] = []
+
+    def take(i):
+        ready.discard(i)
+        out.append(ops[i])
+        for s_ in succ[i]:
+            npred[s_] -= 1
+            if npred[s_] == 0:
+                ready.add(s_)
+
+    while ready:
+        first = min(ready)
+        take(first)
+        if not _stageable(ops[first]):
+            continue
+        P = set(range(4)) | {pos(q) for q in ops[first].qubits}
+        ks = [len(ops[first].qubits)]
+        while True:
+            best = None
+            for i in ready:
+                if not _stageable(ops[i]):
+                    continue
+                P2 = P | {pos(q) for q in ops[i].qubits}
+                if not _fits(P2, ks + [len(ops[i].qubits)], tmax):
+                    continue
+                key = (len(P2) - len(P), i)
+                if best is None or key < best[0]:
+                    best = (key, i, P2)
+            if best is None:
+                break
+            _, i, P = best
+            ks.append(len(ops[i].qubits))
+            take(i)
+    assert len(out) == n
+    return out
+
+
+# Modelled device time (ms per 2^30 complex64 amplitudes) of a single sweep
+# of a k-qubit block, and of a staged pass: a fixed part plus a part per
+# block.  Only the ranking of candidate plans uses these figures.
+SWEEP_MS = {1: 2.9, 2: 2.9, 3: 3.4, 4: 3.55, 5: 3.6, 6: 3.7}
+STAGE_MS_FIXED = 1.5
+STAGE_MS_BLOCK = {4: 1.15, 5: 1.7}
+
+
+def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> float:
+    """Modelled time of `ops` in this order, staged runs formed as the
+    device forms them."""
+    tot = 0.0
+    for r in stage_runs(ops, pos_of, tmax):
+        if len(r) >= 2:
+            tot += STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r)
+        else:
+            o = ops[r[0]]
+            tot += SWEEP_MS.get(len(o.qubits), 4.0) if o.kind == "dense" else SWEEP_MS[1]
+    return tot
+
+
 def plan_cost(ops: Sequence[Op]) -> float:
     """Relative cost of a plan: one unit per HBM sweep plus the block's
     arithmetic (8 2^k flop per amplitude) in units of a 6-qubit block."""
     return sum(1.0 + (8 << len(o.qubits)) / 4096.0 if o.kind == "dense" else 1.0 for o in ops)
 
 
-def plan(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
-    """Aggregate with every available heuristic and keep the cheapest plan."""
+def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None) -> List[Op]:
+    """Aggregate with every available heuristic and keep the cheapest plan.
+
+    staged: order commuting blocks for staged passes (`order_for_staging`,
+    positions given by pos_of, default position = qubit) and rank the
+    candidates by `staged_cost`; otherwise rank by `plan_cost`."""
     cands = [fuse(gates, kmax, fold_diag=fold_diag)]
     if not fold_diag:
         for w in (3, 4, 5, 6, 8):
             cands.append(fuse_grow(gates, kmax, window=w))
-    return min(cands, key=plan_cost)
+    if not staged or fold_diag:
+        return min(cands, key=plan_cost)
+    cands = [order_for_staging(c, pos_of) for c in cands]
+    return min(cands, key=lambda c: staged_cost(c, pos_of))
 
 
 @dataclasses.dataclass
@@ -303,7 +442,8 @@ def phase_schedule(circuit, set_a: Sequence[int], set_b: Sequence[int], kmax: in
             else:
                 take.append(i)
         ph = Phase(cur, phase_layout(n, cur, nxt), take)
-        ph.ops = plan([gates[i] for i in take], kmax) if take else []
+        where = {q: p for p, q in enumerate(ph.order)}
+        ph.ops = plan([gates[i] for i in take], kmax, pos_of=where.__getitem__) if take else []
         phases.append(ph)
         stall = stall + 1 if not take else 0
         if stall >= 2 or len(phases) > max_phases:
