@@ -7,10 +7,17 @@ amplitudes (8 GiB, resident in HBM), gates aggregated into dense blocks of
 at most 5 qubits, output = norm + amplitudes of 2^16 seeded bitstrings with
 FP64 cross-entropy sums.
 
-One step = reset the state to |0...0> (init kernel) + every fused sweep of
-the planned circuit + the FP64 gather / norm / cross-entropy reduction,
+One step = reset the state to |0...0> (init kernel) + every HBM pass of
+the planned circuit (staged passes of several 4/5-qubit blocks, single
+sweeps for the rest) + the FP64 gather / norm / cross-entropy reduction,
 with the circuit already planned (host planning is not timed) and the state
 already allocated in HBM.
+
+roofline: the kernel kind with the most time in the timed steps (staged
+passes: matrix-core bound, flops = 6 2^k per amplitude per block, the
+three real products of the 3M form; single sweeps: HBM bound, 16 bytes per
+amplitude per launch), durations from HIP events on the kernels' stream;
+hbm_frac_run: HBM passes x 16 bytes x 2^n per step over the step time.
 
 value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
 un-aggregated work over aggregated time).
@@ -54,31 +61,39 @@ FP32_PEAK_TFLOPS = 157.3
 
 
 KERNEL_SOURCES = ("paper_1910_09534_amd/csrc/sv_device.h", "paper_1910_09534_amd/csrc/sv_kernels.hip",
-                  "paper_1910_09534_amd/csrc/sv_mfma.hip", "paper_1910_09534_amd/csrc/sv_internal.h")
-TRAFFIC_FILE = "profiles/dense_sweep_30q_d14_traffic.json"
+                  "paper_1910_09534_amd/csrc/sv_mfma.hip", "paper_1910_09534_amd/csrc/sv_stage.hip",
+                  "paper_1910_09534_amd/csrc/sv_internal.h")
+TRAFFIC_FILE = "profiles/staged_pass_30q_d14_traffic.json"
 
 
 def kernel_hash() -> str:
+    """Hash of the kernel sources with comments and blank space removed (a
+    comment edit does not invalidate the counter figures)."""
     import hashlib
+    import re
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, f), "rb") as fh:
-            h.update(fh.read())
+        with open(os.path.join(ROOT, f)) as fh:
+            src = fh.read()
+        src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+        src = re.sub(r"//[^\n]*", "", src)
+        h.update(" ".join(src.split()).encode())
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kmax: int):
-    """HBM bytes per dense-sweep launch from the committed counter runs
-    (FETCH_SIZE + WRITE_SIZE, scaled by a plain copy of known size), or None
-    when the kernels changed since the counters were taken."""
+def counter_traffic(kind: str):
+    """HBM bytes per launch of one kernel kind ("staged" passes or single
+    "sweep"s) from the committed counter runs (FETCH_SIZE + WRITE_SIZE,
+    scaled by a plain copy of known size), or None when the kernel sources
+    changed since the counters were taken."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
     with open(path) as f:
         d = json.load(f)
-    if d.get("kernel_hash") != kernel_hash() or d.get("kmax") != kmax:
+    if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d.get("per_kind", {}).get(kind, {}).get("traffic_bytes_per_launch")
 
 
 def calibrate_copy() -> int:
@@ -169,8 +184,9 @@ def main(argv=None) -> int:
 
     for _ in range(args.warmup):
         step()
-    sv.sweep_time(h)                               # clear
-    sv.set_option(h, sv.SV_OPT_TIMING, 1)          # HIP events around every dense sweep
+    sv.sweep_profile(h)                            # clear
+    sv.set_option(h, sv.SV_OPT_TIMING, 1)          # HIP events around every sweep / staged pass
+    c0 = sv.counters(h)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -180,29 +196,48 @@ def main(argv=None) -> int:
     ms_per_step = 1e3 * t / args.steps
     gates = len(circ.gates)
     value = gates * float(1 << n) * args.steps / t
+    c1 = sv.counters(h)
+    passes = (c1["dense_sweeps"] - c0["dense_sweeps"]) / args.steps
 
-    # dominant kernel: the fused dense sweep, every launch of the timed steps
-    # bracketed by HIP events on the stream the kernels run on
-    sweep_ms, nswept = sv.sweep_time(h)
+    # per kernel kind, every launch of the timed steps bracketed by HIP events
+    # on the stream the kernels run on; the dominant kind is the roofline's
+    prof = sv.sweep_profile(h)
     sv.set_option(h, sv.SV_OPT_TIMING, 0)
-    avg_ms = sweep_ms / max(nswept, 1)
-    bytes_per_sweep = 16.0 * (1 << n)              # read + write of complex64
-    flops_per_step = pst["flops_per_amp"] * float(1 << n) * args.steps
-    gbs = bytes_per_sweep / (avg_ms * 1e-3) / 1e9
-    tflops = flops_per_step / (sweep_ms * 1e-3) / 1e12
-    hbm_frac = gbs / HBM_PEAK_GBS
-    alu_frac = tflops / FP32_PEAK_TFLOPS
-    roof = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(hbm_frac, 4), "traffic": counter_traffic(args.kmax),
-            "kernel": "k_dense (fused dense sweep), all launches of the timed steps",
-            "avg_launch_ms": round(avg_ms, 4), "launches": nswept,
-            "alu": {"achieved_tflops": round(tflops, 2), "peak_tflops": FP32_PEAK_TFLOPS,
-                    "frac": round(alu_frac, 4)}}
-    if alu_frac > hbm_frac:
-        roof.update({"bound": "alu", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
-                     "unit": "TFLOP/s", "frac": round(alu_frac, 4),
-                     "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(hbm_frac, 4)}})
-    run_hbm_frac = ndense * bytes_per_sweep / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    bytes_per_pass = 16.0 * (1 << n)               # read + write of complex64
+
+    def kind_roof(kind):
+        p = prof[kind]
+        if p["count"] == 0:
+            return None
+        avg_ms = p["ms"] / p["count"]
+        gbs = bytes_per_pass / (avg_ms * 1e-3) / 1e9
+        tflops = p["flops"] / (p["ms"] * 1e-3) / 1e12
+        r = {"launches": p["count"], "avg_launch_ms": round(avg_ms, 4),
+             "share_of_step": round(p["ms"] / (args.steps * ms_per_step), 4),
+             "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
+                     "bytes_per_launch": bytes_per_pass},
+             "fp32": {"achieved_tflops": round(tflops, 2), "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
+                      "flops_per_launch": p["flops"] / p["count"]},
+             "traffic": counter_traffic(kind)}
+        if kind == "staged":
+            r.update({"kernel": "k_stage (staged pass: 2-5 dense 4/5-qubit blocks per HBM pass, matrix cores)",
+                      "bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
+                      "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4)})
+        else:
+            r.update({"kernel": "k_dense / k_dense_mfma (one dense block per HBM pass)",
+                      "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        return r
+
+    kinds = {k: kind_roof(k) for k in ("staged", "sweep")}
+    dom = max((k for k in kinds if kinds[k]), key=lambda k: prof[k]["ms"])
+    roof = dict(kinds[dom])
+    roof = {key: roof[key] for key in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
+                                       "avg_launch_ms", "launches", "share_of_step", "hbm", "fp32")}
+    other = [k for k in kinds if k != dom and kinds[k]]
+    if other:
+        roof["other_kernel"] = kinds[other[0]]
+    run_hbm_frac = passes * bytes_per_pass / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     sv.destroy_state(h)
     del buf
@@ -220,7 +255,8 @@ def main(argv=None) -> int:
         "config": {"workload": "30-qubit 5x6 ABCDCDAB random circuit, depth 14, complex64, "
                                "fusion k<=%d, norm + 2^16 bitstrings" % args.kmax,
                    "n": n, "depth": circ.depth, "gates": gates, "kmax": args.kmax,
-                   "bitstrings": int(bits.size), "sweeps": ndense, "k_hist": pst["k_hist"]},
+                   "bitstrings": int(bits.size), "blocks": ndense, "hbm_passes": passes,
+                   "k_hist": pst["k_hist"]},
         "hbm_frac_run": round(run_hbm_frac, 4),
         "norm": stats[0],
         "roofline": roof,

@@ -201,6 +201,14 @@ int sv_set_option(sv_handle h, int option, int64_t value);
 int sv_counters(sv_handle h, int64_t counters[8]);
 int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
 
+/* sv_sweep_profile -- with SV_OPT_TIMING: the timed launches split by kind,
+ * [0] single dense sweeps, [1] staged multi-block passes: total
+ * milliseconds, launch count and the arithmetic the launches performed
+ * (flops: 6 2^k per amplitude for a complex64 block on the matrix cores,
+ * 8 2^k on the vector units, 32 2^k for complex128).  Resets the same
+ * accumulators as sv_sweep_time.  Any pointer may be NULL. */
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2]);
+
 /* ---- batches of independent states ----------------------------------------
  * Many circuits of different qubit counts run as one recorded execution: the
  * queued operations of each state (its plan) are taken over, sweep r of every

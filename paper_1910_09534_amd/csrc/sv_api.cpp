@@ -129,9 +129,24 @@ int collect_timing(sv_state* h)
         TRY(h, hipEventElapsedTime(&ms, h->tev_pool[i], h->tev_pool[i + 1]));
         h->t_ms += ms;
         h->t_count += 1;
+        const auto& info = h->tev_info[i / 2];
+        h->tk_ms[info.first] += ms;
+        h->tk_count[info.first] += 1;
+        h->tk_flops[info.first] += info.second;
     }
     h->tev_used = 0;
+    h->tev_info.clear();
     return SV_OK;
+}
+
+// Arithmetic of one dense k-qubit block per amplitude: 6 2^k flops in the
+// matrix-core form (three real products), 8 2^k on the vector units
+// (complex multiply-adds), 4x that for complex128.
+static double block_flops_per_amp(int dtype, int k, int nloc, int mfma_min_k)
+{
+    const double d = (double)(1 << k);
+    if (dtype == 0 && dense_uses_mfma(k, nloc, mfma_min_k)) return 6.0 * d;
+    return 8.0 * d;
 }
 
 // ---- running the queue over one range of amplitudes ----------------------
@@ -181,7 +196,12 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 }
                 int tused = 0;
                 TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, &tused));
-                if (h->timing) TRY(h, hipEventRecord(e1, st));
+                if (h->timing) {
+                    TRY(h, hipEventRecord(e1, st));
+                    double f = 0.0;
+                    for (int c = 0; c < cnt; ++c) f += 6.0 * (double)(1 << ks[c]);
+                    h->tev_info.emplace_back(1, f * (double)((uint64_t)1 << nloc));
+                }
                 h->counters[0] += 1;
                 h->counters[3] += (int64_t)1 << nloc;
                 h->counters[7] += cnt;
@@ -209,7 +229,11 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
             }
             TRY(h, launch_dense(st, *psi, h->dtype, nloc, op.k, op.pos, dbase + op.off, fp,
                                 idx_offset, h->mfma_min_k));
-            if (h->timing) TRY(h, hipEventRecord(e1, st));
+            if (h->timing) {
+                TRY(h, hipEventRecord(e1, st));
+                h->tev_info.emplace_back(0, block_flops_per_amp(h->dtype, op.k, nloc, h->mfma_min_k) *
+                                                (h->dtype ? 4.0 : 1.0) * (double)((uint64_t)1 << nloc));
+            }
             h->counters[0] += 1;
             h->counters[3] += (int64_t)1 << nloc;
         } else if (op.kind == OP_DIAG) {
@@ -1201,6 +1225,17 @@ int sv_counters(sv_handle h, int64_t counters[8])
     return SV_OK;
 }
 
+static void reset_timing(sv_state* h)
+{
+    h->t_ms = 0.0;
+    h->t_count = 0;
+    for (int k = 0; k < 2; ++k) {
+        h->tk_ms[k] = 0.0;
+        h->tk_count[k] = 0;
+        h->tk_flops[k] = 0.0;
+    }
+}
+
 int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
 {
     CHECK_HANDLE(h);
@@ -1208,8 +1243,21 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
     if (rc) return rc;
     if (total_ms) *total_ms = h->t_ms;
     if (count) *count = h->t_count;
-    h->t_ms = 0.0;
-    h->t_count = 0;
+    reset_timing(h);
+    return SV_OK;
+}
+
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2])
+{
+    CHECK_HANDLE(h);
+    int rc = collect_timing(h);
+    if (rc) return rc;
+    for (int k = 0; k < 2; ++k) {
+        if (ms) ms[k] = h->tk_ms[k];
+        if (count) count[k] = h->tk_count[k];
+        if (flops) flops[k] = h->tk_flops[k];
+    }
+    reset_timing(h);
     return SV_OK;
 }
 

@@ -89,6 +89,13 @@ hipError_t launch_dense_mfma_batch(hipStream_t st, int k, bool fold, bool staged
                                    int nitems, uint64_t total_blocks);
 uint64_t mfma_batch_blocks(uint64_t groups);
 
+// Whether a complex64 k-qubit sweep over 2^nloc amplitudes runs on the
+// matrix cores (else on the vector units).
+inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
+{
+    return mfma_min_k >= 4 && k >= mfma_min_k && nloc >= k + 4;
+}
+
 // Staged sweep: nops dense blocks (k = 4 or 5, complex64) applied to LDS
 // tiles in one HBM pass.  pos[o] / mats[o]: block o's positions and device
 // matrix.  The tile (positions 0..3 and every target) is widened with free

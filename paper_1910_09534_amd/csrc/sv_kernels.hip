@@ -220,7 +220,7 @@ hipError_t launch_dense(hipStream_t st, void* psi, int dtype, int nloc, int k, c
 {
     if (k < 1 || k > kMaxDense || k > nloc) return hipErrorInvalidValue;
     if (dtype && k > 5) return hipErrorInvalidValue;
-    if (dtype == 0 && mfma_min_k >= 4 && k >= mfma_min_k && nloc >= k + 4)
+    if (dtype == 0 && dense_uses_mfma(k, nloc, mfma_min_k))
         return launch_dense_mfma(st, psi, nloc, k, pos, mat, fold, idx_offset);
     const Sweep a = make_sweep(psi, nloc, k, pos, mat, fold, idx_offset);
     if (dtype == 0) {

@@ -1,6 +1,8 @@
-// Staged sweep: several dense blocks applied in one pass over HBM (cache
-// blocking of aggregate gates, as in the appendix's description of 5-qubit
-// aggregate gates built with cache blocking).
+// Staged sweep: several dense blocks applied in one pass over HBM.  The
+// appendix uses cache blocking to form the 5-qubit aggregate gates
+// themselves (each "cache" line of its listing is one aggregate); here a
+// second level of blocking applies a run of aggregates to an LDS-resident
+// tile, so the run costs one HBM round trip instead of one per aggregate.
 //
 // A stage is a run of consecutive dense blocks (k = 4 or 5, complex64) whose
 // target positions, together with positions 0..3, fit in t <= 12 tile

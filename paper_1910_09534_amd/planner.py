@@ -13,9 +13,10 @@
   |01>, |10> block.  With fold_diag the diagonal part is emitted as its own
   op right after the cluster holding the non-diagonal part, and the library
   folds it into that cluster's sweep as an element-wise phase.
-* Staged passes (cache blocking of aggregate gates, as in the appendix): the
-  device applies a run of consecutive 4/5-qubit blocks whose positions, with
-  positions 0..3, fit in one 12-position tile in a single HBM pass.
+* Staged passes (a second level of cache blocking over the appendix's
+  aggregate gates): the device applies a run of consecutive 4/5-qubit
+  blocks whose positions, with positions 0..3, fit in one 12-position tile
+  in a single HBM pass.
   `order_for_staging` reorders commuting blocks so that such runs are
   consecutive, and `plan` picks among aggregations by a cost model of
   staged and single passes.

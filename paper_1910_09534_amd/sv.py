@@ -26,7 +26,7 @@ ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_E
 EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "apply_diag",
            "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
-           "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
+           "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
            "sv_batch_destroy", "sv_batch_error")
 SV_BATCH_GRAPH = 1
 
@@ -60,6 +60,7 @@ def load():
     L.sv_set_option.argtypes = [P, I, I64]
     L.sv_counters.argtypes = [P, P]
     L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
+    L.sv_sweep_profile.argtypes = [P, P, P, P]
     L.sv_batch_prepare.argtypes = [I, P, I, P, ctypes.POINTER(P)]
     L.sv_batch_launch.argtypes = [P]
     L.sv_batch_sync.argtypes = [P]
@@ -207,6 +208,17 @@ def sweep_time(h):
     cnt = ctypes.c_int64()
     _check(lib().sv_sweep_time(h, ctypes.byref(ms), ctypes.byref(cnt)), h)
     return ms.value, cnt.value
+
+
+def sweep_profile(h) -> dict:
+    """Timed launches by kind ("sweep": single dense sweeps, "staged":
+    staged passes): ms, count, flops.  Resets the timing accumulators."""
+    ms = np.zeros(2, dtype=np.float64)
+    cnt = np.zeros(2, dtype=np.int64)
+    fl = np.zeros(2, dtype=np.float64)
+    _check(lib().sv_sweep_profile(h, _ptr(ms), _ptr(cnt), _ptr(fl)), h)
+    return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i])}
+            for i, kind in enumerate(("sweep", "staged"))}
 
 
 def _bcheck(rc: int, b=None):

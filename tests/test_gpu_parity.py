@@ -287,3 +287,28 @@ def test_staged_pass_any_positions(n, tmax):
     assert orc.rel_l2(outs[tmax], ref) <= 1e-5
     assert orc.rel_l2(outs[0], ref) <= 1e-5
     assert orc.rel_l2(outs[tmax], outs[0]) <= 1e-6
+
+
+def test_sweep_profile_splits_kinds():
+    """With timing on, staged passes and single sweeps are reported apart,
+    with their launch counts and the arithmetic of their blocks."""
+    n = 16
+    rng = np.random.default_rng(5)
+    h, t = state_from_numpy(W.random_state(n, rng), "c64")
+    try:
+        sv.set_option(h, sv.SV_OPT_TIMING, 1)
+        blocks = [([4, 5, 6, 7, 8], 5), ([6, 7, 8, 9], 4), ([3, 9, 10, 11, 4], 5)]
+        for qs, k in blocks:                 # one staged pass (tile 0..11)
+            sv.apply_fused(h, qs, W.random_unitary(1 << k, rng), "c64")
+        sv.sync_state(h)
+        sv.apply_fused(h, [5, 13, 15], W.random_unitary(8, rng), "c64")    # single VALU sweep
+        sv.sync_state(h)
+        p = sv.sweep_profile(h)
+        assert p["staged"]["count"] == 1 and p["sweep"]["count"] == 1
+        assert p["staged"]["flops"] == 6.0 * (32 + 16 + 32) * (1 << n)
+        assert p["sweep"]["flops"] == 8.0 * 8 * (1 << n)
+        assert p["staged"]["ms"] > 0 and p["sweep"]["ms"] > 0
+        q = sv.sweep_profile(h)              # reset by the previous call
+        assert q["staged"]["count"] == 0 and q["sweep"]["count"] == 0
+    finally:
+        sv.destroy_state(h)
