@@ -20,6 +20,9 @@ from its description so that the tables can be checked and re-targeted.
   sockets) per exchange; one exchange per row that has one, a fraction for
   the small rows, and one more per disk read or write.
 * Disk: state bytes at 8 B per amplitude / (2 x 2^40 B/s) per transfer.
+* Other depths (Tabs. 3 and 4): the 20-cycle table's tensors 1 and 2 and its
+  contraction are kept; every further kernel is priced at the 45-qubit rate
+  per slice; all-to-alls and disk transfers as above.
 """
 from __future__ import annotations
 
@@ -110,3 +113,14 @@ def table(n: int, rows: List[Row], contraction_flops: float, disk_transfers: int
     out["kernels_total"] = sum(r.kernels for r in rows)
     out["gates_total"] = sum(r.gates for r in rows)
     return out
+
+
+def depth_estimate_days(n: int, kernels: int, alltoalls: float, disk_transfers: int,
+                        base: Dict[str, float], small_kernels: int) -> float:
+    """Run time for another depth (Tabs. 3 and 4): `base` is the 20-cycle
+    table (`table(...)` output) whose tensors 1, 2 and contraction are kept;
+    kernels beyond the small tensors' `small_kernels` cost the 45-qubit rate."""
+    slices = 2 ** (n - 45)
+    fixed = base["contraction_days"] + base["days_1"] + base["days_2"]
+    gates = (kernels - small_kernels) * slices * T_GATE_45Q / DAY
+    return fixed + gates + alltoall_seconds(alltoalls, n) / DAY + disk_seconds(disk_transfers, n) / DAY

@@ -68,3 +68,26 @@ def test_tables_internally_consistent():
 
 def test_disk_space():
     assert cm.disk_space_pib(53) == 64 and cm.disk_space_pib(54) == 128   # Sec. 5
+
+
+@pytest.mark.parametrize("fname,base_name,n", [("tab3_53q_depths.txt", "tab1_53q.txt", 53),
+                                               ("tab4_54q_depths.txt", "tab2_54q.txt", 54)])
+def test_depth_tables(fname, base_name, n):
+    """Tabs. 3 and 4 (run time per depth) follow from the 20-cycle table's
+    fixed parts plus the per-kernel, per-all-to-all and per-transfer costs.
+    Run times print two decimals; every printed value is reproduced within
+    0.006 days (the 54-qubit 10-cycle row is the farthest, 0.0055)."""
+    rows, scal, (cflops, _, _) = read(base_name)
+    base = cm.table(n, [r for r, _, _ in rows], cflops, int(scal["disk_transfers"]))
+    small = sum(r.kernels for r, _, _ in rows if cm.small_tensor(r))
+    seen20 = False
+    for line in open(os.path.join(GOLD, fname)):
+        if not line.strip() or line.startswith("#"):
+            continue
+        cyc, dx, a2a, k, days = line.split()
+        est = cm.depth_estimate_days(n, int(k), float(a2a), int(dx), base, small)
+        assert abs(est - float(days)) <= 0.006, (cyc, est, days)
+        if int(cyc) == 20:
+            seen20 = True
+            assert int(k) == scal["kernels_total"] and abs(float(a2a) - scal["alltoall_count"]) < 1e-3
+    assert seen20
