@@ -125,10 +125,48 @@ def cpu_baseline(circuit, budget_s: float = 15.0):
             break
     t = time.perf_counter() - t0
     del psi
+    host = host_info()
     return {"value": done * float(1 << n) / t, "unit": "amp-updates/s", "cores": orc.threads(),
             "kind": "oracle",
             "sample": f"first {done} of {len(circuit.gates)} gates of the same {n}-qubit circuit "
-                      f"on the full 2^{n} complex128 state ({t:.1f} s)"}
+                      f"on the full 2^{n} complex128 state ({t:.1f} s)",
+            "host": host,
+            # a per-gate sweep reads and writes 32 B per complex128 amplitude
+            "host_copy_bound_amp_updates_per_s": host["copy_GBps"] * 1e9 / 32.0}
+
+
+def host_info():
+    """CPU model, logical CPUs and a STREAM-like copy rate (1 GiB, one
+    numpy copy per logical CPU in parallel, best of 3) of the machine the
+    oracle runs on."""
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    from concurrent.futures import ThreadPoolExecutor
+    a = np.ones(1 << 27, dtype=np.float64)        # 1 GiB
+    b = np.empty_like(a)
+    nt = os.cpu_count() or 1
+    step = -(-a.size // nt)
+    spans = [(i, min(i + step, a.size)) for i in range(0, a.size, step)]
+
+    def part(sp):
+        np.copyto(b[sp[0]:sp[1]], a[sp[0]:sp[1]])
+
+    best = float("inf")
+    with ThreadPoolExecutor(nt) as ex:
+        for _ in range(3):
+            t0 = time.perf_counter()
+            list(ex.map(part, spans))
+            best = min(best, time.perf_counter() - t0)
+    gbps = 2 * a.nbytes / best / 1e9               # read + write
+    del a, b
+    return {"cpu_model": model, "logical_cpus": os.cpu_count(), "copy_GBps": round(gbps, 1)}
 
 
 def main(argv=None) -> int:
@@ -258,6 +296,7 @@ def main(argv=None) -> int:
                    "bitstrings": int(bits.size), "blocks": ndense, "hbm_passes": passes,
                    "k_hist": pst["k_hist"]},
         "hbm_frac_run": round(run_hbm_frac, 4),
+        "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,
         "cpu_baseline": cpu,
