@@ -401,7 +401,7 @@ def bench_batch(args) -> int:
     tuned = autotune.tune(sorted({c.n for c in circs}))
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plans = [planner.plan(c.gates, tuned["kmax"][c.n]) for c in circs]
+    plans = [planner.plan(c.gates, tuned["kmax"][c.n], staged=False) for c in circs]
     for p in plans:
         for o in p:
             o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)

@@ -63,7 +63,7 @@ def tune(ns: Iterable[int] = range(20, 29), ks=(3, 4, 5, 6), depth: int = 15) ->
         circ = W.sycamore_circuit(n, depth, seed=777)
         costs = {}
         for kk in ks:
-            ops = planner.plan(circ.gates, kk)
+            ops = planner.plan(circ.gates, kk, staged=False)
             costs[kk] = sum(t[len(o.qubits)] for o in ops if o.kind == "dense")
         kmax[n] = min(costs, key=costs.get)
     return {"kmax": kmax, "mfma_min_k": mfma_min, "sweep_ms": table}

@@ -8,7 +8,7 @@
 // target positions, together with positions 0..3, fit in t <= 12 tile
 // positions P[0] < ... < P[t-1] (P[0..3] = 0..3; free low positions widen
 // the tile to 12).  A tile is the 2^t amplitudes whose other bits equal the
-// tile id.  A persistent workgroup (2^kLaneBits lanes) loops over tiles:
+// tile id.  A persistent workgroup (256 lanes) loops over tiles:
 //   1. the next tile's loads are issued (into registers);
 //   2. each block runs on the LDS tile: pairs of 16-group units per wave
 //      through the three real products of the matrix-core form
@@ -28,16 +28,11 @@ namespace sv {
 constexpr int kStageMaxOps = 8;
 constexpr int kStageMaxT = 12;
 constexpr int kStageMaxLds = 80 * 1024;     // two workgroups per CU
-#ifndef SV_STAGE_LANE_BITS
-#define SV_STAGE_LANE_BITS 8
-#endif
-constexpr int kLaneBits = SV_STAGE_LANE_BITS;    // workgroup = 2^kLaneBits lanes
-constexpr int kNT = 1 << kLaneBits;
 
 struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
     uint64_t tile_lowmask[kStageMaxT];       // (1 << P[b]) - 1, ascending (tile-id spreading)
-    uint64_t dep_lane[9];                    // global offset of element bit b (lane bits, b < kLaneBits)
+    uint64_t dep_lane[8];                    // global offset of element bit b (lane bits, b < 8)
     uint64_t dep_i[16];                      // global offset of element bits 8.. (i = e >> 8)
     int t;
     int nops;
@@ -189,9 +184,9 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
 // (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
 // per-lane offset, so loads and stores take the scalar-base form).
 template <int TW, bool WIDE>
-__global__ __launch_bounds__(kNT) void k_stage(float2* __restrict__ psi, StageK a)
+__global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK a)
 {
-    constexpr int PER = 1 << (TW - kLaneBits);
+    constexpr int PER = 1 << (TW - 8);
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
     f4* Abase = smem + ((lslot(1 << TW) * 8 + 15) / 16);          // operand matrices
@@ -211,7 +206,7 @@ __global__ __launch_bounds__(kNT) void k_stage(float2* __restrict__ psi, StageK 
         }
     }
     uint64_t dl = 0;
-    for (int b = 0; b < kLaneBits; ++b)
+    for (int b = 0; b < 8; ++b)
         if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
     const uint32_t dlb = (uint32_t)(dl * sizeof(float2));       // used when !WIDE
     // element i of this lane in the tile at uniform index base tb
@@ -227,8 +222,7 @@ __global__ __launch_bounds__(kNT) void k_stage(float2* __restrict__ psi, StageK 
         }
         return base;
     };
-    constexpr int LS = kNT + kNT / 16;                          // lslot(kNT i) = LS i
-    const int ls = lslot(threadIdx.x);
+    const int ls = lslot(threadIdx.x);                          // + lslot(256 i) = 272 i
     float2 xr[PER];
     uint64_t tile = blockIdx.x;
     if (tile < a.tiles) {
@@ -236,7 +230,7 @@ __global__ __launch_bounds__(kNT) void k_stage(float2* __restrict__ psi, StageK 
 #pragma unroll
         for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
 #pragma unroll
-        for (int i = 0; i < PER; ++i) T[ls + LS * i] = xr[i];
+        for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
     }
     __syncthreads();
     // Per tile: issue the next tile's loads, run the blocks on the LDS tile,
@@ -258,11 +252,11 @@ __global__ __launch_bounds__(kNT) void k_stage(float2* __restrict__ psi, StageK 
             __syncthreads();
         }
 #pragma unroll
-        for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + LS * i];
+        for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + 272 * i];
         __syncthreads();
         if (next) {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) T[ls + LS * i] = xr[i];
+            for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
         }
         __syncthreads();
     }
@@ -310,11 +304,11 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.nops = nops;
     a.tiles = 1ull << (nloc - t);
     for (int b = 0; b < t; ++b) a.tile_lowmask[b] = (1ull << P[b]) - 1;
-    for (int b = 0; b < kLaneBits; ++b) a.dep_lane[b] = 1ull << P[b];
-    for (int i = 0; i < (1 << (t - kLaneBits)); ++i) {
+    for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
+    for (int i = 0; i < (1 << (t - 8)); ++i) {
         uint64_t d = 0;
-        for (int b = kLaneBits; b < t; ++b)
-            if ((i >> (b - kLaneBits)) & 1) d |= 1ull << P[b];
+        for (int b = 8; b < t; ++b)
+            if ((i >> (b - 8)) & 1) d |= 1ull << P[b];
         a.dep_i[i] = d;
     }
     int aoff = 0;
@@ -340,7 +334,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     if (lds > kStageMaxLds) return hipErrorInvalidValue;
     // byte offset of the lane part of an element address
     uint64_t dl_max = 0;
-    for (int b = 0; b < kLaneBits; ++b) dl_max |= a.dep_lane[b];
+    for (int b = 0; b < 8; ++b) dl_max |= a.dep_lane[b];
     const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
     void (*kern)(float2*, StageK) = nullptr;
     switch (t * 2 + (wide ? 1 : 0)) {
@@ -369,7 +363,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t grid = a.tiles;
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kNT), lds, st, (float2*)psi, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     return hipGetLastError();
 }

@@ -160,7 +160,7 @@ def fuse(gates, kmax: int, fold_diag: bool = False) -> List[Op]:
     return ops
 
 
-def fuse_grow(gates, kmax: int, window: int = 4) -> List[Op]:
+def fuse_grow(gates, kmax: int, window: int = 4, last_gain: float = 0.0) -> List[Op]:
     """Aggregation by growing qubit sets (Sec. 5 aggregate gates, clusters that
     span several depths as in the appendix listing's cache rows).
 
@@ -171,7 +171,12 @@ def fuse_grow(gates, kmax: int, window: int = 4) -> List[Op]:
     the set, up to kmax qubits; then emit one block holding every pending
     gate that lies inside the set and whose predecessors on each of its
     qubits are already applied (its causal closure within the set).  Per
-    qubit, gates keep their order, so the product is unchanged."""
+    qubit, gates keep their order, so the product is unchanged.
+
+    last_gain > 0: the last qubit (growing to kmax) is only added when it
+    raises the block's gate weight by that fraction or more; a kmax block
+    costs twice the arithmetic of a kmax-1 block, so one that absorbs few
+    more gates is not worth it when the passes are compute bound."""
     ng = len(gates)
     qs_of = [tuple(g.qubits) for g in gates]
     per_q: Dict[int, List[int]] = {}
@@ -224,6 +229,9 @@ def fuse_grow(gates, kmax: int, window: int = 4) -> List[Op]:
                 scored.append((w, -c, c, cl))
             scored.sort(reverse=True)
             w, _, c, cl = scored[0]
+            if last_gain > 0 and len(Q) == kmax - 1 and \
+                    w < (1.0 + last_gain) * sum(len(qs_of[i]) for i in best):
+                break
             Q.append(c)
             best = cl
         # emit the block
@@ -349,11 +357,16 @@ def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> 
 
 
 # Modelled device time (ms per 2^30 complex64 amplitudes) of a single sweep
-# of a k-qubit block, and of a staged pass: a fixed part plus a part per
-# block.  Only the ranking of candidate plans uses these figures.
-SWEEP_MS = {1: 2.9, 2: 2.9, 3: 3.4, 4: 3.55, 5: 3.6, 6: 3.7}
-STAGE_MS_FIXED = 1.5
-STAGE_MS_BLOCK = {4: 1.15, 5: 1.7}
+# of a k-qubit block, and of a staged pass: the larger of its memory time
+# and a fixed part plus the blocks' matrix-core work (the vector and matrix
+# units do not overlap, so a pass with several blocks is compute bound).
+# Only the ranking of candidate plans uses these figures.
+# (Fitted to measured 30-qubit step times of 31 aggregations: per staged
+# pass 1.475 ms, per 5-qubit block 1.78, per 4-qubit block 1.10.)
+SWEEP_MS = {1: 2.9, 2: 2.9, 3: 3.4, 4: 3.5, 5: 3.57, 6: 3.7}
+STAGE_MS_MEM = 3.35
+STAGE_MS_FIXED = 1.475
+STAGE_MS_BLOCK = {4: 1.10, 5: 1.78}
 
 
 def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> float:
@@ -362,11 +375,36 @@ def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> float:
     tot = 0.0
     for r in stage_runs(ops, pos_of, tmax):
         if len(r) >= 2:
-            tot += STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r)
+            tot += max(STAGE_MS_MEM, STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r))
         else:
             o = ops[r[0]]
             tot += SWEEP_MS.get(len(o.qubits), 4.0) if o.kind == "dense" else SWEEP_MS[1]
     return tot
+
+
+def widen_small_blocks(ops: Sequence["Op"], pos_of=None) -> List["Op"]:
+    """Dense blocks on fewer than 4 qubits become 4-qubit blocks (identity on
+    the added qubits, exact) by adding the qubits at positions 0..3, which
+    every staged tile holds anyway: they can then join staged passes."""
+    pos = (lambda q: q) if pos_of is None else pos_of
+    where = {}
+    for o in ops:
+        for q in o.qubits:
+            where[pos(q)] = q
+    out: List[Op] = []
+    for o in ops:
+        if o.kind != "dense" or len(o.qubits) >= 4:
+            out.append(o)
+            continue
+        extra = [where[p] for p in range(4) if p in where and where[p] not in o.qubits]
+        extra = extra[:4 - len(o.qubits)]
+        if len(o.qubits) + len(extra) < 4:
+            out.append(o)
+            continue
+        qs = tuple(o.qubits) + tuple(extra)
+        m = embed_in(qs, o.qubits, np.asarray(o.matrix, dtype=np.complex128))
+        out.append(Op("dense", qs, m, ngates=o.ngates))
+    return out
 
 
 def plan_cost(ops: Sequence[Op]) -> float:
@@ -378,16 +416,22 @@ def plan_cost(ops: Sequence[Op]) -> float:
 def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None) -> List[Op]:
     """Aggregate with every available heuristic and keep the cheapest plan.
 
-    staged: order commuting blocks for staged passes (`order_for_staging`,
-    positions given by pos_of, default position = qubit) and rank the
-    candidates by `staged_cost`; otherwise rank by `plan_cost`."""
+    staged (complex64 states): blocks on fewer than 4 qubits are widened to
+    4 (`widen_small_blocks`), commuting blocks are ordered for staged passes
+    (`order_for_staging`; positions given by pos_of, default position =
+    qubit) and the candidates are ranked by `staged_cost`; otherwise they
+    are ranked by `plan_cost`."""
     cands = [fuse(gates, kmax, fold_diag=fold_diag)]
     if not fold_diag:
         for w in (3, 4, 5, 6, 8):
             cands.append(fuse_grow(gates, kmax, window=w))
     if not staged or fold_diag:
         return min(cands, key=plan_cost)
-    cands = [order_for_staging(c, pos_of) for c in cands]
+    if kmax >= 3:
+        for w in (3, 4, 5, 6, 8):
+            for g in (0.2, 0.4, 0.6, 0.8, 1.0):
+                cands.append(fuse_grow(gates, kmax, window=w, last_gain=g))
+    cands = [order_for_staging(widen_small_blocks(c, pos_of), pos_of) for c in cands]
     return min(cands, key=lambda c: staged_cost(c, pos_of))
 
 

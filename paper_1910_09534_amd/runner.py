@@ -20,7 +20,7 @@ from . import planner, sv
 def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: bool = False,
              timing: bool = False, mfma: int = 4, stream=None) -> Dict[str, object]:
     t0 = time.perf_counter()
-    ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag)
+    ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag, staged=(dtype == "c64"))
     t_plan = time.perf_counter() - t0
     st = sv.State(circuit.n, 0, dtype, stream)
     try:
@@ -97,7 +97,7 @@ def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: boo
     mof = (lambda n: mfma_min_k[n]) if isinstance(mfma_min_k, dict) else (lambda n: mfma_min_k)
     t0 = time.perf_counter()
     if plans is None:
-        plans = [planner.plan(c.gates, kof(c.n)) for c in circuits]
+        plans = [planner.plan(c.gates, kof(c.n), staged=False) for c in circuits]
     t_plan = time.perf_counter() - t0
     states = []
     b = None

@@ -30,7 +30,7 @@ def test_batch_equals_alone_and_oracle(graph):
     _gpu()
     circs, bits = _batch()
     kmax = {n: (4 if n % 2 else 5) for n in range(12, 21)}
-    plans = [planner.plan(c.gates, kmax[c.n]) for c in circs]
+    plans = [planner.plan(c.gates, kmax[c.n], staged=False) for c in circs]
     res = runner.run_batch(circs, bits, "c64", kmax=kmax, graph=graph, repeats=2, plans=plans)
     assert res["info"]["graph"] == graph
     for c, b, amps, p in zip(circs, bits, res["amps"], plans):
