@@ -158,7 +158,9 @@ int sync_state(sv_handle h);
 
 /* sv_reset -- drop queued operations and set the state back to |0...0>
    (the layout is kept; |0...0> is index 0 in every layout).  Reuses the
-   handle's memory: nothing is allocated.  */
+   handle's memory: nothing is allocated.  For a resident state the write
+   is deferred: the first staged pass builds its input from |0...0>
+   without reading HBM, and any other first use writes |0...0> first. */
 int sv_reset(sv_handle h);
 
 /* last_error -- text of the most recent failure on h (or of the last failed

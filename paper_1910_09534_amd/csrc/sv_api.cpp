@@ -149,6 +149,18 @@ static double block_flops_per_amp(int dtype, int k, int nloc, int mfma_min_k)
     return 8.0 * d;
 }
 
+// ---- deferred reset --------------------------------------------------------
+// sv_reset leaves a resident state marked |0...0> without writing it; the
+// first staged pass then builds its tiles from |0...0> instead of reading
+// HBM, and anything else that needs the amplitudes writes them first.
+int materialize_state(sv_state* h)
+{
+    if (!h->e0_pending) return SV_OK;
+    h->e0_pending = false;
+    TRY(h, launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << h->n, true));
+    return SV_OK;
+}
+
 // ---- running the queue over one range of amplitudes ----------------------
 // psi: 2^nloc amplitudes whose global index starts at idx_offset.
 int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset)
@@ -187,6 +199,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 ++j;
             }
             if (cnt >= 2) {
+                const bool from_e0 = h->e0_pending && i == 0 && !h->tier;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (h->timing) {
                     e0 = next_event(h);
@@ -195,7 +208,8 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                     TRY(h, hipEventRecord(e0, st));
                 }
                 int tused = 0;
-                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, &tused));
+                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, from_e0, &tused));
+                h->e0_pending = false;
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
                     double f = 0.0;
@@ -208,6 +222,10 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 i = j - 1;
                 continue;
             }
+        }
+        if (h->e0_pending) {
+            const int rc = materialize_state(h);
+            if (rc) return rc;
         }
         if (op.kind == OP_DENSE) {
             DiagSpec fold;
@@ -611,7 +629,7 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
 
 int flush(sv_state* h)
 {
-    if (h->ops.empty()) return SV_OK;
+    if (h->ops.empty()) return materialize_state(h);
     int rc = upload_arena(h);
     if (rc) return rc;
     if (!h->tier) {
@@ -1163,7 +1181,7 @@ int sv_reset(sv_handle h)
     h->ops.clear();
     h->arena.clear();
     if (!h->tier) {
-        TRY(h, launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << h->n, true));
+        h->e0_pending = true;        // written by the first pass or on demand
         return SV_OK;
     }
     TRY(h, hipStreamSynchronize(h->stream));
@@ -1199,6 +1217,11 @@ int sv_get_order(sv_handle h, int* order)
 int sv_device_buffer(sv_handle h, void** dev, size_t* bytes)
 {
     if (!h || !dev || !bytes) return SV_EINVAL;
+    CHECK_HANDLE(h);
+    {
+        const int rc = materialize_state(h);
+        if (rc) return rc;
+    }
     *dev = h->tier ? nullptr : h->dev;
     *bytes = h->tier ? 0 : ((size_t)1 << h->n) * h->amp;
     return SV_OK;
@@ -1262,3 +1285,8 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
 }
 
 }  // extern "C"
+
+int sv::materialize_e0(sv_state* h)
+{
+    return materialize_state(h);
+}

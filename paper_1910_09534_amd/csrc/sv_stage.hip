@@ -28,6 +28,7 @@ namespace sv {
 constexpr int kStageMaxOps = 8;
 constexpr int kStageMaxT = 12;
 constexpr int kStageMaxLds = 80 * 1024;     // two workgroups per CU
+constexpr int kStageThreads = 256;          // lanes per workgroup (four waves)
 
 struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
@@ -36,6 +37,7 @@ struct StageK {
     uint64_t dep_i[16];                      // global offset of element bits 8.. (i = e >> 8)
     int t;
     int nops;
+    int from_e0;                             // 1: input is |0...0>, not read
     int op_k[kStageMaxOps];
     int op_bits[kStageMaxOps][kMaxDense];    // tile-local bit of matrix bit j
     int op_lowmask_bits[kStageMaxOps][kMaxDense];  // the same bits, ascending
@@ -118,12 +120,12 @@ __device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][
 
 template <int K>
 __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __restrict__ As,
-                                            float2* __restrict__ T)
+                                            float2* __restrict__ T, int wave)
 {
     using S = MfmaShape<K>;
     constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
     const int lane = threadIdx.x & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nw = blockDim.x >> 6;
+    constexpr int nw = kStageThreads / 64;
     const int j = lane & 15, h = lane >> 4;
     int bit[K], low[K];
 #pragma unroll
@@ -184,11 +186,12 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
 // (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
 // per-lane offset, so loads and stores take the scalar-base form).
 template <int TW, bool WIDE>
-__global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK a)
+__global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ psi, StageK a)
 {
     constexpr int PER = 1 << (TW - 8);
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     f4* Abase = smem + ((lslot(1 << TW) * 8 + 15) / 16);          // operand matrices
     // stage every block's three real matrices in operand order
     for (int o = 0; o < a.nops; ++o) {
@@ -196,7 +199,7 @@ __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK 
         const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 2 * RB * KQ * 256;
         float* dst = (float*)(Abase) + a.op_aoff[o];
         const float2* mat = a.op_mat[o];
-        for (int i = threadIdx.x; i < NA; i += blockDim.x) {
+        for (int i = threadIdx.x; i < NA; i += kStageThreads) {
             const int s4 = i & 3, l = (i >> 2) & 63, blk = i >> 8;
             const int sq = blk % KQ, rb = (blk / KQ) % RB, p = blk / (KQ * RB);
             const int R = 16 * rb + (l & 15);
@@ -224,11 +227,21 @@ __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK 
     };
     const int ls = lslot(threadIdx.x);                          // + lslot(256 i) = 272 i
     float2 xr[PER];
+    // |0...0>: only element 0 of tile 0 (lane 0, i = 0) is non-zero
+    auto load_tile = [&](uint64_t tile) {
+        if (a.from_e0) {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) xr[i] = float2{0.f, 0.f};
+            if (tile == 0 && threadIdx.x == 0) xr[0].x = 1.f;
+        } else {
+            const uint64_t tb = tile_base(tile);
+#pragma unroll
+            for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
+        }
+    };
     uint64_t tile = blockIdx.x;
     if (tile < a.tiles) {
-        const uint64_t tb = tile_base(tile);
-#pragma unroll
-        for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
+        load_tile(tile);
 #pragma unroll
         for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
     }
@@ -240,15 +253,11 @@ __global__ __launch_bounds__(256) void k_stage(float2* __restrict__ psi, StageK 
         const uint64_t tb = tile_base(tile);
         const uint64_t nt = tile + gridDim.x;
         const bool next = nt < a.tiles;
-        if (next) {
-            const uint64_t nb = tile_base(nt);
-#pragma unroll
-            for (int i = 0; i < PER; ++i) xr[i] = *elem(nb, i);
-        }
+        if (next) load_tile(nt);
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
-            if (a.op_k[o] == 5) stage_block<5>(a, o, As, T);
-            else stage_block<4>(a, o, As, T);
+            if (a.op_k[o] == 5) stage_block<5>(a, o, As, T, wave);
+            else stage_block<4>(a, o, As, T, wave);
             __syncthreads();
         }
 #pragma unroll
@@ -272,7 +281,7 @@ int stage_lds_bytes(int t, int nops, const int* ks)
 }
 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int t_max, int* t_out)
+                        const void* const* mats, int t_max, bool from_e0, int* t_out)
 {
     if (t_max > kStageMaxT) t_max = kStageMaxT;
     if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
@@ -302,6 +311,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     StageK a{};
     a.t = t;
     a.nops = nops;
+    a.from_e0 = from_e0 ? 1 : 0;
     a.tiles = 1ull << (nloc - t);
     for (int b = 0; b < t; ++b) a.tile_lowmask[b] = (1ull << P[b]) - 1;
     for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
@@ -363,7 +373,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t grid = a.tiles;
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(256), lds, st, (float2*)psi, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kStageThreads), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     return hipGetLastError();
 }

@@ -23,6 +23,10 @@ struct Op {
     BitRuns runs;              // OP_LPERM: destination -> source over local bits
 };
 
+// Writes |0...0> into a resident state whose reset was deferred (no-op
+// otherwise); on the handle's stream.
+int materialize_e0(sv_state* h);
+
 }  // namespace sv
 
 struct sv_state {
@@ -72,6 +76,7 @@ struct sv_state {
     bool timing = false, fold = true;
     int mfma_min_k = 4;
     int stage_t = 12;
+    bool e0_pending = false;     // resident state is |0...0> but not yet written (sv_reset)
     int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;

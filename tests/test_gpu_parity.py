@@ -312,3 +312,36 @@ def test_sweep_profile_splits_kinds():
         assert q["staged"]["count"] == 0 and q["sweep"]["count"] == 0
     finally:
         sv.destroy_state(h)
+
+
+@pytest.mark.parametrize("first", ["staged", "single", "read"])
+def test_deferred_reset(first):
+    """sv_reset defers writing |0...0>: a first staged pass builds its input
+    from |0...0> without reading HBM, any other first use writes it first.
+    The state is dirtied before the reset so a skipped write would show."""
+    n = 14
+    rng = np.random.default_rng(11)
+    h, t = state_from_numpy(W.random_state(n, rng), "c64")
+    try:
+        for _ in range(3):                       # several resets in a row
+            sv.reset(h)
+            ops = []
+            if first == "staged":
+                ops = [([4, 5, 6, 7, 8], W.random_unitary(32, rng)), ([6, 7, 8, 9], W.random_unitary(16, rng)),
+                       ([9, 10, 11, 4], W.random_unitary(16, rng))]
+            elif first == "single":
+                ops = [([5, 11], W.random_unitary(4, rng)), ([4, 5, 6, 7, 8], W.random_unitary(32, rng))]
+            for qs, u in ops:
+                sv.apply_fused(h, qs, u, "c64")
+            got = read_all(h, n)
+            ref = orc.zero_state(n)
+            for qs, u in ops:
+                orc.apply_dense(ref, qs, u)
+            assert orc.rel_l2(got, ref) <= 1e-5
+            # dirty the buffer again for the next round
+            sv.apply_fused(h, [0, 1, 2], W.random_unitary(8, rng), "c64")
+            sv.sync_state(h)
+        if first == "staged":
+            assert sv.counters(h)["staged_blocks"] >= 9
+    finally:
+        sv.destroy_state(h)
