@@ -163,8 +163,13 @@ int materialize_state(sv_state* h)
 
 // ---- running the queue over one range of amplitudes ----------------------
 // psi: 2^nloc amplitudes whose global index starts at idx_offset.
-int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset)
+// norm_out (resident states): when the queue ends with a staged run, that
+// pass also writes per-workgroup FP64 sums of |psi|^2 there and
+// *norm_blocks receives their count (else 0).
+int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64_t idx_offset,
+            double* norm_out = nullptr, int* norm_blocks = nullptr)
 {
+    if (norm_blocks) *norm_blocks = 0;
     const char* dbase = (const char*)h->d_arena;
     const size_t nops = h->ops.size();
     for (size_t i = 0; i < nops; ++i) {
@@ -198,7 +203,9 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 ++cnt;
                 ++j;
             }
-            if (cnt >= 2) {
+            // a single block goes through a staged pass only when it is the
+            // queue's last op and the pass also sums the norm (saving a read)
+            if (cnt >= 2 || (cnt == 1 && j == nops && norm_out != nullptr)) {
                 const bool from_e0 = h->e0_pending && i == 0 && !h->tier;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (h->timing) {
@@ -208,7 +215,9 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                     TRY(h, hipEventRecord(e0, st));
                 }
                 int tused = 0;
-                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, from_e0, &tused));
+                const bool last = j == nops && norm_out != nullptr;
+                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, from_e0,
+                                    last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused));
                 h->e0_pending = false;
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
@@ -627,14 +636,15 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
     return tier_pass_pageable(h, write_back, std::forward<F>(visit));
 }
 
-int flush(sv_state* h)
+int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr)
 {
+    if (norm_blocks) *norm_blocks = 0;
     if (h->ops.empty()) return materialize_state(h);
     int rc = upload_arena(h);
     if (rc) return rc;
     if (!h->tier) {
         void* cur = h->dev;
-        rc = run_ops(h, h->stream, &cur, h->scratch, h->n, 0);
+        rc = run_ops(h, h->stream, &cur, h->scratch, h->n, 0, norm_out, norm_blocks);
         if (rc) return rc;
         if (cur != h->dev) return set_err(h, SV_EDEVICE, "internal: permute left in scratch");
     } else {
@@ -894,6 +904,7 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
     TRY(h, hipMemcpyAsync(h->d_rowmap, rowmap.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
     if (T) TRY(h, hipMemcpyAsync(h->d_tcol, tcols.data(), tcols.size() * 8, hipMemcpyHostToDevice, st));
     TRY(h, hipMemsetAsync(d_snorm, 0, (size_t)ns * 8, st));
+    int folded_blocks = 0;
     // nothing below synchronises the host per slice: the tier pipeline keeps
     // staging the next slice while this one is reduced
     auto visit = [&](int t, const void* slice_buf) -> int {
@@ -902,14 +913,16 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
                                  (const uint64_t*)h->d_bits, tc, (const int*)h->d_rowmap,
                                  (double*)h->d_acc));
         if (stats) {
-            int nb = 0;
-            TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)h->d_part, &nb));
+            int nb = folded_blocks;      // partials already written by the last staged pass
+            if (nb == 0)
+                TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)h->d_part, &nb));
             TRY(h, launch_finish_sum(st, (const double*)h->d_part, nb, 1, d_snorm + t));
         }
         return SV_OK;
     };
     if (!h->tier) {
-        rc = flush(h);
+        // unsliced: the norm rides on the queue's last staged pass when it has one
+        rc = (stats && ns == 1) ? flush(h, (double*)h->d_part, &folded_blocks) : flush(h);
         if (rc) return rc;
         for (int t = 0; t < ns && !rc; ++t)
             rc = visit(t, (const char*)h->dev + ((size_t)t << h->L) * h->amp);

@@ -102,10 +102,14 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // low positions up to t_max (<= 12) within the LDS budget.  Fails
 // (hipErrorInvalidValue) when the targets alone exceed t_max positions or
 // the LDS budget; *t_out receives the tile width used.  from_e0: the input
-// is |0...0> and is not read (the pass writes every amplitude).
+// is |0...0> and is not read (the pass writes every amplitude).  norm_out
+// (non-null): each workgroup writes the FP64 sum of |psi|^2 of the amplitudes
+// it wrote to norm_out[workgroup]; *norm_blocks receives the workgroup count
+// (at most 1024).
 int stage_lds_bytes(int t, int nops, const int* ks);
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int t_max, bool from_e0, int* t_out);
+                        const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
+                        int* t_out);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
 hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,

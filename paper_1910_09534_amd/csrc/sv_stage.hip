@@ -38,6 +38,7 @@ struct StageK {
     int t;
     int nops;
     int from_e0;                             // 1: input is |0...0>, not read
+    double* norm_out;                        // non-null: per-workgroup FP64 sum of |psi|^2 of the result
     int op_k[kStageMaxOps];
     int op_bits[kStageMaxOps][kMaxDense];    // tile-local bit of matrix bit j
     int op_lowmask_bits[kStageMaxOps][kMaxDense];  // the same bits, ascending
@@ -239,6 +240,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
             for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
         }
     };
+    double nacc = 0.0;                                           // this lane's sum of |psi|^2
     uint64_t tile = blockIdx.x;
     if (tile < a.tiles) {
         load_tile(tile);
@@ -260,14 +262,35 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
             else stage_block<4>(a, o, As, T, wave);
             __syncthreads();
         }
+        if (a.norm_out) {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + 272 * i];
+            for (int i = 0; i < PER; ++i) {
+                const float2 v = T[ls + 272 * i];
+                *elem(tb, i) = v;
+                nacc = fma((double)v.x, (double)v.x, nacc);
+                nacc = fma((double)v.y, (double)v.y, nacc);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + 272 * i];
+        }
         __syncthreads();
         if (next) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
         }
         __syncthreads();
+    }
+    if (a.norm_out) {
+        // fixed-order tree over the workgroup's lanes (the tile buffer is free)
+        double* sh = (double*)smem;
+        sh[threadIdx.x] = nacc;
+        __syncthreads();
+        for (int h = kStageThreads / 2; h > 0; h >>= 1) {
+            if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.norm_out[blockIdx.x] = sh[0];
     }
 }
 
@@ -281,7 +304,8 @@ int stage_lds_bytes(int t, int nops, const int* ks)
 }
 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int t_max, bool from_e0, int* t_out)
+                        const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
+                        int* t_out)
 {
     if (t_max > kStageMaxT) t_max = kStageMaxT;
     if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
@@ -312,6 +336,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.t = t;
     a.nops = nops;
     a.from_e0 = from_e0 ? 1 : 0;
+    a.norm_out = norm_out;
     a.tiles = 1ull << (nloc - t);
     for (int b = 0; b < t; ++b) a.tile_lowmask[b] = (1ull << P[b]) - 1;
     for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
@@ -375,6 +400,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     if (grid > cap) grid = cap;
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kStageThreads), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
+    if (norm_blocks) *norm_blocks = norm_out ? (int)grid : 0;
     return hipGetLastError();
 }
 

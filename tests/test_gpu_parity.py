@@ -345,3 +345,34 @@ def test_deferred_reset(first):
             assert sv.counters(h)["staged_blocks"] >= 9
     finally:
         sv.destroy_state(h)
+
+
+@pytest.mark.parametrize("last", ["staged", "single", "single-dense"])
+def test_norm_folded_into_last_staged_pass(last):
+    """When the queue ends with a staged pass, that pass also sums |psi|^2
+    (FP64, per workgroup) and the reduction uses those sums; the norm and
+    the amplitudes equal the oracle's either way."""
+    n = 15
+    rng = np.random.default_rng({"staged": 21, "single": 22, "single-dense": 23}[last])
+    psi = W.random_state(n, rng)
+    h, t = state_from_numpy(psi, "c64")
+    ops = [([4, 5, 6, 7, 8], W.random_unitary(32, rng)), ([6, 7, 8, 9], W.random_unitary(16, rng)),
+           ([1, 9, 10, 14], W.random_unitary(16, rng))]
+    if last == "single":              # promoted to 4 qubits: a one-block staged pass
+        ops.append(([2, 13], W.random_unitary(4, rng)))
+    if last == "single-dense":        # 3 qubits above position 3: a plain sweep, norm read after
+        ops.append(([5, 11, 13], W.random_unitary(8, rng)))
+    try:
+        for qs, u in ops:
+            sv.apply_fused(h, qs, u, "c64")
+        bits = W.bitstrings(n, 512, seed=5)
+        amps, stats = sv.reduce_slices(h, bits)
+        ref = psi.astype(np.complex128).copy()
+        for qs, u in ops:
+            orc.apply_dense(ref, qs, u)
+        assert abs(stats[0] - orc.norm(ref)) <= 2e-6
+        assert orc.rel_l2(amps, orc.gather(ref, bits)) <= 1e-5
+        if last == "staged":
+            assert sv.counters(h)["staged_blocks"] >= 2
+    finally:
+        sv.destroy_state(h)
