@@ -56,8 +56,9 @@ def state_bytes(n: int) -> int:
 
 
 def plan_request(circuit, kmax: int):
-    """Single-heuristic plan (fast enough to sit inside the request path)."""
-    ops = planner.fuse_grow(circuit.gates, kmax, window=4)
+    """Single-heuristic staged plan (fast enough to sit inside the request
+    path): blocks ordered and widened for staged passes."""
+    ops = planner.plan_fast(circuit.gates, kmax)
     for o in ops:
         o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     return ops

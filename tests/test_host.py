@@ -45,7 +45,9 @@ def test_fusion_generic_asymmetric_gates():
     c = W.random_generic_circuit(9, 60, seed=4, max_arity=3)
     for kmax in (3, 4, 5):
         for ops in (planner.fuse(c.gates, kmax), planner.fuse_grow(c.gates, kmax),
-                    planner.plan(c.gates, kmax)):
+                    planner.plan(c.gates, kmax), planner.plan_fast(c.gates, kmax),
+                    planner.plan(c.gates, kmax, staged=False),
+                    planner.fuse_grow(c.gates, kmax, window=4, last_gain=0.5)):
             assert np.abs(apply_ops_on_oracle(9, ops) - orc.simulate(c)).max() < 1e-13
 
 
@@ -174,3 +176,24 @@ def test_sliced_36q_schedule_structure():
     for ph in sp.phases:
         assert not any(set(c.gates[i].qubits) & set(ph.sliced) for i in ph.gate_ids)
         assert all(max(o.qubits) < c.n and len(o.qubits) <= 5 for o in ph.ops)
+
+
+def test_staging_transforms_are_exact():
+    """Widening small blocks with low qubits and reordering for staged runs
+    keep the product (sequential application on the oracle), the order
+    respects every qubit's gate order, and the planner mirror of the device
+    run formation only groups 4/5-qubit blocks within the tile limits."""
+    c = W.sycamore_circuit(16, 12, seed=41)
+    for ops0 in (planner.fuse(c.gates, 3), planner.fuse_grow(c.gates, 5, window=4, last_gain=0.6)):
+        wide = planner.widen_small_blocks(ops0)
+        assert all(len(o.qubits) >= 4 for o in wide if o.kind == "dense")
+        ordered = planner.order_for_staging(wide)
+        ref = orc.simulate(c)
+        for ops in (wide, ordered):
+            assert np.abs(apply_ops_on_oracle(16, ops) - ref).max() < 1e-12
+        for run in planner.stage_runs(ordered):
+            if len(run) < 2:
+                continue
+            pos = set(range(4)) | {q for i in run for q in ordered[i].qubits}
+            assert len(pos) <= planner.STAGE_T and len(run) <= planner.STAGE_MAX_OPS
+            assert all(len(ordered[i].qubits) in (4, 5) for i in run)
