@@ -14,9 +14,11 @@ with the circuit already planned (host planning is not timed) and the state
 already allocated in HBM.
 
 roofline: the kernel kind with the most time in the timed steps (staged
-passes: matrix-core bound, flops = 6 2^k per amplitude per block, the
-three real products of the 3M form; single sweeps: HBM bound, 16 bytes per
-amplitude per launch), durations from HIP events on the kernels' stream;
+passes: matrix-core bound, algorithmic flops = 8 2^k - 2 per amplitude per
+block, the complex dot product; the kernels issue 6 2^k of them as the
+three real products of the 3M form, reported as issued_frac; single
+sweeps: HBM bound, 16 bytes per amplitude per launch), durations from HIP
+events on the kernels' stream;
 hbm_frac_run: HBM passes x 16 bytes x 2^n per step over the step time.
 
 value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
@@ -249,13 +251,15 @@ def main(argv=None) -> int:
             return None
         avg_ms = p["ms"] / p["count"]
         gbs = bytes_per_pass / (avg_ms * 1e-3) / 1e9
-        tflops = p["flops"] / (p["ms"] * 1e-3) / 1e12
+        tflops = p["flops"] / (p["ms"] * 1e-3) / 1e12          # algorithmic
+        issued = p["issued"] / (p["ms"] * 1e-3) / 1e12         # as executed (3M on the matrix cores)
         r = {"launches": p["count"], "avg_launch_ms": round(avg_ms, 4),
              "share_of_step": round(p["ms"] / (args.steps * ms_per_step), 4),
              "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": bytes_per_pass},
              "fp32": {"achieved_tflops": round(tflops, 2), "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
-                      "flops_per_launch": p["flops"] / p["count"]},
+                      "flops_per_launch": p["flops"] / p["count"],
+                      "issued_tflops": round(issued, 2), "issued_frac": round(issued / FP32_PEAK_TFLOPS, 4)},
              "traffic": counter_traffic(kind)}
         if kind == "staged":
             r.update({"kernel": "k_stage (staged pass: 2-5 dense 4/5-qubit blocks per HBM pass, matrix cores)",

@@ -205,11 +205,12 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
 
 /* sv_sweep_profile -- with SV_OPT_TIMING: the timed launches split by kind,
  * [0] single dense sweeps, [1] staged multi-block passes: total
- * milliseconds, launch count and the arithmetic the launches performed
- * (flops: 6 2^k per amplitude for a complex64 block on the matrix cores,
- * 8 2^k on the vector units, 32 2^k for complex128).  Resets the same
- * accumulators as sv_sweep_time.  Any pointer may be NULL. */
-int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2]);
+ * milliseconds, launch count, algorithmic flops (a k-qubit block is a
+ * complex 2^k-term dot product per amplitude: 8 2^k - 2 flops) and the
+ * flops the kernels issued (6 2^k per amplitude per complex64 block on the
+ * matrix cores, 3 real products; 8 2^k on the vector units).  Resets the
+ * same accumulators as sv_sweep_time.  Any pointer may be NULL. */
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2]);
 
 /* ---- batches of independent states ----------------------------------------
  * Many circuits of different qubit counts run as one recorded execution: the

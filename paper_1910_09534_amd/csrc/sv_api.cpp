@@ -130,19 +130,26 @@ int collect_timing(sv_state* h)
         h->t_ms += ms;
         h->t_count += 1;
         const auto& info = h->tev_info[i / 2];
-        h->tk_ms[info.first] += ms;
-        h->tk_count[info.first] += 1;
-        h->tk_flops[info.first] += info.second;
+        h->tk_ms[info.kind] += ms;
+        h->tk_count[info.kind] += 1;
+        h->tk_flops[info.kind] += info.flops;
+        h->tk_issued[info.kind] += info.issued;
     }
     h->tev_used = 0;
     h->tev_info.clear();
     return SV_OK;
 }
 
-// Arithmetic of one dense k-qubit block per amplitude: 6 2^k flops in the
-// matrix-core form (three real products), 8 2^k on the vector units
-// (complex multiply-adds), 4x that for complex128.
-static double block_flops_per_amp(int dtype, int k, int nloc, int mfma_min_k)
+// Arithmetic of one dense k-qubit block per amplitude.  Algorithmic: a
+// complex 2^k-term dot product per output, 8 2^k - 2 flops.  Issued: 6 2^k
+// in the matrix-core form (three real products), 8 2^k on the vector units
+// (complex multiply-adds).
+static double block_flops_alg(int k)
+{
+    return 8.0 * (double)(1 << k) - 2.0;
+}
+
+static double block_flops_issued(int dtype, int k, int nloc, int mfma_min_k)
 {
     const double d = (double)(1 << k);
     if (dtype == 0 && dense_uses_mfma(k, nloc, mfma_min_k)) return 6.0 * d;
@@ -221,9 +228,13 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 h->e0_pending = false;
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
-                    double f = 0.0;
-                    for (int c = 0; c < cnt; ++c) f += 6.0 * (double)(1 << ks[c]);
-                    h->tev_info.emplace_back(1, f * (double)((uint64_t)1 << nloc));
+                    double f = 0.0, fi = 0.0;
+                    for (int c = 0; c < cnt; ++c) {
+                        f += block_flops_alg(ks[c]);
+                        fi += 6.0 * (double)(1 << ks[c]);
+                    }
+                    const double amps = (double)((uint64_t)1 << nloc);
+                    h->tev_info.push_back({1, f * amps, fi * amps});
                 }
                 h->counters[0] += 1;
                 h->counters[3] += (int64_t)1 << nloc;
@@ -258,8 +269,9 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                                 idx_offset, h->mfma_min_k));
             if (h->timing) {
                 TRY(h, hipEventRecord(e1, st));
-                h->tev_info.emplace_back(0, block_flops_per_amp(h->dtype, op.k, nloc, h->mfma_min_k) *
-                                                (h->dtype ? 4.0 : 1.0) * (double)((uint64_t)1 << nloc));
+                const double amps = (double)((uint64_t)1 << nloc);
+                h->tev_info.push_back({0, block_flops_alg(op.k) * amps,
+                                       block_flops_issued(h->dtype, op.k, nloc, h->mfma_min_k) * amps});
             }
             h->counters[0] += 1;
             h->counters[3] += (int64_t)1 << nloc;
@@ -1269,6 +1281,7 @@ static void reset_timing(sv_state* h)
         h->tk_ms[k] = 0.0;
         h->tk_count[k] = 0;
         h->tk_flops[k] = 0.0;
+        h->tk_issued[k] = 0.0;
     }
 }
 
@@ -1283,7 +1296,7 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
     return SV_OK;
 }
 
-int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2])
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2])
 {
     CHECK_HANDLE(h);
     int rc = collect_timing(h);
@@ -1292,6 +1305,7 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
         if (ms) ms[k] = h->tk_ms[k];
         if (count) count[k] = h->tk_count[k];
         if (flops) flops[k] = h->tk_flops[k];
+        if (issued) issued[k] = h->tk_issued[k];
     }
     reset_timing(h);
     return SV_OK;

@@ -80,13 +80,19 @@ struct sv_state {
     int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;
-    std::vector<std::pair<int, double>> tev_info;   // per event pair: kind, flops
+    struct TimedLaunch {
+        int kind;           // 0 single sweep, 1 staged pass
+        double flops;       // algorithmic: (8 2^k - 2) per amplitude per block
+        double issued;      // as executed: 6 2^k (3M, matrix cores) or 8 2^k (vector units)
+    };
+    std::vector<TimedLaunch> tev_info;              // per event pair
     size_t tev_used = 0;
     double t_ms = 0.0;
     int64_t t_count = 0;
     double tk_ms[2] = {0.0, 0.0};                   // by kind: single sweeps, staged passes
     int64_t tk_count[2] = {0, 0};
     double tk_flops[2] = {0.0, 0.0};
+    double tk_issued[2] = {0.0, 0.0};
     int64_t counters[8] = {};
 
     bool poisoned = false;

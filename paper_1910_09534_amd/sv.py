@@ -60,7 +60,7 @@ def load():
     L.sv_set_option.argtypes = [P, I, I64]
     L.sv_counters.argtypes = [P, P]
     L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
-    L.sv_sweep_profile.argtypes = [P, P, P, P]
+    L.sv_sweep_profile.argtypes = [P, P, P, P, P]
     L.sv_batch_prepare.argtypes = [I, P, I, P, ctypes.POINTER(P)]
     L.sv_batch_launch.argtypes = [P]
     L.sv_batch_sync.argtypes = [P]
@@ -212,12 +212,14 @@ def sweep_time(h):
 
 def sweep_profile(h) -> dict:
     """Timed launches by kind ("sweep": single dense sweeps, "staged":
-    staged passes): ms, count, flops.  Resets the timing accumulators."""
+    staged passes): ms, count, algorithmic flops, issued flops.  Resets the
+    timing accumulators."""
     ms = np.zeros(2, dtype=np.float64)
     cnt = np.zeros(2, dtype=np.int64)
     fl = np.zeros(2, dtype=np.float64)
-    _check(lib().sv_sweep_profile(h, _ptr(ms), _ptr(cnt), _ptr(fl)), h)
-    return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i])}
+    iss = np.zeros(2, dtype=np.float64)
+    _check(lib().sv_sweep_profile(h, _ptr(ms), _ptr(cnt), _ptr(fl), _ptr(iss)), h)
+    return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i]), "issued": float(iss[i])}
             for i, kind in enumerate(("sweep", "staged"))}
 
 

@@ -305,8 +305,10 @@ def test_sweep_profile_splits_kinds():
         sv.sync_state(h)
         p = sv.sweep_profile(h)
         assert p["staged"]["count"] == 1 and p["sweep"]["count"] == 1
-        assert p["staged"]["flops"] == 6.0 * (32 + 16 + 32) * (1 << n)
-        assert p["sweep"]["flops"] == 8.0 * 8 * (1 << n)
+        assert p["staged"]["issued"] == 6.0 * (32 + 16 + 32) * (1 << n)
+        assert p["staged"]["flops"] == (8.0 * 32 - 2 + 8.0 * 16 - 2 + 8.0 * 32 - 2) * (1 << n)
+        assert p["sweep"]["issued"] == 8.0 * 8 * (1 << n)
+        assert p["sweep"]["flops"] == (8.0 * 8 - 2) * (1 << n)
         assert p["staged"]["ms"] > 0 and p["sweep"]["ms"] > 0
         q = sv.sweep_profile(h)              # reset by the previous call
         assert q["staged"]["count"] == 0 and q["sweep"]["count"] == 0
