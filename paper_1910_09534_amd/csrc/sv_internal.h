@@ -99,7 +99,7 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // Staged sweep: nops dense blocks (k = 4 or 5, complex64) applied to LDS
 // tiles in one HBM pass.  pos[o] / mats[o]: block o's positions and device
 // matrix.  The tile (positions 0..3 and every target) is widened with free
-// low positions up to t_max (<= 12) within the LDS budget.  Fails
+// low positions up to t_max (<= 13) within the LDS budget.  Fails
 // (hipErrorInvalidValue) when the targets alone exceed t_max positions or
 // the LDS budget; *t_out receives the tile width used.  from_e0: the input
 // is |0...0> and is not read (the pass writes every amplitude).  norm_out

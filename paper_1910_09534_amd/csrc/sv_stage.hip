@@ -5,9 +5,9 @@
 // tile, so the run costs one HBM round trip instead of one per aggregate.
 //
 // A stage is a run of consecutive dense blocks (k = 4 or 5, complex64) whose
-// target positions, together with positions 0..3, fit in t <= 12 tile
+// target positions, together with positions 0..3, fit in t <= 13 tile
 // positions P[0] < ... < P[t-1] (P[0..3] = 0..3; free low positions widen
-// the tile to 12).  A tile is the 2^t amplitudes whose other bits equal the
+// the tile to 13 when the LDS budget allows).  A tile is the 2^t amplitudes whose other bits equal the
 // tile id.  A persistent workgroup (256 lanes) loops over tiles:
 //   1. the next tile's loads are issued (into registers);
 //   2. each block runs on the LDS tile: pairs of 16-group units per wave
@@ -26,7 +26,7 @@
 namespace sv {
 
 constexpr int kStageMaxOps = 8;
-constexpr int kStageMaxT = 12;
+constexpr int kStageMaxT = 13;
 constexpr int kStageMaxLds = 80 * 1024;     // two workgroups per CU
 constexpr int kStageThreads = 256;          // lanes per workgroup (four waves)
 
@@ -34,7 +34,7 @@ struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
     uint64_t tile_lowmask[kStageMaxT];       // (1 << P[b]) - 1, ascending (tile-id spreading)
     uint64_t dep_lane[8];                    // global offset of element bit b (lane bits, b < 8)
-    uint64_t dep_i[16];                      // global offset of element bits 8.. (i = e >> 8)
+    uint64_t dep_i[32];                      // global offset of element bits 8.. (i = e >> 8)
     int t;
     int nops;
     int from_e0;                             // 1: input is |0...0>, not read
@@ -381,9 +381,11 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
         case 23: kern = k_stage<11, true>; break;
         case 24: kern = k_stage<12, false>; break;
         case 25: kern = k_stage<12, true>; break;
+        case 26: kern = k_stage<13, false>; break;
+        case 27: kern = k_stage<13, true>; break;
         default: return hipErrorInvalidValue;
     }
-    static std::atomic<bool> attr_set[8];
+    static std::atomic<bool> attr_set[10];
     const int ai = (t - 9) * 2 + (wide ? 1 : 0);
     if (!attr_set[ai]) {
         const hipError_t e = hipFuncSetAttribute((const void*)kern,

@@ -75,7 +75,7 @@ struct sv_state {
     // options and accounting
     bool timing = false, fold = true;
     int mfma_min_k = 4;
-    int stage_t = 12;
+    int stage_t = 13;
     bool e0_pending = false;     // resident state is |0...0> but not yet written (sv_reset)
     int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
     int nslots = 3;

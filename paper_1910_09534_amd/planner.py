@@ -15,7 +15,7 @@
   folds it into that cluster's sweep as an element-wise phase.
 * Staged passes (a second level of cache blocking over the appendix's
   aggregate gates): the device applies a run of consecutive 4/5-qubit
-  blocks whose positions, with positions 0..3, fit in one 12-position tile
+  blocks whose positions, with positions 0..3, fit in one 13-position tile
   in a single HBM pass.
   `order_for_staging` reorders commuting blocks so that such runs are
   consecutive, and `plan` picks among aggregations by a cost model of
@@ -255,7 +255,7 @@ def fuse_grow(gates, kmax: int, window: int = 4, last_gain: float = 0.0) -> List
 # holds at most STAGE_MAX_OPS 4/5-qubit blocks, the tile at most STAGE_T
 # positions (0..3 always), and the LDS budget covers the tile (2^t complex64
 # plus one pad per 16) and Re/Im of every block's matrix.
-STAGE_T = 12
+STAGE_T = 13
 STAGE_MAX_OPS = 8
 STAGE_LDS = 80 * 1024
 
@@ -274,9 +274,10 @@ def _fits(pos: set, ks: Sequence[int], tmax: int) -> bool:
     return t <= tmax and len(ks) <= STAGE_MAX_OPS and _stage_lds(t, ks) <= STAGE_LDS
 
 
-def stage_runs(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> List[List[int]]:
+def stage_runs(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) -> List[List[int]]:
     """The runs the device forms from `ops` in this order (lists of indices;
     a single-element list is a sweep of its own)."""
+    tmax = STAGE_T if tmax is None else tmax
     pos = (lambda q: q) if pos_of is None else pos_of
     runs: List[List[int]] = []
     i = 0
@@ -297,7 +298,7 @@ def stage_runs(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> List[Li
     return runs
 
 
-def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> List["Op"]:
+def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) -> List["Op"]:
     """Reorder ops so that blocks which can share a staged pass are adjacent.
 
     Ops are nodes of a dependency graph (an op depends on the last earlier op
@@ -306,6 +307,7 @@ def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> 
     Greedy: take the earliest ready op; if it is a 4/5-qubit block, keep
     adding the ready block that adds the fewest new tile positions (earliest
     first) while the tile and LDS limits hold."""
+    tmax = STAGE_T if tmax is None else tmax
     pos = (lambda q: q) if pos_of is None else pos_of
     n = len(ops)
     npred = [0] * n
@@ -369,9 +371,10 @@ STAGE_MS_FIXED = 1.475
 STAGE_MS_BLOCK = {4: 1.10, 5: 1.78}
 
 
-def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: int = STAGE_T) -> float:
+def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) -> float:
     """Modelled time of `ops` in this order, staged runs formed as the
     device forms them."""
+    tmax = STAGE_T if tmax is None else tmax
     tot = 0.0
     for r in stage_runs(ops, pos_of, tmax):
         if len(r) >= 2:

@@ -252,7 +252,7 @@ def test_staged_multiblock_pass(n):
     assert orc.rel_l2(outs[12], outs[0]) <= 1e-6
 
 
-@pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12)])
+@pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12), (13, 13), (19, 13)])
 def test_staged_pass_any_positions(n, tmax):
     """Staged passes over blocks whose targets lie anywhere (no position
     limit), with tiles widened to the largest width allowed: equal to one
