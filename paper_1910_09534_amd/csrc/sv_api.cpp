@@ -183,7 +183,8 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
         const Op& op = h->ops[i];
         // a run of consecutive 4/5-qubit complex64 blocks whose targets fit in
         // one LDS tile goes through a single staged HBM pass
-        if (op.kind == OP_DENSE && h->dtype == 0 && h->stage_t >= 9 && h->mfma_min_k == 4 &&
+        const int stage_t = h->stage_t;
+        if (op.kind == OP_DENSE && h->dtype == 0 && stage_t >= 9 && h->mfma_min_k == 4 &&
             (op.k == 4 || op.k == 5)) {
             int ks[8];
             const int* pp[8];
@@ -203,7 +204,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 for (int p = 0; p < 64; ++p) t += in2[p];
                 if (t < 9) t = 9;
                 ks[cnt] = q.k;
-                if (t > h->stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
+                if (t > stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
                 for (int p = 0; p < 64; ++p) in[p] = in2[p];
                 pp[cnt] = q.pos;
                 mm[cnt] = dbase + q.off;
@@ -223,7 +224,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 }
                 int tused = 0;
                 const bool last = j == nops && norm_out != nullptr;
-                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, h->stage_t, from_e0,
+                TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, stage_t, from_e0,
                                     last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused));
                 h->e0_pending = false;
                 if (h->timing) {

@@ -260,6 +260,15 @@ STAGE_MAX_OPS = 8
 STAGE_LDS = 80 * 1024
 
 
+def stage_tmax(nloc: int) -> int:
+    """Tile limit for a state of 2^nloc amplitudes: at most nloc - 9
+    positions, so that a pass has at least 512 tiles (two workgroups per
+    CU); 0 (no staged passes) below 9.  Callers pass it to the device as
+    SV_OPT_STAGE for the state."""
+    t = min(STAGE_T, nloc - 9)
+    return t if t >= 9 else 0
+
+
 def _stage_lds(t: int, ks: Sequence[int]) -> int:
     tile = (((1 << t) + ((1 << t) >> 4)) * 8 // 16 + 1) * 16
     return tile + sum(2 * (1 << (2 * k)) for k in ks) * 4
@@ -416,15 +425,23 @@ def plan_cost(ops: Sequence[Op]) -> float:
     return sum(1.0 + (8 << len(o.qubits)) / 4096.0 if o.kind == "dense" else 1.0 for o in ops)
 
 
-def plan_fast(gates, kmax: int, pos_of=None) -> List[Op]:
+def _nloc_of(gates) -> int:
+    return 1 + max((q for g in gates for q in g.qubits), default=0)
+
+
+def plan_fast(gates, kmax: int, pos_of=None, nloc: Optional[int] = None) -> List[Op]:
     """One staged aggregation (grow-based, window 4, last qubit only when it
     adds 40 % more gate weight), widened and ordered for staged passes: for
     request paths where planning time counts (tens of ms for ~600 gates)."""
-    ops = fuse_grow(gates, kmax, window=4, last_gain=0.4 if kmax >= 5 else 0.0)
-    return order_for_staging(widen_small_blocks(ops, pos_of), pos_of)
+    tmax = stage_tmax(_nloc_of(gates) if nloc is None else nloc)
+    ops = fuse_grow(gates, kmax, window=4, last_gain=0.4 if kmax >= 5 and tmax else 0.0)
+    if not tmax:
+        return ops
+    return order_for_staging(widen_small_blocks(ops, pos_of), pos_of, tmax)
 
 
-def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None) -> List[Op]:
+def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None,
+         nloc: Optional[int] = None) -> List[Op]:
     """Aggregate with every available heuristic and keep the cheapest plan.
 
     staged (complex64 states): blocks on fewer than 4 qubits are widened to
@@ -436,14 +453,15 @@ def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=
     if not fold_diag:
         for w in (3, 4, 5, 6, 8):
             cands.append(fuse_grow(gates, kmax, window=w))
-    if not staged or fold_diag:
+    tmax = stage_tmax(_nloc_of(gates) if nloc is None else nloc) if staged else 0
+    if not tmax or fold_diag:
         return min(cands, key=plan_cost)
     if kmax >= 3:
         for w in (3, 4, 5, 6, 8):
             for g in (0.2, 0.4, 0.6, 0.8, 1.0):
                 cands.append(fuse_grow(gates, kmax, window=w, last_gain=g))
-    cands = [order_for_staging(widen_small_blocks(c, pos_of), pos_of) for c in cands]
-    return min(cands, key=lambda c: staged_cost(c, pos_of))
+    cands = [order_for_staging(widen_small_blocks(c, pos_of), pos_of, tmax) for c in cands]
+    return min(cands, key=lambda c: staged_cost(c, pos_of, tmax))
 
 
 @dataclasses.dataclass
@@ -499,7 +517,8 @@ def phase_schedule(circuit, set_a: Sequence[int], set_b: Sequence[int], kmax: in
                 take.append(i)
         ph = Phase(cur, phase_layout(n, cur, nxt), take)
         where = {q: p for p, q in enumerate(ph.order)}
-        ph.ops = plan([gates[i] for i in take], kmax, pos_of=where.__getitem__) if take else []
+        ph.ops = plan([gates[i] for i in take], kmax, pos_of=where.__getitem__,
+                      nloc=n - len(cur)) if take else []
         phases.append(ph)
         stall = stall + 1 if not take else 0
         if stall >= 2 or len(phases) > max_phases:

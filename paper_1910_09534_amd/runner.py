@@ -18,15 +18,21 @@ from . import planner, sv
 
 
 def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: bool = False,
-             timing: bool = False, mfma: int = 4, stream=None) -> Dict[str, object]:
+             timing: bool = False, mfma: int = 4, stream=None, stage: Optional[int] = None) -> Dict[str, object]:
+    """stage: widest staged tile (SV_OPT_STAGE); None = planner.stage_tmax(n)
+    for complex64, 0 = no staged passes."""
     t0 = time.perf_counter()
-    ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag, staged=(dtype == "c64"))
+    if stage is None:
+        stage = planner.stage_tmax(circuit.n) if dtype == "c64" else 0
+    ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag, staged=stage > 0,
+                       nloc=max(circuit.n, stage + 9) if stage else None)
     t_plan = time.perf_counter() - t0
     st = sv.State(circuit.n, 0, dtype, stream)
     try:
         if timing:
             sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
         sv.set_option(st.h, sv.SV_OPT_MFMA, int(mfma))
+        sv.set_option(st.h, sv.SV_OPT_STAGE, int(stage))
         t1 = time.perf_counter()
         planner.enqueue(st.h, ops, st.dtype)
         amps, stats = st.reduce(bits)

@@ -73,6 +73,7 @@ def run_one(torch, stream, req: Request, kmax: int, mfma_min_k: int = 4):
     h = sv.create_state_ext(n, 0, "c64", stream.cuda_stream, buf.data_ptr(), buf.numel() * 8)
     try:
         sv.set_option(h, sv.SV_OPT_MFMA, mfma_min_k)
+        sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
         planner.enqueue(h, ops, sv.SV_C64)
         amps, stats = sv.reduce_slices(h, req.bits)
     finally:

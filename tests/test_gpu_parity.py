@@ -150,6 +150,23 @@ def test_circuit_c64_vs_oracle(kmax, fold, mfma):
     assert abs(res["norm"] - 1) < 1e-4
 
 
+@pytest.mark.parametrize("stage", [0, 9, 11, 12, 13])
+def test_circuit_c64_staged_widths(stage):
+    """The whole planned circuit (planner ordered for the tile width, deferred
+    reset, folded norm) at every staged tile width, and without staging."""
+    n, d = 20, 14
+    c = W.sycamore_circuit(n, d, seed=2003)
+    bits = W.bitstrings(n, 4096, seed=4)
+    res = runner.simulate(c, bits, dtype="c64", kmax=5, stage=stage)
+    ref_psi = orc.simulate(c)
+    assert orc.rel_l2(res["amps"], orc.gather(ref_psi, bits)) <= TOL["c64"]
+    assert abs(res["norm"] - orc.norm(ref_psi)) < 1e-5
+    if stage:
+        assert res["counters"]["staged_blocks"] > 0
+    else:
+        assert res["counters"]["staged_blocks"] == 0
+
+
 def test_circuit_c128_k5():
     n = 18
     c = W.sycamore_circuit(n, 10, seed=44)
