@@ -182,6 +182,8 @@ def main(argv=None) -> int:
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--pins", action="store_true", help="config 3: also run the mirror pin")
+    ap.add_argument("--batch-unstaged", action="store_true",
+                    help="config 4: autotuned single sweeps instead of staged passes")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -402,16 +404,23 @@ def bench_batch(args) -> int:
     circs = [W.sycamore_circuit(s["n"], s["depth"], s["seed"]) for s in specs]
     bits = [W.bitstrings(s["n"], 1024, s["bit_seed"]) for s in specs]
     t0 = time.perf_counter()
-    tuned = autotune.tune(sorted({c.n for c in circs}))
+    if args.batch_unstaged:
+        tuned = autotune.tune(sorted({c.n for c in circs}))
+    else:
+        # staged passes for every state (n >= 18): k <= 5 on the matrix cores
+        ns = sorted({c.n for c in circs})
+        tuned = {"kmax": {n: 5 for n in ns}, "mfma_min_k": {n: 4 for n in ns}}
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
-    plans = [planner.plan(c.gates, tuned["kmax"][c.n], staged=False) for c in circs]
+    staged = not args.batch_unstaged
+    plans = [planner.plan(c.gates, tuned["kmax"][c.n], staged=staged and planner.stage_tmax(c.n) > 0,
+                          nloc=c.n) for c in circs]
     for p in plans:
         for o in p:
             o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     t_plan = time.perf_counter() - t0
     res = runner.run_batch(circs, bits, "c64", kmax=tuned["kmax"], mfma_min_k=tuned["mfma_min_k"],
-                           graph=True, repeats=args.warmup + args.steps, plans=plans)
+                           graph=True, repeats=args.warmup + args.steps, plans=plans, staged=staged)
     times = res["times"][args.warmup:]
     t = sum(times) / len(times)
     gate_amps = sum(len(c.gates) * float(1 << c.n) for c in circs)
@@ -444,7 +453,7 @@ def bench_batch(args) -> int:
                    "sweeps": sum(res["sweeps"]), "launches_per_batch": res["info"]["launches"]},
         "amp_updates_per_s": gate_amps / t,
         "hbm_GBps_sweeps": 16.0 * swept / t / 1e9,
-        "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"],
+        "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"], "staged": staged,
         "t_tune_s": round(t_tune, 2), "t_plan_s": round(t_plan, 2),
         "c128_batch_s": round(t128, 3),
         "rel_l2_vs_c128_max": max(err), "rel_l2_vs_oracle_by_n": oracle_err,

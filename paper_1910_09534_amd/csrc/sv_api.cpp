@@ -186,31 +186,15 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
         const int stage_t = h->stage_t;
         if (op.kind == OP_DENSE && h->dtype == 0 && stage_t >= 9 && h->mfma_min_k == 4 &&
             (op.k == 4 || op.k == 5)) {
-            int ks[8];
-            const int* pp[8];
-            const void* mm[8];
-            bool in[64] = {};
-            for (int p = 0; p < 4; ++p) in[p] = true;
-            int cnt = 0;
-            size_t j = i;
-            while (j < nops && cnt < 8) {
-                const Op& q = h->ops[j];
-                if (q.kind != OP_DENSE || (q.k != 4 && q.k != 5)) break;
-                if (h->fold && j + 1 < nops && h->ops[j + 1].kind == OP_DIAG) break;
-                bool in2[64];
-                for (int p = 0; p < 64; ++p) in2[p] = in[p];
-                for (int u = 0; u < q.k; ++u) in2[q.pos[u]] = true;
-                int t = 0;
-                for (int p = 0; p < 64; ++p) t += in2[p];
-                if (t < 9) t = 9;
-                ks[cnt] = q.k;
-                if (t > stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
-                for (int p = 0; p < 64; ++p) in[p] = in2[p];
-                pp[cnt] = q.pos;
-                mm[cnt] = dbase + q.off;
-                ++cnt;
-                ++j;
+            int ks[kStageRunMax];
+            const int* pp[kStageRunMax];
+            const void* mm[kStageRunMax];
+            const int cnt = form_stage_run(h->ops.data(), nops, i, stage_t, nloc, h->fold, ks);
+            for (int c = 0; c < cnt; ++c) {
+                pp[c] = h->ops[i + c].pos;
+                mm[c] = dbase + h->ops[i + c].off;
             }
+            const size_t j = i + cnt;
             // a single block goes through a staged pass only when it is the
             // queue's last op and the pass also sums the norm (saving a read)
             if (cnt >= 2 || (cnt == 1 && j == nops && norm_out != nullptr)) {
@@ -1317,4 +1301,28 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
 int sv::materialize_e0(sv_state* h)
 {
     return materialize_state(h);
+}
+
+// ---- staged-run formation (shared with the batch executor) -----------------
+int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks)
+{
+    bool in[64] = {};
+    for (int p = 0; p < 4; ++p) in[p] = true;
+    int cnt = 0;
+    for (size_t j = i; j < nops && cnt < kStageRunMax; ++j) {
+        const Op& q = ops[j];
+        if (q.kind != OP_DENSE || (q.k != 4 && q.k != 5)) break;
+        if (fold && j + 1 < nops && ops[j + 1].kind == OP_DIAG) break;
+        bool in2[64];
+        for (int p = 0; p < 64; ++p) in2[p] = in[p];
+        for (int u = 0; u < q.k; ++u) in2[q.pos[u]] = true;
+        int t = 0;
+        for (int p = 0; p < 64; ++p) t += in2[p];
+        if (t < 9) t = 9;
+        ks[cnt] = q.k;
+        if (t > stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
+        for (int p = 0; p < 64; ++p) in[p] = in2[p];
+        ++cnt;
+    }
+    return cnt;
 }

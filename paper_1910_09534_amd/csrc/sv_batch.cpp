@@ -24,17 +24,21 @@ using namespace sv;
 namespace {
 
 struct Launch {
-    int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal (one item)
+    int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal, 3 staged pass (one state each)
     int dtype, k;
     bool fold;
     bool staged;       // MFMA: address-ordered LDS staging
     size_t first;      // index of the first Sweep item
     int nitems;
     uint64_t blocks;
-    // diagonal launches
+    // diagonal and staged launches
     void* psi;
     int nloc;
     DiagSpec diag;
+    int cnt, t_max;                           // staged: blocks, tile limit
+    int ks[kStageRunMax];
+    int spos[kStageRunMax][6];
+    const void* smat[kStageRunMax];
 };
 
 }  // namespace
@@ -90,8 +94,15 @@ hipError_t enqueue_all(sv_batch_s* b)
         else if (L.kind == 1)
             e = launch_dense_mfma_batch(b->stream, L.k, L.fold, L.staged, items + L.first, L.nitems,
                                         L.blocks);
-        else
+        else if (L.kind == 2)
             e = launch_diag(b->stream, L.psi, L.dtype, L.nloc, 0, L.diag);
+        else {
+            const int* pp[kStageRunMax];
+            for (int c = 0; c < L.cnt; ++c) pp[c] = L.spos[c];
+            int t = 0;
+            e = launch_stage(b->stream, L.psi, L.nloc, L.cnt, L.ks, pp, L.smat, L.t_max, false, nullptr,
+                             nullptr, &t);
+        }
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -149,20 +160,33 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             }
     }
 
-    // per state: its sweeps (dense + folded diagonal, or diagonal alone)
-    struct Sw { int kind; const Op* op; const Op* fold; };
+    // per state: its sweeps (dense + folded diagonal, diagonal alone, or a
+    // staged run of 4/5-qubit blocks formed as for the state alone)
+    struct Sw { int kind; const Op* op; const Op* fold; int cnt; int ks[kStageRunMax]; };
     std::vector<std::vector<Sw>> sweeps(count);
     size_t rounds = 0;
+    bool any_staged = false;
     for (int i = 0; i < count; ++i) {
         sv_state* h = handles[i];
         const auto& ops = h->ops;
+        const bool can_stage = h->dtype == 0 && h->stage_t >= 9 && h->mfma_min_k == 4;
         for (size_t j = 0; j < ops.size(); ++j) {
+            if (can_stage && ops[j].kind == OP_DENSE && (ops[j].k == 4 || ops[j].k == 5)) {
+                Sw w{3, &ops[j], nullptr, 0, {}};
+                w.cnt = form_stage_run(ops.data(), ops.size(), j, h->stage_t, h->n, h->fold, w.ks);
+                if (w.cnt >= 2) {
+                    sweeps[i].push_back(w);
+                    j += w.cnt - 1;
+                    any_staged = true;
+                    continue;
+                }
+            }
             if (ops[j].kind == OP_DENSE) {
                 const Op* f = nullptr;
                 if (h->fold && j + 1 < ops.size() && ops[j + 1].kind == OP_DIAG) f = &ops[++j];
-                sweeps[i].push_back({0, &ops[j - (f ? 1 : 0)], f});
+                sweeps[i].push_back({0, &ops[j - (f ? 1 : 0)], f, 0, {}});
             } else {
-                sweeps[i].push_back({2, &ops[j], nullptr});
+                sweeps[i].push_back({2, &ops[j], nullptr, 0, {}});
             }
         }
         rounds = std::max(rounds, sweeps[i].size());
@@ -179,6 +203,25 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             const char* ab = (const char*)b->d_arena + abase[i];
             b->sweeps += 1;
             b->amps_swept += (double)((uint64_t)1 << h->n);
+            if (w.kind == 3) {
+                Launch L{};
+                L.kind = 3;
+                L.dtype = h->dtype;
+                L.psi = h->dev;
+                L.nloc = h->n;
+                L.cnt = w.cnt;
+                L.t_max = h->stage_t;
+                for (int c = 0; c < w.cnt; ++c) {
+                    L.ks[c] = w.ks[c];
+                    for (int u = 0; u < w.ks[c]; ++u) L.spos[c][u] = w.op[c].pos[u];
+                    L.smat[c] = ab + w.op[c].off;
+                }
+                b->launches.push_back(L);
+                h->counters[0] += 1;
+                h->counters[3] += (int64_t)1 << h->n;
+                h->counters[7] += w.cnt;
+                continue;
+            }
             if (w.kind == 2) {
                 Launch L{};
                 L.kind = 2;
@@ -249,6 +292,11 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             return berr(nullptr, SV_EDEVICE, "event creation failed");
         }
     if (flags & SV_BATCH_GRAPH) {
+        // kernel attributes are set outside the capture
+        if (any_staged && (e = stage_prepare()) != hipSuccess) {
+            free_batch(b);
+            return berr(nullptr, SV_EDEVICE, "staged kernel set-up failed");
+        }
         e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess) {
             hipError_t e2 = enqueue_all(b);

@@ -107,6 +107,9 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // it wrote to norm_out[workgroup]; *norm_blocks receives the workgroup count
 // (at most 1024).
 int stage_lds_bytes(int t, int nops, const int* ks);
+// Sets the staged kernels' LDS attribute for every tile width (idempotent;
+// launch_stage does it on first use, graph capture needs it beforehand).
+hipError_t stage_prepare();
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out);

@@ -303,6 +303,23 @@ int stage_lds_bytes(int t, int nops, const int* ks)
     return tile_f4 * 16 + floats * 4;
 }
 
+hipError_t stage_prepare()
+{
+    static std::atomic<bool> done{false};
+    if (done) return hipSuccess;
+    void (*kerns[])(float2*, StageK) = {k_stage<9, false>,  k_stage<9, true>,  k_stage<10, false>,
+                                        k_stage<10, true>, k_stage<11, false>, k_stage<11, true>,
+                                        k_stage<12, false>, k_stage<12, true>, k_stage<13, false>,
+                                        k_stage<13, true>};
+    for (auto k : kerns) {
+        const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 kStageMaxLds);
+        if (e != hipSuccess) return e;
+    }
+    done = true;
+    return hipSuccess;
+}
+
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out)
@@ -385,13 +402,9 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
         case 27: kern = k_stage<13, true>; break;
         default: return hipErrorInvalidValue;
     }
-    static std::atomic<bool> attr_set[10];
-    const int ai = (t - 9) * 2 + (wide ? 1 : 0);
-    if (!attr_set[ai]) {
-        const hipError_t e = hipFuncSetAttribute((const void*)kern,
-                                                 hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds);
+    {
+        const hipError_t e = stage_prepare();
         if (e != hipSuccess) return e;
-        attr_set[ai] = true;
     }
     // persistent: as many workgroups as are resident (LDS-limited, at most 4 per CU)
     int per_cu = (160 * 1024) / lds;

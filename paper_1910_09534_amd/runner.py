@@ -94,16 +94,20 @@ def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: 
 
 
 def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: bool = True,
-              repeats: int = 1, plans=None) -> Dict[str, object]:
+              repeats: int = 1, plans=None, staged: bool = False) -> Dict[str, object]:
     """Many independent circuits as one batched execution (one graph launch
     per run).  kmax / mfma_min_k: an int, or a dict n -> value (autotuned).
+    staged (complex64): each state's runs of 4/5-qubit blocks go through
+    staged passes (tile limit planner.stage_tmax(n)), planned for them.
     Each repeat resets every state and replays the batch; the returned
     amplitudes are those of the last repeat."""
     kof = (lambda n: kmax[n]) if isinstance(kmax, dict) else (lambda n: kmax)
     mof = (lambda n: mfma_min_k[n]) if isinstance(mfma_min_k, dict) else (lambda n: mfma_min_k)
+    staged = staged and dtype == "c64"
+    tmax = (lambda n: planner.stage_tmax(n)) if staged else (lambda n: 0)
     t0 = time.perf_counter()
     if plans is None:
-        plans = [planner.plan(c.gates, kof(c.n), staged=False) for c in circuits]
+        plans = [planner.plan(c.gates, kof(c.n), staged=tmax(c.n) > 0, nloc=c.n) for c in circuits]
     t_plan = time.perf_counter() - t0
     states = []
     b = None
@@ -111,6 +115,7 @@ def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: boo
         for c in circuits:
             st = sv.State(c.n, 0, dtype)
             sv.set_option(st.h, sv.SV_OPT_MFMA, int(mof(c.n)))
+            sv.set_option(st.h, sv.SV_OPT_STAGE, int(tmax(c.n)))
             states.append(st)
         for st, ops in zip(states, plans):
             planner.enqueue(st.h, ops, st.dtype)

@@ -45,6 +45,31 @@ def test_batch_equals_alone_and_oracle(graph):
         assert orc.rel_l2(amps, ref) <= 1e-4
 
 
+@pytest.mark.parametrize("graph", [True, False])
+def test_staged_batch_equals_alone_and_oracle(graph):
+    """States of 2^18..2^21 amplitudes with staged passes in the batch (tile
+    limit n - 9): each equals the same plan and tile limit alone (bitwise)
+    and the oracle; replays after sv_reset give the same result."""
+    _gpu()
+    circs, bits = _batch(count=6, nmin=18, nmax=21, seed=13)
+    res = runner.run_batch(circs, bits, "c64", kmax=5, graph=graph, repeats=2, staged=True)
+    plans = [planner.plan(c.gates, 5, staged=True, nloc=c.n) for c in circs]
+    staged_blocks = 0
+    for c, b, amps, p in zip(circs, bits, res["amps"], plans):
+        st = sv.State(c.n, 0, "c64")
+        try:
+            sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(c.n))
+            planner.enqueue(st.h, p, st.dtype)
+            alone = st.gather(b)
+            staged_blocks += sv.counters(st.h)["staged_blocks"]
+        finally:
+            st.close()
+        assert np.array_equal(alone, amps), "batched result differs from the same plan alone"
+        ref = orc.gather(orc.simulate(c), b)
+        assert orc.rel_l2(amps, ref) <= 1e-4
+    assert staged_blocks > 0
+
+
 def test_batch_c128_vs_c64_vs_oracle():
     _gpu()
     circs, bits = _batch(count=6, nmin=10, nmax=16, seed=9)
