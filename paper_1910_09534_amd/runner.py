@@ -107,7 +107,8 @@ def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: boo
     tmax = (lambda n: planner.stage_tmax(n)) if staged else (lambda n: 0)
     t0 = time.perf_counter()
     if plans is None:
-        plans = [planner.plan(c.gates, kof(c.n), staged=tmax(c.n) > 0, nloc=c.n) for c in circuits]
+        plans = [planner.plan_fast(c.gates, kof(c.n), nloc=c.n) if tmax(c.n) > 0
+                 else planner.plan(c.gates, kof(c.n), staged=False) for c in circuits]
     t_plan = time.perf_counter() - t0
     states = []
     b = None

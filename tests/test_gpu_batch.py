@@ -53,7 +53,7 @@ def test_staged_batch_equals_alone_and_oracle(graph):
     _gpu()
     circs, bits = _batch(count=6, nmin=18, nmax=21, seed=13)
     res = runner.run_batch(circs, bits, "c64", kmax=5, graph=graph, repeats=2, staged=True)
-    plans = [planner.plan(c.gates, 5, staged=True, nloc=c.n) for c in circs]
+    plans = [planner.plan_fast(c.gates, 5, nloc=c.n) for c in circs]
     staged_blocks = 0
     for c, b, amps, p in zip(circs, bits, res["amps"], plans):
         st = sv.State(c.n, 0, "c64")
