@@ -128,13 +128,45 @@ def cpu_baseline(circuit, budget_s: float = 15.0):
     t = time.perf_counter() - t0
     del psi
     host = host_info()
+    single = single_core_points(orc)
     return {"value": done * float(1 << n) / t, "unit": "amp-updates/s", "cores": orc.threads(),
             "kind": "oracle",
             "sample": f"first {done} of {len(circuit.gates)} gates of the same {n}-qubit circuit "
                       f"on the full 2^{n} complex128 state ({t:.1f} s)",
             "host": host,
             # a per-gate sweep reads and writes 32 B per complex128 amplitude
-            "host_copy_bound_amp_updates_per_s": host["copy_GBps"] * 1e9 / 32.0}
+            "host_copy_bound_amp_updates_per_s": host["copy_GBps"] * 1e9 / 32.0,
+            "single_core": single}
+
+
+def single_core_points(orc, budget_s: float = 3.0):
+    """The oracle on one core: the whole 16-qubit depth-8 circuit (all 192
+    gates), and the first gates of a 24-qubit depth-14 circuit for ~3 s."""
+    from paper_1910_09534_amd import workload as W
+    nt = orc.threads()
+    out = {}
+    try:
+        orc.set_threads(1)
+        c1 = W.config_circuit(1)
+        t0 = time.perf_counter()
+        orc.simulate(c1)
+        t = time.perf_counter() - t0
+        out["16q_d8_all_gates"] = len(c1.gates) * float(1 << c1.n) / t
+        c24 = W.sycamore_circuit(24, 14, seed=1024)
+        psi = orc.zero_state(24)
+        done = 0
+        t0 = time.perf_counter()
+        for g in c24.gates:
+            orc.apply_dense(psi, g.qubits, g.matrix)
+            done += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        t = time.perf_counter() - t0
+        out["24q_d14_first_gates"] = done * float(1 << 24) / t
+        out["unit"] = "amp-updates/s"
+    finally:
+        orc.set_threads(nt)
+    return out
 
 
 def host_info():

@@ -48,6 +48,7 @@ def lib():
         L = ctypes.CDLL(_SO)
         P = ctypes.c_void_p
         L.orc_threads.restype = ctypes.c_int
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         L.orc_init_zero.argtypes = [P, ctypes.c_int]
         L.orc_apply_dense.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
         L.orc_apply_diag.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P]
@@ -66,6 +67,11 @@ def _ptr(a: np.ndarray):
 
 def threads() -> int:
     return int(lib().orc_threads())
+
+
+def set_threads(n: int) -> None:
+    """OpenMP threads for the following oracle calls (timing only)."""
+    lib().orc_set_threads(int(n))
 
 
 def zero_state(n: int) -> np.ndarray:

@@ -32,6 +32,16 @@ typedef double _Complex cplx;
 
 #define ORC_MAXK 12
 
+/* Thread count for the following calls (timing runs on one core). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    omp_set_num_threads(n > 0 ? n : 1);
+#else
+    (void)n;
+#endif
+}
+
 int orc_threads(void)
 {
 #ifdef _OPENMP
