@@ -329,7 +329,8 @@ def main(argv=None) -> int:
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "c64",
         "data": "synthetic",
         "config": {"workload": "30-qubit 5x6 ABCDCDAB random circuit, depth 14, complex64, "
-                               "fusion k<=%d, norm + 2^16 bitstrings" % args.kmax,
+                               "fusion k<=%d (fSim phases applied to the outputs of their block), "
+                               "norm + 2^16 bitstrings" % args.kmax,
                    "n": n, "depth": circ.depth, "gates": gates, "kmax": args.kmax,
                    "bitstrings": int(bits.size), "blocks": ndense, "hbm_passes": passes,
                    "k_hist": pst["k_hist"]},
