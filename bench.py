@@ -7,19 +7,24 @@ amplitudes (8 GiB, resident in HBM), gates aggregated into dense blocks of
 at most 5 qubits, output = norm + amplitudes of 2^16 seeded bitstrings with
 FP64 cross-entropy sums.
 
-One step = reset the state to |0...0> (init kernel) + every HBM pass of
-the planned circuit (staged passes of several 4/5-qubit blocks, single
-sweeps for the rest) + the FP64 gather / norm / cross-entropy reduction,
-with the circuit already planned (host planning is not timed) and the state
-already allocated in HBM.
+One step = reset the state to |0...0> + every HBM pass of the planned
+circuit (staged passes of several 4/5-qubit blocks, single sweeps for the
+rest) + the FP64 gather / norm / cross-entropy reduction, with the circuit
+already planned (host planning is not timed) and the state already
+allocated in HBM.  After the reset, passes visit only the tiles whose
+amplitudes can be non-zero until every qubit has been touched (the others
+are zero and are zero-filled if still unwritten when the state is read);
+amps_visited_frac gives the share of the full passes' amplitudes visited,
+and dense_start the same steps with every pass over the whole state.
 
 roofline: the kernel kind with the most time in the timed steps (staged
 passes: matrix-core bound, algorithmic flops = 8 2^k - 2 per amplitude per
 block, the complex dot product; the kernels issue 6 2^k of them as the
 three real products of the 3M form, reported as issued_frac; single
-sweeps: HBM bound, 16 bytes per amplitude per launch), durations from HIP
-events on the kernels' stream;
-hbm_frac_run: HBM passes x 16 bytes x 2^n per step over the step time.
+sweeps: HBM bound, 16 bytes per amplitude per launch; a staged pass moves
+16 bytes per amplitude visited, 8 when it starts from |0...0> or takes an
+amplitude as zero), durations from HIP events on the kernels' stream;
+hbm_frac_run: the bytes those launches moved per step over the step time.
 
 value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
 un-aggregated work over aggregated time).
@@ -277,20 +282,32 @@ def main(argv=None) -> int:
     # on the stream the kernels run on; the dominant kind is the roofline's
     prof = sv.sweep_profile(h)
     sv.set_option(h, sv.SV_OPT_TIMING, 0)
-    bytes_per_pass = 16.0 * (1 << n)               # read + write of complex64
+    visited = (c1["amps_swept"] - c0["amps_swept"]) / args.steps
+
+    # the same steps with every pass over the whole state (no sparse start
+    # after the reset), for comparison
+    sv.set_option(h, sv.SV_OPT_SPARSE_START, 0)
+    step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dense_ms = 1e3 * (time.perf_counter() - t0) / args.steps
+    sv.set_option(h, sv.SV_OPT_SPARSE_START, 1)
 
     def kind_roof(kind):
         p = prof[kind]
         if p["count"] == 0:
             return None
         avg_ms = p["ms"] / p["count"]
-        gbs = bytes_per_pass / (avg_ms * 1e-3) / 1e9
+        gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         tflops = p["flops"] / (p["ms"] * 1e-3) / 1e12          # algorithmic
         issued = p["issued"] / (p["ms"] * 1e-3) / 1e12         # as executed (3M on the matrix cores)
         r = {"launches": p["count"], "avg_launch_ms": round(avg_ms, 4),
              "share_of_step": round(p["ms"] / (args.steps * ms_per_step), 4),
              "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
-                     "bytes_per_launch": bytes_per_pass},
+                     "bytes_per_launch": p["bytes"] / p["count"]},
              "fp32": {"achieved_tflops": round(tflops, 2), "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
                       "flops_per_launch": p["flops"] / p["count"],
                       "issued_tflops": round(issued, 2), "issued_frac": round(issued / FP32_PEAK_TFLOPS, 4)},
@@ -313,7 +330,8 @@ def main(argv=None) -> int:
     other = [k for k in kinds if k != dom and kinds[k]]
     if other:
         roof["other_kernel"] = kinds[other[0]]
-    run_hbm_frac = passes * bytes_per_pass / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
+    run_bytes = (prof["staged"]["bytes"] + prof["sweep"]["bytes"]) / args.steps
+    run_hbm_frac = run_bytes / (ms_per_step * 1e-3) / (HBM_PEAK_GBS * 1e9)
 
     sv.destroy_state(h)
     del buf
@@ -335,6 +353,8 @@ def main(argv=None) -> int:
                    "bitstrings": int(bits.size), "blocks": ndense, "hbm_passes": passes,
                    "k_hist": pst["k_hist"]},
         "hbm_frac_run": round(run_hbm_frac, 4),
+        "amps_visited_frac": round(visited / (passes * float(1 << n)), 4),
+        "dense_start": {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3)},
         "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,

@@ -160,7 +160,10 @@ int sync_state(sv_handle h);
    (the layout is kept; |0...0> is index 0 in every layout).  Reuses the
    handle's memory: nothing is allocated.  For a resident state the write
    is deferred: the first staged pass builds its input from |0...0>
-   without reading HBM, and any other first use writes |0...0> first. */
+   without reading HBM, and any other first use writes |0...0> first.
+   Until every qubit position has been touched, staged passes visit only
+   the tiles that can be non-zero (SV_OPT_SPARSE_START); the state is
+   complete in memory again when the queue has run (sync_state, reads). */
 int sv_reset(sv_handle h);
 
 /* last_error -- text of the most recent failure on h (or of the last failed
@@ -185,15 +188,22 @@ enum {
     SV_OPT_STAGE = 5,      /* widest LDS tile (9..13 positions, default 13) for running a
                               run of consecutive 4/5-qubit complex64 blocks in one pass
                               over HBM; 0: one pass per block */
-    SV_OPT_FAIL_IO = 6     /* failure injection for tests: the n-th host-tier transfer
+    SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer
                               from now on (n >= 1) is not issued and reports SV_EIO,
                               poisoning the handle; 0 (default): off */
+    SV_OPT_SPARSE_START = 7 /* 1 (default): after sv_reset of a resident state, staged
+                              passes visit only the tiles whose amplitudes can be
+                              non-zero (positions some operation has touched); the
+                              rest is zero-filled before the amplitudes are read.
+                              0: every pass visits the whole state.  Takes effect at
+                              the next sv_reset. */
 };
 int sv_set_option(sv_handle h, int option, int64_t value);
 
 /*
  * sv_counters -- work done since creation: [0] dense sweeps (HBM passes),
- * [1] diagonal sweeps, [2] permute sweeps, [3] amplitudes touched by sweeps,
+ * [1] diagonal sweeps, [2] permute sweeps, [3] amplitudes touched by sweeps
+ * (staged passes: the amplitudes they visit),
  * [4] bytes staged host->device, [5] bytes staged device->host, [6] slices
  * skipped because they are known to be zero, [7] blocks applied in staged
  * multi-block passes.
@@ -206,11 +216,16 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
 /* sv_sweep_profile -- with SV_OPT_TIMING: the timed launches split by kind,
  * [0] single dense sweeps, [1] staged multi-block passes: total
  * milliseconds, launch count, algorithmic flops (a k-qubit block is a
- * complex 2^k-term dot product per amplitude: 8 2^k - 2 flops) and the
- * flops the kernels issued (6 2^k per amplitude per complex64 block on the
- * matrix cores, 3 real products; 8 2^k on the vector units).  Resets the
- * same accumulators as sv_sweep_time.  Any pointer may be NULL. */
-int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2]);
+ * complex 2^k-term dot product per amplitude: 8 2^k - 2 flops), the flops
+ * the kernels issued (6 2^k per amplitude per complex64 block on the
+ * matrix cores, 3 real products; 8 2^k on the vector units) and the HBM
+ * bytes the launches had to move (amplitudes read and written; after
+ * sv_reset a staged pass visits only the amplitudes that can be non-zero,
+ * reads none from |0...0> and none on positions no operation has reached).
+ * Flops count the amplitudes visited.  Resets the same accumulators as
+ * sv_sweep_time.  Any pointer may be NULL. */
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2],
+                     double bytes[2]);
 
 /* ---- batches of independent states ----------------------------------------
  * Many circuits of different qubit counts run as one recorded execution: the

@@ -13,6 +13,7 @@
 #include <sys/mman.h>
 
 #include <algorithm>
+#include <cmath>
 #include <deque>
 #include <new>
 #include <thread>
@@ -134,6 +135,7 @@ int collect_timing(sv_state* h)
         h->tk_count[info.kind] += 1;
         h->tk_flops[info.kind] += info.flops;
         h->tk_issued[info.kind] += info.issued;
+        h->tk_bytes[info.kind] += info.bytes;
     }
     h->tev_used = 0;
     h->tev_info.clear();
@@ -160,11 +162,21 @@ static double block_flops_issued(int dtype, int k, int nloc, int mfma_min_k)
 // sv_reset leaves a resident state marked |0...0> without writing it; the
 // first staged pass then builds its tiles from |0...0> instead of reading
 // HBM, and anything else that needs the amplitudes writes them first.
+// Until every position has been touched, staged passes skip the tiles that
+// are still zero (the support, in sv_state), so the memory there is written
+// here before anything else reads it.
 int materialize_state(sv_state* h)
 {
-    if (!h->e0_pending) return SV_OK;
-    h->e0_pending = false;
-    TRY(h, launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << h->n, true));
+    if (h->e0_pending) {
+        h->e0_pending = false;
+        h->garbage = false;
+        TRY(h, launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << h->n, true));
+        return SV_OK;
+    }
+    if (h->garbage) {
+        h->garbage = false;
+        TRY(h, launch_zero_outside(h->stream, h->dev, h->dtype, h->n, h->support));
+    }
     return SV_OK;
 }
 
@@ -208,9 +220,19 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 }
                 int tused = 0;
                 const bool last = j == nops && norm_out != nullptr;
+                const bool track = !h->tier;
+                const bool h_garbage_before = h->garbage;
+                const uint64_t support_before = h->support;
+                uint64_t pmask = 0, visited = 0;
                 TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, stage_t, from_e0,
-                                    last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused));
+                                    last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused,
+                                    track ? h->support : ~0ull, track && h->garbage, &pmask, &visited));
                 h->e0_pending = false;
+                if (track) {
+                    const uint64_t full = ((uint64_t)1 << nloc) - 1;
+                    h->support |= pmask;
+                    if ((h->support & full) == full) h->garbage = false;
+                }
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
                     double f = 0.0, fi = 0.0;
@@ -218,20 +240,26 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                         f += block_flops_alg(ks[c]);
                         fi += 6.0 * (double)(1 << ks[c]);
                     }
-                    const double amps = (double)((uint64_t)1 << nloc);
-                    h->tev_info.push_back({1, f * amps, fi * amps});
+                    // from |0...0> nothing is read; amplitudes on positions
+                    // not reached yet are taken as zero, not read
+                    const double amps = (double)visited;
+                    double rd = from_e0 ? 0.0 : amps;
+                    if (!from_e0 && track && h_garbage_before)
+                        rd = std::ldexp(amps, -__builtin_popcountll(pmask & ~support_before));
+                    h->tev_info.push_back({1, f * amps, fi * amps, 8.0 * (amps + rd)});
                 }
                 h->counters[0] += 1;
-                h->counters[3] += (int64_t)1 << nloc;
+                h->counters[3] += (int64_t)visited;
                 h->counters[7] += cnt;
                 i = j - 1;
                 continue;
             }
         }
-        if (h->e0_pending) {
+        if (h->e0_pending || h->garbage) {
             const int rc = materialize_state(h);
             if (rc) return rc;
         }
+        h->support = ~0ull;
         if (op.kind == OP_DENSE) {
             DiagSpec fold;
             const DiagSpec* fp = nullptr;
@@ -256,7 +284,8 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 TRY(h, hipEventRecord(e1, st));
                 const double amps = (double)((uint64_t)1 << nloc);
                 h->tev_info.push_back({0, block_flops_alg(op.k) * amps,
-                                       block_flops_issued(h->dtype, op.k, nloc, h->mfma_min_k) * amps});
+                                       block_flops_issued(h->dtype, op.k, nloc, h->mfma_min_k) * amps,
+                                       2.0 * (double)h->amp * amps});
             }
             h->counters[0] += 1;
             h->counters[3] += (int64_t)1 << nloc;
@@ -644,6 +673,8 @@ int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr)
         rc = run_ops(h, h->stream, &cur, h->scratch, h->n, 0, norm_out, norm_blocks);
         if (rc) return rc;
         if (cur != h->dev) return set_err(h, SV_EDEVICE, "internal: permute left in scratch");
+        rc = materialize_state(h);   // tiles the passes skipped hold older values
+        if (rc) return rc;
     } else {
         TRY(h, hipEventRecord(h->ev_arena, h->stream));
         TRY(h, hipStreamWaitEvent(h->s_in, h->ev_arena, 0));
@@ -1192,6 +1223,8 @@ int sv_reset(sv_handle h)
     h->arena.clear();
     if (!h->tier) {
         h->e0_pending = true;        // written by the first pass or on demand
+        h->support = h->sparse_start ? 0 : ~0ull;
+        h->garbage = h->sparse_start;
         return SV_OK;
     }
     TRY(h, hipStreamSynchronize(h->stream));
@@ -1232,6 +1265,7 @@ int sv_device_buffer(sv_handle h, void** dev, size_t* bytes)
         const int rc = materialize_state(h);
         if (rc) return rc;
     }
+    h->support = ~0ull;              // the caller may write it
     *dev = h->tier ? nullptr : h->dev;
     *bytes = h->tier ? 0 : ((size_t)1 << h->n) * h->amp;
     return SV_OK;
@@ -1247,6 +1281,7 @@ int sv_set_option(sv_handle h, int option, int64_t value)
         case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
         case SV_OPT_STAGE: h->stage_t = (int)value; return SV_OK;
         case SV_OPT_FAIL_IO: h->fail_io_at = value; return SV_OK;
+        case SV_OPT_SPARSE_START: h->sparse_start = value != 0; return SV_OK;
     }
     return set_err(h, SV_EINVAL, "unknown option");
 }
@@ -1267,6 +1302,7 @@ static void reset_timing(sv_state* h)
         h->tk_count[k] = 0;
         h->tk_flops[k] = 0.0;
         h->tk_issued[k] = 0.0;
+        h->tk_bytes[k] = 0.0;
     }
 }
 
@@ -1281,7 +1317,8 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
     return SV_OK;
 }
 
-int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2])
+int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2],
+                     double bytes[2])
 {
     CHECK_HANDLE(h);
     int rc = collect_timing(h);
@@ -1291,6 +1328,7 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
         if (count) count[k] = h->tk_count[k];
         if (flops) flops[k] = h->tk_flops[k];
         if (issued) issued[k] = h->tk_issued[k];
+        if (bytes) bytes[k] = h->tk_bytes[k];
     }
     reset_timing(h);
     return SV_OK;

@@ -322,10 +322,11 @@ int sv_batch_launch(sv_batch b)
         if (h->poisoned) return SV_ESTATE;
         if (!h->ops.empty()) return berr(b, SV_EINVAL, "state has operations queued after the batch was prepared");
         // a deferred reset is written on the state's stream, ahead of the batch
-        if (h->e0_pending) {
+        if (h->e0_pending || h->garbage) {
             const int rc = materialize_e0(h);
             if (rc) return rc;
         }
+        h->support = ~0ull;
         if (hipEventRecord(b->ev_in[i], h->stream) != hipSuccess ||
             hipStreamWaitEvent(b->stream, b->ev_in[i], 0) != hipSuccess)
             return berr(b, SV_EDEVICE, "stream ordering failed");

@@ -105,14 +105,24 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // is |0...0> and is not read (the pass writes every amplitude).  norm_out
 // (non-null): each workgroup writes the FP64 sum of |psi|^2 of the amplitudes
 // it wrote to norm_out[workgroup]; *norm_blocks receives the workgroup count
-// (at most 1024).
+// (at most 1024).  support: positions on which the state may be non-zero
+// (every other bit of a non-zero amplitude's index is 0); only tiles whose
+// id bits lie on support positions are visited, the others hold zeros and
+// stay zero.  garbage: the memory outside the support's reach is not zero,
+// so tile amplitudes with a bit on a tile position outside the support are
+// taken as zero instead of read.  *tile_mask_out: the tile's positions;
+// *amps_out: amplitudes visited.
 int stage_lds_bytes(int t, int nops, const int* ks);
 // Sets the staged kernels' LDS attribute for every tile width (idempotent;
 // launch_stage does it on first use, graph capture needs it beforehand).
 hipError_t stage_prepare();
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
-                        int* t_out);
+                        int* t_out, uint64_t support = ~0ull, bool garbage = false,
+                        uint64_t* tile_mask_out = nullptr, uint64_t* amps_out = nullptr);
+
+// Zeroes every amplitude whose index has a bit outside `support`.
+hipError_t launch_zero_outside(hipStream_t st, void* psi, int dtype, int nloc, uint64_t support);
 
 // Diagonal op on its own: psi[i] *= table[c(i + idx_offset)].
 hipError_t launch_diag(hipStream_t st, void* psi, int dtype, int nloc, uint64_t idx_offset,

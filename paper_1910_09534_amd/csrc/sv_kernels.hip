@@ -3,6 +3,7 @@
 // Every kernel streams the amplitude array once (read + write) and keeps the
 // per-amplitude arithmetic in registers:
 //   k_fill    initial state |0...0>                           (8/16 B per amp)
+//   k_zero_outside  clear amplitudes outside the reached positions
 //   k_dense   fused dense 2^k x 2^k block, optional folded diagonal epilogue
 //             (Sec. 5 aggregate gates; Sec. 2 diagonal gates as phases)
 //   k_diag    diagonal op on its own                          (Sec. 2 hyperedges)
@@ -99,6 +100,30 @@ hipError_t launch_init(hipStream_t st, void* psi, int dtype, uint64_t count, boo
     }
     const uint64_t n16 = bytes / 16;
     hipLaunchKernelGGL(k_fill, dim3(grid_for(n16, 256)), dim3(256), 0, st, (uint4*)psi, n16, first);
+    return hipGetLastError();
+}
+
+// amplitudes whose index has a bit outside `support` are zero; memory that
+// still holds older values there is cleared (8/16 B written per such amp)
+template <typename T>
+__global__ __launch_bounds__(256) void k_zero_outside(T* __restrict__ p, uint64_t n, uint64_t outside)
+{
+    const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride)
+        if (i & outside) p[i] = T{};
+}
+
+hipError_t launch_zero_outside(hipStream_t st, void* psi, int dtype, int nloc, uint64_t support)
+{
+    const uint64_t n = 1ull << nloc;
+    const uint64_t outside = (n - 1) & ~support;
+    if (!outside) return hipSuccess;
+    if (dtype)
+        hipLaunchKernelGGL(k_zero_outside<double2>, dim3(grid_for(n, 256)), dim3(256), 0, st, (double2*)psi, n,
+                           outside);
+    else
+        hipLaunchKernelGGL(k_zero_outside<float2>, dim3(grid_for(n, 256)), dim3(256), 0, st, (float2*)psi, n,
+                           outside);
     return hipGetLastError();
 }
 

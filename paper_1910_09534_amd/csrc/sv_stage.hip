@@ -32,7 +32,16 @@ constexpr int kStageThreads = 256;          // lanes per workgroup (four waves)
 
 struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
-    uint64_t tile_lowmask[kStageMaxT];       // (1 << P[b]) - 1, ascending (tile-id spreading)
+    // tile id bits go, in ascending order, to the set bits of tmask (the
+    // positions outside the tile that can be non-zero); consecutive tiles of
+    // a workgroup are gridDim.x apart, their bases tstep = that stride
+    // spread onto tmask apart (added in the masked number system)
+    uint64_t tmask;
+    uint64_t tstep;
+    // amplitudes on tile positions no earlier operation has reached are
+    // zero but their memory may hold older values: tile-local index bits
+    // (bit b = position P[b]) of such elements, cleared in LDS
+    uint32_t newmask_t;
     uint64_t dep_lane[8];                    // global offset of element bit b (lane bits, b < 8)
     uint64_t dep_i[32];                      // global offset of element bits 8.. (i = e >> 8)
     int t;
@@ -186,6 +195,19 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
 // lane part of an element's address needs more than 32 bits of byte offset
 // (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
 // per-lane offset, so loads and stores take the scalar-base form).
+// bits of x, in ascending order, onto the set bits of m (host and device)
+__host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
+{
+    uint64_t r = 0;
+    while (m && x) {
+        const uint64_t low = m & (~m + 1);
+        if (x & 1) r |= low;
+        x >>= 1;
+        m &= m - 1;
+    }
+    return r;
+}
+
 template <int TW, bool WIDE>
 __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ psi, StageK a)
 {
@@ -218,44 +240,47 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         if (WIDE) return psi + (tb + dl + a.dep_i[i]);
         return (float2*)((char*)(psi + (tb + a.dep_i[i])) + dlb);
     };
-    auto tile_base = [&](uint64_t tile) {
-        uint64_t base = tile;
-        for (int b = 0; b < TW; ++b) {
-            const uint64_t lw = base & a.tile_lowmask[b];
-            base = ((base ^ lw) << 1) | lw;
-        }
-        return base;
-    };
+
     const int ls = lslot(threadIdx.x);                          // + lslot(256 i) = 272 i
     float2 xr[PER];
     // |0...0>: only element 0 of tile 0 (lane 0, i = 0) is non-zero
-    auto load_tile = [&](uint64_t tile) {
+    auto load_tile = [&](uint64_t tile, uint64_t tb) {
         if (a.from_e0) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) xr[i] = float2{0.f, 0.f};
             if (tile == 0 && threadIdx.x == 0) xr[0].x = 1.f;
         } else {
-            const uint64_t tb = tile_base(tile);
 #pragma unroll
             for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
         }
     };
-    double nacc = 0.0;                                           // this lane's sum of |psi|^2
-    uint64_t tile = blockIdx.x;
-    if (tile < a.tiles) {
-        load_tile(tile);
+    auto park = [&]() {
 #pragma unroll
         for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
+    };
+    double nacc = 0.0;                                           // this lane's sum of |psi|^2
+    uint64_t tile = blockIdx.x;
+    uint64_t tb = spread_bits(tile, a.tmask);
+    if (tile < a.tiles) {
+        load_tile(tile, tb);
+        park();
     }
     __syncthreads();
     // Per tile: issue the next tile's loads, run the blocks on the LDS tile,
     // store it, then park the next tile.  Its loads precede this tile's
     // stores, so parking waits for the loads only, never for the stores.
     for (; tile < a.tiles; tile += gridDim.x) {
-        const uint64_t tb = tile_base(tile);
+        if (a.newmask_t) {
+            // tile elements on positions no operation has reached were read
+            // from memory that may hold older values: they are zero
+            for (int j = threadIdx.x; j < (1 << TW); j += kStageThreads)
+                if (j & a.newmask_t) T[lslot(j)] = float2{0.f, 0.f};
+            __syncthreads();
+        }
         const uint64_t nt = tile + gridDim.x;
+        const uint64_t nb = ((tb | ~a.tmask) + a.tstep) & a.tmask;
         const bool next = nt < a.tiles;
-        if (next) load_tile(nt);
+        if (next) load_tile(nt, nb);
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
             if (a.op_k[o] == 5) stage_block<5>(a, o, As, T, wave);
@@ -276,10 +301,10 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         }
         __syncthreads();
         if (next) {
-#pragma unroll
-            for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
+            park();
         }
         __syncthreads();
+        tb = nb;
     }
     if (a.norm_out) {
         // fixed-order tree over the workgroup's lanes (the tile buffer is free)
@@ -322,7 +347,8 @@ hipError_t stage_prepare()
 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
-                        int* t_out)
+                        int* t_out, uint64_t support, bool garbage, uint64_t* tile_mask_out,
+                        uint64_t* amps_out)
 {
     if (t_max > kStageMaxT) t_max = kStageMaxT;
     if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
@@ -354,8 +380,18 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.nops = nops;
     a.from_e0 = from_e0 ? 1 : 0;
     a.norm_out = norm_out;
-    a.tiles = 1ull << (nloc - t);
-    for (int b = 0; b < t; ++b) a.tile_lowmask[b] = (1ull << P[b]) - 1;
+    // tiles: only those whose id bits lie on positions that may be non-zero
+    // (support); the other tiles hold zeros and stay zero
+    uint64_t pmask = 0;
+    for (int b = 0; b < t; ++b) pmask |= 1ull << P[b];
+    const uint64_t full = nloc >= 64 ? ~0ull : ((1ull << nloc) - 1);
+    support &= full;
+    a.tmask = full & ~pmask & support;
+    a.tiles = 1ull << __builtin_popcountll(a.tmask);
+    const uint64_t newmask = (garbage && !from_e0) ? (pmask & ~support) : 0;
+    a.newmask_t = 0;
+    for (int b = 0; b < t; ++b)
+        if ((newmask >> P[b]) & 1) a.newmask_t |= 1u << b;
     for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
     for (int i = 0; i < (1 << (t - 8)); ++i) {
         uint64_t d = 0;
@@ -413,9 +449,12 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t grid = a.tiles;
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
+    a.tstep = spread_bits(grid, a.tmask);
     hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kStageThreads), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     if (norm_blocks) *norm_blocks = norm_out ? (int)grid : 0;
+    if (tile_mask_out) *tile_mask_out = pmask;
+    if (amps_out) *amps_out = a.tiles << t;
     return hipGetLastError();
 }
 

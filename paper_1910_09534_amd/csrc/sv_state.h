@@ -85,6 +85,13 @@ struct sv_state {
     int mfma_min_k = 4;
     int stage_t = 13;
     bool e0_pending = false;     // resident state is |0...0> but not yet written (sv_reset)
+    // Resident states after sv_reset: every amplitude whose index has a bit
+    // outside `support` is zero (the positions no operation has touched since
+    // the reset), and while `garbage` is set the memory there may still hold
+    // older values.  Staged passes visit only the tiles inside the support.
+    uint64_t support = ~0ull;
+    bool garbage = false;
+    bool sparse_start = true;
     int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;
@@ -92,6 +99,7 @@ struct sv_state {
         int kind;           // 0 single sweep, 1 staged pass
         double flops;       // algorithmic: (8 2^k - 2) per amplitude per block
         double issued;      // as executed: 6 2^k (3M, matrix cores) or 8 2^k (vector units)
+        double bytes;       // HBM bytes the launch must move: amplitudes read + written
     };
     std::vector<TimedLaunch> tev_info;              // per event pair
     size_t tev_used = 0;
@@ -101,6 +109,7 @@ struct sv_state {
     int64_t tk_count[2] = {0, 0};
     double tk_flops[2] = {0.0, 0.0};
     double tk_issued[2] = {0.0, 0.0};
+    double tk_bytes[2] = {0.0, 0.0};
     int64_t counters[8] = {};
 
     bool poisoned = false;

@@ -19,6 +19,7 @@ SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, 
 SV_C64, SV_C128 = 0, 1
 SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE = 0x100, 0x200, 0x400
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
+SV_OPT_SPARSE_START = 7
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
@@ -60,7 +61,7 @@ def load():
     L.sv_set_option.argtypes = [P, I, I64]
     L.sv_counters.argtypes = [P, P]
     L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
-    L.sv_sweep_profile.argtypes = [P, P, P, P, P]
+    L.sv_sweep_profile.argtypes = [P, P, P, P, P, P]
     L.sv_batch_prepare.argtypes = [I, P, I, P, ctypes.POINTER(P)]
     L.sv_batch_launch.argtypes = [P]
     L.sv_batch_sync.argtypes = [P]
@@ -212,14 +213,16 @@ def sweep_time(h):
 
 def sweep_profile(h) -> dict:
     """Timed launches by kind ("sweep": single dense sweeps, "staged":
-    staged passes): ms, count, algorithmic flops, issued flops.  Resets the
-    timing accumulators."""
+    staged passes): ms, count, algorithmic flops, issued flops, HBM bytes
+    moved.  Resets the timing accumulators."""
     ms = np.zeros(2, dtype=np.float64)
     cnt = np.zeros(2, dtype=np.int64)
     fl = np.zeros(2, dtype=np.float64)
     iss = np.zeros(2, dtype=np.float64)
-    _check(lib().sv_sweep_profile(h, _ptr(ms), _ptr(cnt), _ptr(fl), _ptr(iss)), h)
-    return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i]), "issued": float(iss[i])}
+    by = np.zeros(2, dtype=np.float64)
+    _check(lib().sv_sweep_profile(h, _ptr(ms), _ptr(cnt), _ptr(fl), _ptr(iss), _ptr(by)), h)
+    return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i]), "issued": float(iss[i]),
+                   "bytes": float(by[i])}
             for i, kind in enumerate(("sweep", "staged"))}
 
 

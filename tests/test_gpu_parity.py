@@ -327,8 +327,19 @@ def test_sweep_profile_splits_kinds():
         assert p["sweep"]["issued"] == 8.0 * 8 * (1 << n)
         assert p["sweep"]["flops"] == (8.0 * 8 - 2) * (1 << n)
         assert p["staged"]["ms"] > 0 and p["sweep"]["ms"] > 0
+        assert p["staged"]["bytes"] == 16.0 * (1 << n) and p["sweep"]["bytes"] == 16.0 * (1 << n)
         q = sv.sweep_profile(h)              # reset by the previous call
         assert q["staged"]["count"] == 0 and q["sweep"]["count"] == 0
+        # from |0...0> the pass visits the one tile that can be non-zero and
+        # reads nothing
+        sv.reset(h)
+        for qs, k in blocks:
+            sv.apply_fused(h, qs, W.random_unitary(1 << k, rng), "c64")
+        sv.sync_state(h)
+        r = sv.sweep_profile(h)["staged"]
+        visited = r["flops"] / (8.0 * 32 - 2 + 8.0 * 16 - 2 + 8.0 * 32 - 2)
+        assert r["count"] == 1 and visited in (2.0 ** 12, 2.0 ** 13)
+        assert r["bytes"] == 8.0 * visited
     finally:
         sv.destroy_state(h)
 
@@ -362,6 +373,61 @@ def test_deferred_reset(first):
             sv.sync_state(h)
         if first == "staged":
             assert sv.counters(h)["staged_blocks"] >= 9
+    finally:
+        sv.destroy_state(h)
+
+
+@pytest.mark.parametrize("case", ["read", "sweep", "diag", "chain", "chain-t11", "norm"])
+def test_sparse_start_after_reset(case):
+    """After sv_reset only the positions some operation has touched can hold
+    non-zero amplitudes; staged passes visit only the tiles inside that
+    support and take the never-written part of their tile as zero.  The
+    buffer is dirtied before every reset, then the queue reads the state
+    before every position is reached, runs a plain sweep or a diagonal in
+    between, or reaches all positions pass by pass."""
+    n = 20
+    rng = np.random.default_rng(["read", "sweep", "diag", "chain", "chain-t11", "norm"].index(case) + 40)
+    h, t = state_from_numpy(W.random_state(n, rng), "c64")
+    if case == "chain-t11":
+        sv.set_option(h, sv.SV_OPT_STAGE, 11)
+    U = lambda k: W.random_unitary(1 << k, rng)
+    try:
+        for rep in range(2):
+            sv.reset(h)
+            c0 = sv.counters(h)["amps_swept"]
+            ops = [("d", [4, 5, 6, 7, 8], U(5)), ("d", [5, 6, 7, 8, 9], U(5))]
+            if case == "sweep":
+                ops += [("d", [14, 16, 18], U(3))]
+            if case == "diag":
+                ops += [("g", [15, 17], np.exp(1j * rng.uniform(0, 6.3, 4)))]
+            if case in ("sweep", "diag", "chain", "chain-t11"):
+                ops += [("d", [13, 14, 15, 16], U(4)), ("d", [15, 16, 17, 18], U(4)),
+                        ("d", [19, 4, 5, 6], U(4)), ("d", [18, 19, 2, 10], U(4))]
+            for kind, qs, m in ops:
+                if kind == "d":
+                    sv.apply_fused(h, qs, m, "c64")
+                else:
+                    sv.apply_diag(h, qs, m, "c64")
+            ref = orc.zero_state(n)
+            for kind, qs, m in ops:
+                if kind == "d":
+                    orc.apply_dense(ref, qs, m)
+                else:
+                    orc.apply_diag(ref, qs, m)
+            if case == "norm":
+                bits = W.bitstrings(n, 256, seed=rep)
+                amps, stats = sv.reduce_slices(h, bits)
+                assert abs(stats[0] - orc.norm(ref)) <= 2e-6
+                assert orc.rel_l2(amps, orc.gather(ref, bits)) <= 1e-5
+            else:
+                got = read_all(h, n)
+                assert orc.rel_l2(got, ref) <= 1e-5
+            if case.startswith("chain"):
+                # the first two passes visit a fraction of the state only
+                assert sv.counters(h)["amps_swept"] - c0 < 3 * (1 << n)
+            # dirty the whole buffer for the next reset
+            sv.apply_fused(h, [0, 1, 2], U(3), "c64")
+            sv.sync_state(h)
     finally:
         sv.destroy_state(h)
 
