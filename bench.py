@@ -245,7 +245,7 @@ def main(argv=None) -> int:
     circ = W.config_circuit(2)
     bits = W.config_bitstrings(2)
     n = circ.n
-    ops = planner.plan(circ.gates, args.kmax)
+    ops = planner.plan(circ.gates, args.kmax, sparse_start=True)   # each step starts from a reset
     for o in ops:                                 # pre-cast once (host, untimed)
         o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     pst = planner.stats(ops)
@@ -284,14 +284,23 @@ def main(argv=None) -> int:
     sv.set_option(h, sv.SV_OPT_TIMING, 0)
     visited = (c1["amps_swept"] - c0["amps_swept"]) / args.steps
 
-    # the same steps with every pass over the whole state (no sparse start
-    # after the reset), for comparison
+    # for comparison: every pass over the whole state (no sparse start
+    # after the reset), with the plan ranked for that
+    dense_ops = planner.plan(circ.gates, args.kmax)
+    for o in dense_ops:
+        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+
+    def dense_step():
+        sv.reset(h)
+        planner.enqueue(h, dense_ops, sv.SV_C64)
+        return sv.reduce_slices(h, bits)
+
     sv.set_option(h, sv.SV_OPT_SPARSE_START, 0)
-    step()
+    dense_step()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        dense_step()
     torch.cuda.synchronize()
     dense_ms = 1e3 * (time.perf_counter() - t0) / args.steps
     sv.set_option(h, sv.SV_OPT_SPARSE_START, 1)

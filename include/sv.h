@@ -191,12 +191,13 @@ enum {
     SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer
                               from now on (n >= 1) is not issued and reports SV_EIO,
                               poisoning the handle; 0 (default): off */
-    SV_OPT_SPARSE_START = 7 /* 1 (default): after sv_reset of a resident state, staged
-                              passes visit only the tiles whose amplitudes can be
-                              non-zero (positions some operation has touched); the
-                              rest is zero-filled before the amplitudes are read.
-                              0: every pass visits the whole state.  Takes effect at
-                              the next sv_reset. */
+    SV_OPT_SPARSE_START = 7 /* 1 (default): a resident state created as |0...0> or
+                              reset with sv_reset is non-zero only on index bits some
+                              operation has targeted since; staged passes visit only
+                              the tiles inside them and widen their tile with them
+                              only; after a reset the rest is zero-filled before the
+                              amplitudes are read.  0: every pass visits the whole
+                              state.  Takes effect at the next sv_reset. */
 };
 int sv_set_option(sv_handle h, int option, int64_t value);
 

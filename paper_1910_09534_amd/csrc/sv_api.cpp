@@ -229,8 +229,10 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                                     track ? h->support : ~0ull, track && h->garbage, &pmask, &visited));
                 h->e0_pending = false;
                 if (track) {
+                    // the other tile positions were zero and stay zero
                     const uint64_t full = ((uint64_t)1 << nloc) - 1;
-                    h->support |= pmask;
+                    for (int c = 0; c < cnt; ++c)
+                        for (int q = 0; q < ks[c]; ++q) h->support |= (uint64_t)1 << pp[c][q];
                     if ((h->support & full) == full) h->garbage = false;
                 }
                 if (h->timing) {
@@ -859,6 +861,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
     } else if (!(ext && (dtype & SV_FLAG_KEEP))) {
         e = launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << n, true);
         if (e != hipSuccess) { release(h); return fail_dev(nullptr, "init kernel", e); }
+        h->support = 0;              // |0...0>, written in full: nothing stale
     }
     h->d_small = pool_alloc(64, false, nullptr);
     if (!h->d_small) {
@@ -1113,6 +1116,11 @@ int permute_qubits(sv_handle h, const int* order)
         TRY(h, launch_bitperm(h->stream, h->dev, h->scratch, h->dtype, h->n, r));
         TRY(h, hipMemcpyAsync(h->dev, h->scratch, ((size_t)1 << h->n) * h->amp,
                               hipMemcpyDeviceToDevice, h->stream));
+        // the positions that can be non-zero move with their qubits
+        uint64_t moved = 0;
+        for (int q = 0; q < h->n; ++q)
+            if ((h->support >> h->pos[q]) & 1) moved |= (uint64_t)1 << npos[q];
+        h->support = moved;
         h->counters[2] += 1;
         h->counters[3] += (int64_t)1 << h->n;
     } else {

@@ -108,7 +108,7 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // (at most 1024).  support: positions on which the state may be non-zero
 // (every other bit of a non-zero amplitude's index is 0); only tiles whose
 // id bits lie on support positions are visited, the others hold zeros and
-// stay zero.  garbage: the memory outside the support's reach is not zero,
+// stay zero, and the tile is widened with support positions only.  garbage: the memory outside the support's reach is not zero,
 // so tile amplitudes with a bit on a tile position outside the support are
 // taken as zero instead of read.  *tile_mask_out: the tile's positions;
 // *amps_out: amplitudes visited.

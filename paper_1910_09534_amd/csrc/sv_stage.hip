@@ -364,13 +364,16 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     // widen the tile with the lowest free positions up to t_max (or the LDS
     // limit): a block has 2^(t-k-4) 16-group units per tile for the
     // workgroup's four waves (8 for k = 5 at t = 12), and the tile's
-    // contiguous runs are longer
-    for (int p = 0; p < nloc && cnt < t_max; ++p) {
-        if (in[p]) continue;
-        if (stage_lds_bytes(cnt + 1, nops, ks) > kStageMaxLds) break;
-        in[p] = true;
-        ++cnt;
-    }
+    // contiguous runs are longer.  Only positions inside the support: one
+    // outside it would double the amplitudes visited (beyond the 9 the
+    // kernel needs).
+    for (int round = 0; round < 2; ++round)
+        for (int p = 0; p < nloc && cnt < (round ? 9 : t_max); ++p) {
+            if (in[p] || (round == 0 && !((support >> p) & 1))) continue;
+            if (stage_lds_bytes(cnt + 1, nops, ks) > kStageMaxLds) break;
+            in[p] = true;
+            ++cnt;
+        }
     int P[64], t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;

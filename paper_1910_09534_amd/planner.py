@@ -394,6 +394,123 @@ def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) ->
     return tot
 
 
+# Launch overhead of a staged pass (ms) that touches only a few tiles.
+STAGE_MS_LAUNCH = 0.02
+
+
+def sparse_passes(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[int] = None,
+                  support: int = 0) -> List[Tuple[List[int], int]]:
+    """The passes `ops` run as from |0...0> (after sv_reset), each with the
+    log2 of the amplitudes it visits, mirroring the device: a staged pass
+    visits only the tiles whose id bits lie on positions some earlier op
+    targeted (`support`), widens its tile with support positions only
+    (others only up to the 9 a tile needs), and adds its targets to the
+    support; any other sweep visits the whole state and makes the support
+    full."""
+    tmax = STAGE_T if tmax is None else tmax
+    pos = (lambda q: q) if pos_of is None else pos_of
+    full = (1 << nloc) - 1
+    S = support & full
+    out: List[Tuple[List[int], int]] = []
+    for r in stage_runs(ops, pos_of, tmax):
+        if len(r) < 2:
+            out.append((r, nloc))
+            S = full
+            continue
+        ks = [len(ops[i].qubits) for i in r]
+        tg = 0
+        for i in r:
+            for q in ops[i].qubits:
+                tg |= 1 << pos(q)
+        P = tg | 0xF
+        t = bin(P).count("1")
+        for rnd in (0, 1):
+            for p_ in range(nloc):
+                if t >= (9 if rnd else tmax):
+                    break
+                if (P >> p_) & 1 or (rnd == 0 and not (S >> p_) & 1):
+                    continue
+                if _stage_lds(t + 1, ks) > STAGE_LDS:
+                    break
+                P |= 1 << p_
+                t += 1
+        out.append((r, t + bin(S & ~P).count("1")))
+        S |= tg
+    return out
+
+
+def sparse_cost(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[int] = None,
+                support: int = 0) -> float:
+    """Modelled time of `ops` run from |0...0> (`sparse_passes`): a pass
+    costs its full-state model time scaled by the share of the state it
+    visits, plus a launch overhead for staged passes."""
+    tot = 0.0
+    for r, lv in sparse_passes(ops, nloc, pos_of, tmax, support):
+        if len(r) < 2:
+            o = ops[r[0]]
+            tot += SWEEP_MS.get(len(o.qubits), 4.0) if o.kind == "dense" else SWEEP_MS[1]
+            continue
+        base = max(STAGE_MS_MEM, STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r))
+        tot += base * 2.0 ** (lv - nloc) + STAGE_MS_LAUNCH
+    return tot
+
+
+def activation_orders(gates, n: int) -> List[List[int]]:
+    """Orders in which to bring qubits into play when running from
+    |0...0>: both directions of the Fiedler vector of the coupling graph
+    (the qubits sorted along the graph's longest axis, so the front
+    between touched and untouched qubits stays a narrow cut), and both
+    directions of the qubit index."""
+    A = np.zeros((n, n))
+    for g in gates:
+        qs = list(g.qubits)
+        for a in qs:
+            for b in qs:
+                if a != b:
+                    A[a, b] = 1.0
+    Lp = np.diag(A.sum(1)) - A
+    _, vec = np.linalg.eigh(Lp)
+    f = vec[:, 1] if n > 1 else np.zeros(n)
+    fied = sorted(range(n), key=lambda q: (f[q], q))
+    return [fied, fied[::-1], list(range(n)), list(range(n))[::-1]]
+
+
+def support_order(gates, act: Sequence[int]) -> list:
+    """The gates in a dependency-respecting order that touches new qubits as
+    late as possible: every gate whose qubits are all in play runs (earliest
+    first) before the next qubit of `act` is brought into play."""
+    n_g = len(gates)
+    npred = [0] * n_g
+    succ: List[List[int]] = [[] for _ in range(n_g)]
+    last: Dict[int, int] = {}
+    for i, g in enumerate(gates):
+        ps = {last[q] for q in g.qubits if q in last}
+        for p_ in ps:
+            succ[p_].append(i)
+        npred[i] = len(ps)
+        for q in g.qubits:
+            last[q] = i
+    ready = {i for i in range(n_g) if npred[i] == 0}
+    live: set = set()
+    out: list = []
+    k = 0
+    while ready:
+        ins = [i for i in ready if all(q in live for q in gates[i].qubits)]
+        if not ins:
+            live.add(act[k])
+            k += 1
+            continue
+        i = min(ins)
+        ready.discard(i)
+        out.append(gates[i])
+        for s_ in succ[i]:
+            npred[s_] -= 1
+            if npred[s_] == 0:
+                ready.add(s_)
+    assert len(out) == n_g
+    return out
+
+
 def widen_small_blocks(ops: Sequence["Op"], pos_of=None) -> List["Op"]:
     """Dense blocks on fewer than 4 qubits become 4-qubit blocks (identity on
     the added qubits, exact) by adding the qubits at positions 0..3, which
@@ -440,28 +557,44 @@ def plan_fast(gates, kmax: int, pos_of=None, nloc: Optional[int] = None) -> List
     return order_for_staging(widen_small_blocks(ops, pos_of), pos_of, tmax)
 
 
+def _staged_candidates(gates, kmax: int, pos_of, tmax: int) -> List[List[Op]]:
+    cands = [fuse(gates, kmax)]
+    for w in (3, 4, 5, 6, 8):
+        cands.append(fuse_grow(gates, kmax, window=w))
+    if kmax >= 3:
+        for w in (3, 4, 5, 6, 8):
+            for g in (0.2, 0.4, 0.6, 0.8, 1.0):
+                cands.append(fuse_grow(gates, kmax, window=w, last_gain=g))
+    return [order_for_staging(widen_small_blocks(c, pos_of), pos_of, tmax) for c in cands]
+
+
 def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None,
-         nloc: Optional[int] = None) -> List[Op]:
+         nloc: Optional[int] = None, sparse_start: bool = False) -> List[Op]:
     """Aggregate with every available heuristic and keep the cheapest plan.
 
     staged (complex64 states): blocks on fewer than 4 qubits are widened to
     4 (`widen_small_blocks`), commuting blocks are ordered for staged passes
     (`order_for_staging`; positions given by pos_of, default position =
     qubit) and the candidates are ranked by `staged_cost`; otherwise they
-    are ranked by `plan_cost`."""
-    cands = [fuse(gates, kmax, fold_diag=fold_diag)]
-    if not fold_diag:
-        for w in (3, 4, 5, 6, 8):
-            cands.append(fuse_grow(gates, kmax, window=w))
-    tmax = stage_tmax(_nloc_of(gates) if nloc is None else nloc) if staged else 0
+    are ranked by `plan_cost`.  sparse_start (the ops run right after
+    sv_reset): the gates are also tried in orders that bring qubits into
+    play late (`support_order` over `activation_orders`), and the
+    candidates are ranked by `sparse_cost`."""
+    n_loc = _nloc_of(gates) if nloc is None else nloc
+    tmax = stage_tmax(n_loc) if staged else 0
     if not tmax or fold_diag:
+        cands = [fuse(gates, kmax, fold_diag=fold_diag)]
+        if not fold_diag:
+            for w in (3, 4, 5, 6, 8):
+                cands.append(fuse_grow(gates, kmax, window=w))
         return min(cands, key=plan_cost)
-    if kmax >= 3:
-        for w in (3, 4, 5, 6, 8):
-            for g in (0.2, 0.4, 0.6, 0.8, 1.0):
-                cands.append(fuse_grow(gates, kmax, window=w, last_gain=g))
-    cands = [order_for_staging(widen_small_blocks(c, pos_of), pos_of, tmax) for c in cands]
-    return min(cands, key=lambda c: staged_cost(c, pos_of, tmax))
+    cands = _staged_candidates(gates, kmax, pos_of, tmax)
+    if not sparse_start:
+        return min(cands, key=lambda c: staged_cost(c, pos_of, tmax))
+    n_q = 1 + max((q for g in gates for q in g.qubits), default=0)
+    for act in activation_orders(gates, n_q):
+        cands += _staged_candidates(support_order(gates, act), kmax, pos_of, tmax)
+    return min(cands, key=lambda c: sparse_cost(c, n_loc, pos_of, tmax))
 
 
 @dataclasses.dataclass

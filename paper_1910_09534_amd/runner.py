@@ -25,7 +25,7 @@ def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: b
     if stage is None:
         stage = planner.stage_tmax(circuit.n) if dtype == "c64" else 0
     ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag, staged=stage > 0,
-                       nloc=max(circuit.n, stage + 9) if stage else None)
+                       nloc=max(circuit.n, stage + 9) if stage else None, sparse_start=stage > 0)
     t_plan = time.perf_counter() - t0
     st = sv.State(circuit.n, 0, dtype, stream)
     try:

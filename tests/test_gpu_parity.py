@@ -432,6 +432,66 @@ def test_sparse_start_after_reset(case):
         sv.destroy_state(h)
 
 
+@pytest.mark.parametrize("reset", [False, True])
+def test_sparse_support_follows_permutes(reset):
+    """A fresh (or reset) state is non-zero only on the positions its ops
+    have targeted; a permute moves those positions with their qubits, and
+    later staged passes visit the moved support."""
+    n = 20
+    rng = np.random.default_rng(70 + reset)
+    U = lambda k: W.random_unitary(1 << k, rng)
+    st = sv.State(n, 0, "c64")
+    try:
+        if reset:
+            st.fused([0, 1, 2, 3, 4], U(5).astype(np.complex64))
+            st.sync()
+            sv.reset(st.h)
+        ref = orc.zero_state(n)
+        steps = [("f", [4, 5, 6, 7, 8], U(5)), ("f", [6, 7, 8, 9], U(4)),
+                 ("p", [int(x) for x in rng.permutation(n)], None),
+                 ("f", [7, 8, 15, 16], U(4)), ("f", [16, 17, 18, 19], U(4)),
+                 ("p", list(range(n))[::-1], None),
+                 ("f", [1, 2, 12, 19], U(4)), ("f", [9, 10, 11, 12, 13], U(5))]
+        for kind, qs, m in steps:
+            if kind == "f":
+                st.fused(qs, m.astype(np.complex64))
+                orc.apply_dense(ref, qs, m)
+            else:
+                st.permute(qs)
+        got = st.gather(np.arange(1 << n, dtype=np.uint64))
+    finally:
+        st.close()
+    assert orc.rel_l2(got, ref) <= 1e-5
+
+
+@pytest.mark.parametrize("n,depth", [(20, 12), (22, 10)])
+def test_sparse_start_plan_visits_as_modelled(n, depth):
+    """A circuit planned for a run from |0...0> after sv_reset: the state
+    equals the oracle's, and the amplitudes the passes visit equal the
+    planner's model of the device (tile positions, widening inside the
+    support, support growth), pass by pass in total."""
+    from paper_1910_09534_amd import planner
+    c = W.sycamore_circuit(n, depth, seed=60 + n)
+    tmax = planner.stage_tmax(n)
+    ops = planner.plan(c.gates, 5, sparse_start=True, nloc=n)
+    rng = np.random.default_rng(n)
+    h, t = state_from_numpy(W.random_state(n, rng), "c64")
+    sv.set_option(h, sv.SV_OPT_STAGE, tmax)
+    try:
+        for _ in range(2):
+            sv.reset(h)
+            c0 = sv.counters(h)["amps_swept"]
+            planner.enqueue(h, ops, sv.SV_C64)
+            sv.sync_state(h)
+            swept = sv.counters(h)["amps_swept"] - c0
+            predicted = sum(1 << lv for _, lv in planner.sparse_passes(ops, n, None, tmax))
+            assert swept == predicted
+            assert swept < len(planner.stage_runs(ops, None, tmax)) * (1 << n)
+            assert orc.rel_l2(read_all(h, n), orc.simulate(c)) <= 2e-5
+    finally:
+        sv.destroy_state(h)
+
+
 @pytest.mark.parametrize("last", ["staged", "single", "single-dense"])
 def test_norm_folded_into_last_staged_pass(last):
     """When the queue ends with a staged pass, that pass also sums |psi|^2

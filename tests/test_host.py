@@ -197,3 +197,51 @@ def test_staging_transforms_are_exact():
             pos = set(range(4)) | {q for i in run for q in ordered[i].qubits}
             assert len(pos) <= planner.STAGE_T and len(run) <= planner.STAGE_MAX_OPS
             assert all(len(ordered[i].qubits) in (4, 5) for i in run)
+
+
+def test_support_order_is_a_reassociation():
+    """Running gates in the order that brings qubits into play late keeps
+    every qubit's own gate order, hence the product (gates on disjoint
+    qubits commute); checked on the oracle for every activation order."""
+    c = W.sycamore_circuit(16, 10, seed=51)
+    ref = orc.simulate(c)
+    for act in planner.activation_orders(c.gates, c.n):
+        assert sorted(act) == list(range(c.n))
+        g2 = planner.support_order(c.gates, act)
+        assert len(g2) == len(c.gates)
+        for q in range(c.n):
+            assert [id(g) for g in c.gates if q in g.qubits] == [id(g) for g in g2 if q in g.qubits]
+        psi = orc.apply_gates(orc.zero_state(c.n), g2)
+        assert orc.rel_l2(psi, ref) < 1e-12
+
+
+def test_activation_order_follows_the_long_axis():
+    """On the 5 x 6 grid the Fiedler order brings in whole columns of five
+    (the narrow cut) one after another."""
+    c = W.config_circuit(2)
+    rows, cols = W.grid_shape(c.n)
+    fied = planner.activation_orders(c.gates, c.n)[0]
+    for j in range(0, c.n, rows):
+        assert len({q % cols for q in fied[j:j + rows]}) == 1
+
+
+def test_plan_sparse_start_is_exact_and_modelled():
+    """The sparse-start plan is the circuit's product; the pass model with
+    a full support reduces to the dense staged model plus launch overheads;
+    from |0...0> the first pass visits one tile."""
+    c = W.sycamore_circuit(16, 10, seed=52)
+    tmax = planner.stage_tmax(c.n)
+    ops = planner.plan(c.gates, 5, sparse_start=True, nloc=c.n)
+    assert np.abs(apply_ops_on_oracle(c.n, ops) - orc.simulate(c)).max() < 1e-12
+    full = (1 << c.n) - 1
+    nruns = sum(1 for r in planner.stage_runs(ops, None, tmax) if len(r) >= 2)
+    assert abs(planner.sparse_cost(ops, c.n, None, tmax, support=full)
+               - planner.staged_cost(ops, None, tmax) - planner.STAGE_MS_LAUNCH * nruns) < 1e-9
+    passes = planner.sparse_passes(ops, c.n, None, tmax)
+    r0, lv0 = passes[0]
+    if len(r0) >= 2:
+        P = {q for i in r0 for q in ops[i].qubits} | set(range(4))
+        assert lv0 == max(9, len(P))
+    assert all(lv <= c.n for _, lv in passes)
+    dense = planner.plan(c.gates, 5, nloc=c.n)
+    assert planner.sparse_cost(ops, c.n, None, tmax) <= planner.sparse_cost(dense, c.n, None, tmax) + 1e-9
