@@ -208,7 +208,7 @@ __host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
     return r;
 }
 
-template <int TW, bool WIDE>
+template <int TW, bool WIDE, bool ZERO>
 __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ psi, StageK a)
 {
     constexpr int PER = 1 << (TW - 8);
@@ -270,9 +270,10 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
     // store it, then park the next tile.  Its loads precede this tile's
     // stores, so parking waits for the loads only, never for the stores.
     for (; tile < a.tiles; tile += gridDim.x) {
-        if (a.newmask_t) {
+        if (ZERO) {
             // tile elements on positions no operation has reached were read
-            // from memory that may hold older values: they are zero
+            // from memory that may hold older values: they are zero (a
+            // variant of its own: the check in the loop of every pass costs)
             for (int j = threadIdx.x; j < (1 << TW); j += kStageThreads)
                 if (j & a.newmask_t) T[lslot(j)] = float2{0.f, 0.f};
             __syncthreads();
@@ -328,19 +329,36 @@ int stage_lds_bytes(int t, int nops, const int* ks)
     return tile_f4 * 16 + floats * 4;
 }
 
+// the variant for a tile of t positions (9..13), 64-bit lane offsets, and
+// clearing of stale elements
+static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
+{
+#define SV_STAGE_CASE(T)                                                     \
+    case T:                                                                  \
+        return wide ? (zero ? k_stage<T, true, true> : k_stage<T, true, false>) \
+                    : (zero ? k_stage<T, false, true> : k_stage<T, false, false>);
+    switch (t) {
+        SV_STAGE_CASE(9)
+        SV_STAGE_CASE(10)
+        SV_STAGE_CASE(11)
+        SV_STAGE_CASE(12)
+        SV_STAGE_CASE(13)
+    }
+#undef SV_STAGE_CASE
+    return nullptr;
+}
+
 hipError_t stage_prepare()
 {
     static std::atomic<bool> done{false};
     if (done) return hipSuccess;
-    void (*kerns[])(float2*, StageK) = {k_stage<9, false>,  k_stage<9, true>,  k_stage<10, false>,
-                                        k_stage<10, true>, k_stage<11, false>, k_stage<11, true>,
-                                        k_stage<12, false>, k_stage<12, true>, k_stage<13, false>,
-                                        k_stage<13, true>};
-    for (auto k : kerns) {
-        const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                                 kStageMaxLds);
-        if (e != hipSuccess) return e;
-    }
+    for (int t = 9; t <= kStageMaxT; ++t)
+        for (int v = 0; v < 4; ++v) {
+            void (*k)(float2*, StageK) = stage_kernel(t, v & 1, v & 2);
+            const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                     kStageMaxLds);
+            if (e != hipSuccess) return e;
+        }
     done = true;
     return hipSuccess;
 }
@@ -427,20 +445,8 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t dl_max = 0;
     for (int b = 0; b < 8; ++b) dl_max |= a.dep_lane[b];
     const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
-    void (*kern)(float2*, StageK) = nullptr;
-    switch (t * 2 + (wide ? 1 : 0)) {
-        case 18: kern = k_stage<9, false>; break;
-        case 19: kern = k_stage<9, true>; break;
-        case 20: kern = k_stage<10, false>; break;
-        case 21: kern = k_stage<10, true>; break;
-        case 22: kern = k_stage<11, false>; break;
-        case 23: kern = k_stage<11, true>; break;
-        case 24: kern = k_stage<12, false>; break;
-        case 25: kern = k_stage<12, true>; break;
-        case 26: kern = k_stage<13, false>; break;
-        case 27: kern = k_stage<13, true>; break;
-        default: return hipErrorInvalidValue;
-    }
+    void (*kern)(float2*, StageK) = stage_kernel(t, wide, a.newmask_t != 0);
+    if (!kern) return hipErrorInvalidValue;
     {
         const hipError_t e = stage_prepare();
         if (e != hipSuccess) return e;
