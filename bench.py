@@ -208,6 +208,31 @@ def host_info():
     return {"cpu_model": model, "logical_cpus": os.cpu_count(), "copy_GBps": round(gbps, 1)}
 
 
+def time_dense_start(h, circ, bits, args) -> float:
+    """ms per step of the headline steps with every pass over the whole
+    state (no sparse start after the reset), the plan ranked for that."""
+    import torch
+    from paper_1910_09534_amd import planner, sv
+    dense_ops = planner.plan(circ.gates, args.kmax)
+    for o in dense_ops:
+        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+
+    def dense_step():
+        sv.reset(h)
+        planner.enqueue(h, dense_ops, sv.SV_C64)
+        return sv.reduce_slices(h, bits)
+
+    sv.set_option(h, sv.SV_OPT_SPARSE_START, 0)
+    dense_step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dense_step()
+    torch.cuda.synchronize()
+    sv.set_option(h, sv.SV_OPT_SPARSE_START, 1)
+    return 1e3 * (time.perf_counter() - t0) / args.steps
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,6 +240,8 @@ def main(argv=None) -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--kmax", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-dense-start", action="store_true",
+                    help="skip the comparison run with dense passes (profiling: every launch is a step's)")
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--n", type=int, default=0)
@@ -286,24 +313,9 @@ def main(argv=None) -> int:
 
     # for comparison: every pass over the whole state (no sparse start
     # after the reset), with the plan ranked for that
-    dense_ops = planner.plan(circ.gates, args.kmax)
-    for o in dense_ops:
-        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
-
-    def dense_step():
-        sv.reset(h)
-        planner.enqueue(h, dense_ops, sv.SV_C64)
-        return sv.reduce_slices(h, bits)
-
-    sv.set_option(h, sv.SV_OPT_SPARSE_START, 0)
-    dense_step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dense_step()
-    torch.cuda.synchronize()
-    dense_ms = 1e3 * (time.perf_counter() - t0) / args.steps
-    sv.set_option(h, sv.SV_OPT_SPARSE_START, 1)
+    dense_ms = None
+    if not args.no_dense_start:
+        dense_ms = time_dense_start(h, circ, bits, args)
 
     def kind_roof(kind):
         p = prof[kind]
@@ -322,7 +334,7 @@ def main(argv=None) -> int:
                       "issued_tflops": round(issued, 2), "issued_frac": round(issued / FP32_PEAK_TFLOPS, 4)},
              "traffic": counter_traffic(kind)}
         if kind == "staged":
-            r.update({"kernel": "k_stage (staged pass: 2-5 dense 4/5-qubit blocks per HBM pass, matrix cores)",
+            r.update({"kernel": "k_stage (staged pass: 2-8 dense 4/5-qubit blocks per HBM pass, matrix cores)",
                       "bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4)})
         else:
@@ -363,7 +375,8 @@ def main(argv=None) -> int:
                    "k_hist": pst["k_hist"]},
         "hbm_frac_run": round(run_hbm_frac, 4),
         "amps_visited_frac": round(visited / (passes * float(1 << n)), 4),
-        "dense_start": {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3)},
+        "dense_start": None if dense_ms is None else
+        {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3)},
         "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,
