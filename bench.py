@@ -490,7 +490,7 @@ def bench_batch(args) -> int:
     staged = not args.batch_unstaged
     # one staged aggregation per circuit (plan_fast): within ~2 % of the full
     # candidate search by the cost model, at 1/35 of its planning time
-    plans = [planner.plan_fast(c.gates, 5, nloc=c.n) if staged and planner.stage_tmax(c.n) > 0
+    plans = [planner.plan_fast(c.gates, 5, nloc=c.n, sparse_start=True) if staged and planner.stage_tmax(c.n) > 0
              else planner.plan(c.gates, tuned["kmax"][c.n], staged=False) for c in circs]
     for p in plans:
         for o in p:

@@ -24,7 +24,8 @@ using namespace sv;
 namespace {
 
 struct Launch {
-    int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal, 3 staged pass (one state each)
+    int kind;          // 0 dense VALU, 1 dense MFMA, 2 diagonal, 3 staged pass (one state each),
+                       // 4 write |0...0>, 5 zero outside the support (one state each)
     int dtype, k;
     bool fold;
     bool staged;       // MFMA: address-ordered LDS staging
@@ -39,6 +40,10 @@ struct Launch {
     int ks[kStageRunMax];
     int spos[kStageRunMax][6];
     const void* smat[kStageRunMax];
+    // run from a reset: staged passes start from |0...0> or visit only the
+    // support's tiles; kind 5 clears outside `support`
+    bool from_e0 = false, garbage = false;
+    uint64_t support = ~0ull;
 };
 
 }  // namespace
@@ -50,8 +55,11 @@ struct sv_batch_s {
     void* d_arena = nullptr;
     void* d_items = nullptr;
     std::vector<Launch> launches;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t exec = nullptr;
+    // the same rounds for states all reset since their last use: no |0...0>
+    // writes ahead, staged passes visit only the tiles that can be non-zero
+    std::vector<Launch> launches_reset;
+    hipGraph_t graph = nullptr, graph_reset = nullptr;
+    hipGraphExec_t exec = nullptr, exec_reset = nullptr;
     hipEvent_t ev_done = nullptr;
     std::vector<hipEvent_t> ev_in;
     int64_t sweeps = 0;
@@ -76,6 +84,8 @@ void free_batch(sv_batch_s* b)
     if (b->stream) (void)hipStreamSynchronize(b->stream);
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
+    if (b->exec_reset) (void)hipGraphExecDestroy(b->exec_reset);
+    if (b->graph_reset) (void)hipGraphDestroy(b->graph_reset);
     if (b->d_arena) (void)hipFree(b->d_arena);
     if (b->d_items) (void)hipFree(b->d_items);
     if (b->ev_done) (void)hipEventDestroy(b->ev_done);
@@ -84,10 +94,10 @@ void free_batch(sv_batch_s* b)
     delete b;
 }
 
-hipError_t enqueue_all(sv_batch_s* b)
+hipError_t enqueue_all(sv_batch_s* b, const std::vector<Launch>& launches)
 {
     const Sweep* items = (const Sweep*)b->d_items;
-    for (const Launch& L : b->launches) {
+    for (const Launch& L : launches) {
         hipError_t e = hipSuccess;
         if (L.kind == 0)
             e = launch_dense_batch(b->stream, L.dtype, L.k, L.fold, items + L.first, L.nitems, L.blocks);
@@ -96,12 +106,16 @@ hipError_t enqueue_all(sv_batch_s* b)
                                         L.blocks);
         else if (L.kind == 2)
             e = launch_diag(b->stream, L.psi, L.dtype, L.nloc, 0, L.diag);
+        else if (L.kind == 4)
+            e = launch_init(b->stream, L.psi, L.dtype, (uint64_t)1 << L.nloc, true);
+        else if (L.kind == 5)
+            e = launch_zero_outside(b->stream, L.psi, L.dtype, L.nloc, L.support);
         else {
             const int* pp[kStageRunMax];
             for (int c = 0; c < L.cnt; ++c) pp[c] = L.spos[c];
             int t = 0;
-            e = launch_stage(b->stream, L.psi, L.nloc, L.cnt, L.ks, pp, L.smat, L.t_max, false, nullptr,
-                             nullptr, &t);
+            e = launch_stage(b->stream, L.psi, L.nloc, L.cnt, L.ks, pp, L.smat, L.t_max, L.from_e0, nullptr,
+                             nullptr, &t, L.support, L.garbage);
         }
         if (e != hipSuccess) return e;
     }
@@ -192,6 +206,30 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
         rounds = std::max(rounds, sweeps[i].size());
     }
 
+    // the reset variant: per state, the positions reached since the reset,
+    // whether |0...0> is still unwritten and whether memory outside the
+    // support still holds older values
+    std::vector<uint64_t> rs_support(count, 0);
+    std::vector<char> rs_e0(count, 1), rs_garbage(count, 1);
+    auto rs_full = [&](int i) { return ((uint64_t)1 << handles[i]->n) - 1; };
+    auto rs_materialize = [&](int i) {
+        sv_state* h = handles[i];
+        Launch M{};
+        M.dtype = h->dtype;
+        M.psi = h->dev;
+        M.nloc = h->n;
+        if (rs_e0[i]) {
+            M.kind = 4;
+            b->launches_reset.push_back(M);
+        } else if (rs_garbage[i] && (rs_support[i] & rs_full(i)) != rs_full(i)) {
+            M.kind = 5;
+            M.support = rs_support[i];
+            b->launches_reset.push_back(M);
+        }
+        rs_e0[i] = 0;
+        rs_garbage[i] = 0;
+    };
+
     std::vector<Sweep> items;
     for (size_t r = 0; r < rounds; ++r) {
         // (form, k, fold) -> item indices of this round, in state order
@@ -217,11 +255,23 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
                     L.smat[c] = ab + w.op[c].off;
                 }
                 b->launches.push_back(L);
+                Launch R = L;
+                R.from_e0 = rs_e0[i] != 0;
+                R.support = rs_support[i];
+                R.garbage = rs_garbage[i] != 0;
+                b->launches_reset.push_back(R);
+                for (int c = 0; c < w.cnt; ++c)
+                    for (int u = 0; u < w.ks[c]; ++u) rs_support[i] |= (uint64_t)1 << w.op[c].pos[u];
+                rs_e0[i] = 0;
+                if ((rs_support[i] & rs_full(i)) == rs_full(i)) rs_garbage[i] = 0;
                 h->counters[0] += 1;
                 h->counters[3] += (int64_t)1 << h->n;
                 h->counters[7] += w.cnt;
                 continue;
             }
+            // a plain sweep needs every amplitude in memory
+            rs_materialize(i);
+            rs_support[i] = ~0ull;
             if (w.kind == 2) {
                 Launch L{};
                 L.kind = 2;
@@ -232,6 +282,7 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
                 for (int t = 0; t < w.op->k; ++t) L.diag.pos[t] = w.op->pos[t];
                 L.diag.table = ab + w.op->off;
                 b->launches.push_back(L);
+                b->launches_reset.push_back(L);
                 h->counters[1] += 1;
                 h->counters[3] += (int64_t)1 << h->n;
                 continue;
@@ -268,8 +319,11 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             L.blocks = blk;
             if (blk > 0x7fffffffull) { free_batch(b); return berr(nullptr, SV_EINVAL, "batch round too large"); }
             b->launches.push_back(L);
+            b->launches_reset.push_back(L);
         }
     }
+    // the state is read after the batch: everything in memory
+    for (int i = 0; i < count; ++i) rs_materialize(i);
     if (!items.empty()) {
         if (hipMalloc(&b->d_items, items.size() * sizeof(Sweep)) != hipSuccess) {
             (void)hipGetLastError();
@@ -297,13 +351,17 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             free_batch(b);
             return berr(nullptr, SV_EDEVICE, "staged kernel set-up failed");
         }
-        e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess) {
-            hipError_t e2 = enqueue_all(b);
-            e = hipStreamEndCapture(b->stream, &b->graph);
-            if (e2 != hipSuccess) e = e2;
+        e = hipSuccess;
+        for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+            hipGraph_t& g = v ? b->graph_reset : b->graph;
+            e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_all(b, v ? b->launches_reset : b->launches);
+                e = hipStreamEndCapture(b->stream, &g);
+                if (e2 != hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(v ? &b->exec_reset : &b->exec, g, nullptr, nullptr, 0);
         }
-        if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
         if (e != hipSuccess) {
             free_batch(b);
             return berr(nullptr, SV_EDEVICE, std::string("graph capture failed: ") + hipGetErrorString(e));
@@ -316,22 +374,29 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
 int sv_batch_launch(sv_batch b)
 {
     if (!b) return berr(nullptr, SV_EINVAL, "NULL batch");
+    // every state reset since its last use (sparse start on): the reset
+    // variant, which writes |0...0> only where a plain sweep needs it
+    bool reset = true;
+    for (sv_state* h : b->states) reset = reset && h->e0_pending && h->sparse_start;
     // order after everything already queued on the states' own streams
     for (size_t i = 0; i < b->states.size(); ++i) {
         sv_state* h = b->states[i];
         if (h->poisoned) return SV_ESTATE;
         if (!h->ops.empty()) return berr(b, SV_EINVAL, "state has operations queued after the batch was prepared");
-        // a deferred reset is written on the state's stream, ahead of the batch
-        if (h->e0_pending || h->garbage) {
+        // otherwise a deferred reset is written on the state's stream, ahead of the batch
+        if (!reset && (h->e0_pending || h->garbage)) {
             const int rc = materialize_e0(h);
             if (rc) return rc;
         }
+        h->e0_pending = false;
+        h->garbage = false;
         h->support = ~0ull;
         if (hipEventRecord(b->ev_in[i], h->stream) != hipSuccess ||
             hipStreamWaitEvent(b->stream, b->ev_in[i], 0) != hipSuccess)
             return berr(b, SV_EDEVICE, "stream ordering failed");
     }
-    hipError_t e = b->exec ? hipGraphLaunch(b->exec, b->stream) : enqueue_all(b);
+    hipGraphExec_t ex = reset ? b->exec_reset : b->exec;
+    hipError_t e = ex ? hipGraphLaunch(ex, b->stream) : enqueue_all(b, reset ? b->launches_reset : b->launches);
     if (e != hipSuccess) {
         for (sv_state* h : b->states) { h->poisoned = true; h->err = "batch launch failed"; }
         return berr(b, SV_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));

@@ -546,15 +546,28 @@ def _nloc_of(gates) -> int:
     return 1 + max((q for g in gates for q in g.qubits), default=0)
 
 
-def plan_fast(gates, kmax: int, pos_of=None, nloc: Optional[int] = None) -> List[Op]:
+def plan_fast(gates, kmax: int, pos_of=None, nloc: Optional[int] = None,
+              sparse_start: bool = False) -> List[Op]:
     """One staged aggregation (grow-based, window 4, last qubit only when it
     adds 40 % more gate weight), widened and ordered for staged passes: for
-    request paths where planning time counts (tens of ms for ~600 gates)."""
-    tmax = stage_tmax(_nloc_of(gates) if nloc is None else nloc)
-    ops = fuse_grow(gates, kmax, window=4, last_gain=0.4 if kmax >= 5 and tmax else 0.0)
+    request paths where planning time counts (tens of ms for ~600 gates).
+    sparse_start: the same aggregation also of the gates in the Fiedler
+    orders of `support_order`, the cheapest by `sparse_cost` kept."""
+    n_loc = _nloc_of(gates) if nloc is None else nloc
+    tmax = stage_tmax(n_loc)
+    gain = 0.4 if kmax >= 5 and tmax else 0.0
+    ops = fuse_grow(gates, kmax, window=4, last_gain=gain)
     if not tmax:
         return ops
-    return order_for_staging(widen_small_blocks(ops, pos_of), pos_of, tmax)
+    ops = order_for_staging(widen_small_blocks(ops, pos_of), pos_of, tmax)
+    if not sparse_start:
+        return ops
+    cands = [ops]
+    n_q = 1 + max((q for g in gates for q in g.qubits), default=0)
+    for act in activation_orders(gates, n_q)[:2]:
+        c = fuse_grow(support_order(gates, act), kmax, window=4, last_gain=gain)
+        cands.append(order_for_staging(widen_small_blocks(c, pos_of), pos_of, tmax))
+    return min(cands, key=lambda c: sparse_cost(c, n_loc, pos_of, tmax))
 
 
 def _staged_candidates(gates, kmax: int, pos_of, tmax: int) -> List[List[Op]]:

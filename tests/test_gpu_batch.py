@@ -53,7 +53,7 @@ def test_staged_batch_equals_alone_and_oracle(graph):
     _gpu()
     circs, bits = _batch(count=6, nmin=18, nmax=21, seed=13)
     res = runner.run_batch(circs, bits, "c64", kmax=5, graph=graph, repeats=2, staged=True)
-    plans = [planner.plan_fast(c.gates, 5, nloc=c.n) for c in circs]
+    plans = [planner.plan_fast(c.gates, 5, nloc=c.n, sparse_start=True) for c in circs]
     staged_blocks = 0
     for c, b, amps, p in zip(circs, bits, res["amps"], plans):
         st = sv.State(c.n, 0, "c64")
@@ -68,6 +68,66 @@ def test_staged_batch_equals_alone_and_oracle(graph):
         ref = orc.gather(orc.simulate(c), b)
         assert orc.rel_l2(amps, ref) <= 1e-4
     assert staged_blocks > 0
+
+
+@pytest.mark.parametrize("graph", [True, False])
+def test_batch_reset_variant(graph):
+    """States all reset before the launch run the batch's reset variant:
+    staged passes from |0...0> that visit only the tiles inside each state's
+    support, |0...0> written only ahead of a plain sweep, and the part of the
+    state no pass reached cleared at the end.  Covers a plain sweep early in
+    a plan, a state with no ops, a state whose support stays partial, and a
+    planned circuit; the buffers hold the previous run's values at every
+    reset.  A launch without a reset runs the ordinary variant on the
+    current states (the ops applied twice)."""
+    _gpu()
+    rng = np.random.default_rng(17)
+    U = lambda k: W.random_unitary(1 << k, rng)
+    c = W.sycamore_circuit(20, 10, seed=71)
+    specs = [
+        (18, 9, [([4, 5, 6, 7, 8], U(5)), ([5, 6, 7, 8, 9], U(5)), ([15, 16, 17], U(3)),
+                 ([10, 11, 12, 13], U(4)), ([12, 13, 14, 15], U(4))]),
+        (19, 10, []),
+        (18, 9, [([14, 15, 16], U(3)), ([4, 5, 6, 7], U(4)), ([6, 7, 8, 9], U(4))]),
+        (22, 13, [([0, 1, 2, 3, 4], U(5)), ([2, 3, 4, 5, 6], U(5)), ([6, 7, 8, 9], U(4))]),
+        (20, 11, [(list(o.qubits), o.matrix) for o in
+                  planner.plan_fast(c.gates, 5, nloc=20, sparse_start=True)]),
+    ]
+    states, b = [], None
+    try:
+        for n, tmax, ops in specs:
+            st = sv.State(n, 0, "c64")
+            sv.set_option(st.h, sv.SV_OPT_STAGE, tmax)
+            for qs, m in ops:
+                st.fused(qs, np.asarray(m).astype(np.complex64))
+            states.append(st)
+        b = sv.batch_prepare([st.h for st in states], graph=graph)
+        refs = []
+        for n, _, ops in specs:
+            psi = orc.zero_state(n)
+            for qs, m in ops:
+                orc.apply_dense(psi, qs, m)
+            refs.append(psi)
+        for rep in range(3):
+            for st in states:
+                sv.reset(st.h)
+            sv.batch_launch(b)
+            for st, (n, _, _), ref in zip(states, specs, refs):
+                got = st.gather(np.arange(1 << n, dtype=np.uint64))
+                assert orc.rel_l2(got, ref) <= 1e-4, (n, rep)
+        # no reset: the batch applies its ops to the states as they are
+        sv.batch_launch(b)
+        for st, (n, _, ops), ref in zip(states, specs, refs):
+            twice = ref.copy()
+            for qs, m in ops:
+                orc.apply_dense(twice, qs, m)
+            got = st.gather(np.arange(1 << n, dtype=np.uint64))
+            assert orc.rel_l2(got, twice) <= 2e-4, n
+    finally:
+        if b is not None:
+            sv.batch_destroy(b)
+        for st in states:
+            st.close()
 
 
 def test_batch_c128_vs_c64_vs_oracle():
