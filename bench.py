@@ -529,7 +529,8 @@ def bench_batch(args) -> int:
                    "circuits": count, "gates": sum(len(c.gates) for c in circs),
                    "sweeps": sum(res["sweeps"]), "launches_per_batch": res["info"]["launches"]},
         "amp_updates_per_s": gate_amps / t,
-        "hbm_GBps_sweeps": 16.0 * swept / t / 1e9,
+        "amps_visited_per_batch": swept,
+        "hbm_GBps_visited": 16.0 * swept / t / 1e9,
         "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"], "staged": staged,
         "t_tune_s": round(t_tune, 2), "t_plan_s": round(t_plan, 2),
         "c128_batch_s": round(t128, 3),

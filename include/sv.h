@@ -236,8 +236,12 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
  * divided among the states in proportion to their size.  With
  * SV_BATCH_GRAPH all rounds are captured into one HIP graph, so a batch is
  * one graph launch and can be replayed (e.g. after sv_reset of every state).
- * A state's own operation order is kept; results are bitwise identical to
- * running the same operations on the state alone.
+ * A second variant (and graph) serves launches where every state was reset
+ * since its last use (SV_OPT_SPARSE_START on): staged passes start from
+ * |0...0> and visit only the tiles that can be non-zero, |0...0> is written
+ * only ahead of a plain sweep, and what no pass reached is cleared at the
+ * end.  A state's own operation order is kept; results are bitwise
+ * identical to running the same operations on the state alone.
  *
  * sv_batch_prepare -- handles: `count` distinct resident states of one dtype
  *   (HBM, not tiered) with no queued permutes; their queues are emptied.
@@ -245,9 +249,12 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
  *   the batch.  Errors: SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESTATE.
  * sv_batch_launch  -- enqueue the batch after the work already queued on the
  *   states' streams; later work on those streams waits for it.  Asynchronous.
+ *   Runs the reset variant when every state is reset and not yet used.
  * sv_batch_sync    -- wait for the last launch.
  * sv_batch_info    -- [0] launches per run, [1] sweeps per run, [2]
- *   amplitudes swept per run, [3] 1 if captured in a graph.
+ *   amplitudes the sweeps visit per run, [3] 1 if captured in a graph;
+ *   [0] and [2] for the variant launched last (before any launch: the
+ *   ordinary one).
  * sv_batch_destroy -- free the batch (not the states).
  * sv_batch_error   -- text of the last batch failure (b may be NULL).
  */

@@ -63,7 +63,8 @@ struct sv_batch_s {
     hipEvent_t ev_done = nullptr;
     std::vector<hipEvent_t> ev_in;
     int64_t sweeps = 0;
-    double amps_swept = 0;
+    double amps_swept = 0, amps_swept_reset = 0;
+    bool last_reset = false;                 // variant of the last launch
     std::string err;
 };
 
@@ -260,6 +261,11 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
                 R.support = rs_support[i];
                 R.garbage = rs_garbage[i] != 0;
                 b->launches_reset.push_back(R);
+                {
+                    const int* pp[kStageRunMax];
+                    for (int c = 0; c < w.cnt; ++c) pp[c] = L.spos[c];
+                    b->amps_swept_reset += (double)stage_visits(h->n, w.cnt, w.ks, pp, h->stage_t, rs_support[i]);
+                }
                 for (int c = 0; c < w.cnt; ++c)
                     for (int u = 0; u < w.ks[c]; ++u) rs_support[i] |= (uint64_t)1 << w.op[c].pos[u];
                 rs_e0[i] = 0;
@@ -272,6 +278,7 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             // a plain sweep needs every amplitude in memory
             rs_materialize(i);
             rs_support[i] = ~0ull;
+            b->amps_swept_reset += (double)((uint64_t)1 << h->n);
             if (w.kind == 2) {
                 Launch L{};
                 L.kind = 2;
@@ -396,6 +403,7 @@ int sv_batch_launch(sv_batch b)
             return berr(b, SV_EDEVICE, "stream ordering failed");
     }
     hipGraphExec_t ex = reset ? b->exec_reset : b->exec;
+    b->last_reset = reset;
     hipError_t e = ex ? hipGraphLaunch(ex, b->stream) : enqueue_all(b, reset ? b->launches_reset : b->launches);
     if (e != hipSuccess) {
         for (sv_state* h : b->states) { h->poisoned = true; h->err = "batch launch failed"; }
@@ -422,9 +430,9 @@ int sv_batch_sync(sv_batch b)
 int sv_batch_info(sv_batch b, int64_t info[4])
 {
     if (!b || !info) return SV_EINVAL;
-    info[0] = (int64_t)b->launches.size();
+    info[0] = (int64_t)(b->last_reset ? b->launches_reset.size() : b->launches.size());
     info[1] = b->sweeps;
-    info[2] = (int64_t)b->amps_swept;
+    info[2] = (int64_t)(b->last_reset ? b->amps_swept_reset : b->amps_swept);
     info[3] = b->exec ? 1 : 0;
     return SV_OK;
 }

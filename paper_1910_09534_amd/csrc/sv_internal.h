@@ -121,6 +121,10 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
                         int* t_out, uint64_t support = ~0ull, bool garbage = false,
                         uint64_t* tile_mask_out = nullptr, uint64_t* amps_out = nullptr);
 
+// Amplitudes a staged pass with these blocks visits (launch_stage's tile
+// choice for this support); 0 when the run does not fit a tile.
+uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support);
+
 // Zeroes every amplitude whose index has a bit outside `support`.
 hipError_t launch_zero_outside(hipStream_t st, void* psi, int dtype, int nloc, uint64_t support);
 

@@ -363,28 +363,26 @@ hipError_t stage_prepare()
     return hipSuccess;
 }
 
-hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
-                        const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
-                        int* t_out, uint64_t support, bool garbage, uint64_t* tile_mask_out,
-                        uint64_t* amps_out)
+// Tile positions of a staged pass, ascending, into P (returns t, or -1 when
+// the run does not fit): 0..3 plus every target, widened with the lowest
+// free positions up to t_max (or the LDS limit): a block has 2^(t-k-4)
+// 16-group units per tile for the workgroup's four waves (8 for k = 5 at
+// t = 12), and the tile's contiguous runs are longer.  Only positions
+// inside the support widen it: one outside would double the amplitudes
+// visited (beyond the 9 the kernel needs).
+static int stage_positions(int nloc, int nops, const int* ks, const int* const* pos, int t_max,
+                           uint64_t support, int* P)
 {
     if (t_max > kStageMaxT) t_max = kStageMaxT;
-    if (nops < 1 || nops > kStageMaxOps) return hipErrorInvalidValue;
-    // tile positions: 0..3 plus every target, ascending
+    if (nops < 1 || nops > kStageMaxOps) return -1;
     bool in[64] = {};
     for (int p = 0; p < 4; ++p) in[p] = true;
     for (int o = 0; o < nops; ++o) {
-        if (ks[o] < 4 || ks[o] > 5) return hipErrorInvalidValue;
+        if (ks[o] < 4 || ks[o] > 5) return -1;
         for (int j = 0; j < ks[o]; ++j) in[pos[o][j]] = true;
     }
     int cnt = 0;
     for (int p = 0; p < 64; ++p) cnt += in[p];
-    // widen the tile with the lowest free positions up to t_max (or the LDS
-    // limit): a block has 2^(t-k-4) 16-group units per tile for the
-    // workgroup's four waves (8 for k = 5 at t = 12), and the tile's
-    // contiguous runs are longer.  Only positions inside the support: one
-    // outside it would double the amplitudes visited (beyond the 9 the
-    // kernel needs).
     for (int round = 0; round < 2; ++round)
         for (int p = 0; p < nloc && cnt < (round ? 9 : t_max); ++p) {
             if (in[p] || (round == 0 && !((support >> p) & 1))) continue;
@@ -392,10 +390,32 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
             in[p] = true;
             ++cnt;
         }
-    int P[64], t = 0;
+    int t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;
-    if (t > t_max || t < 9 || nloc < t) return hipErrorInvalidValue;
+    if (t > t_max || t < 9 || nloc < t) return -1;
+    return t;
+}
+
+uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support)
+{
+    int P[64];
+    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P);
+    if (t < 0) return 0;
+    uint64_t pmask = 0;
+    for (int b = 0; b < t; ++b) pmask |= 1ull << P[b];
+    const uint64_t full = nloc >= 64 ? ~0ull : ((1ull << nloc) - 1);
+    return (1ull << t) << __builtin_popcountll(full & ~pmask & support);
+}
+
+hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
+                        const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
+                        int* t_out, uint64_t support, bool garbage, uint64_t* tile_mask_out,
+                        uint64_t* amps_out)
+{
+    int P[64];
+    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P);
+    if (t < 0) return hipErrorInvalidValue;
     StageK a{};
     a.t = t;
     a.nops = nops;

@@ -70,8 +70,11 @@ def run_one(torch, stream, req: Request, kmax: int, mfma_min_k: int = 4):
     ops = plan_request(req.circuit, kmax)
     with torch.cuda.stream(stream):
         buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
-    h = sv.create_state_ext(n, 0, "c64", stream.cuda_stream, buf.data_ptr(), buf.numel() * 8)
+    # the buffer's old contents are kept and the reset deferred: the first
+    # pass builds |0...0> itself, so no fill kernel writes the whole buffer
+    h = sv.create_state_ext(n, 0, "c64", stream.cuda_stream, buf.data_ptr(), buf.numel() * 8, keep=True)
     try:
+        sv.reset(h)
         sv.set_option(h, sv.SV_OPT_MFMA, mfma_min_k)
         sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
         planner.enqueue(h, ops, sv.SV_C64)

@@ -115,8 +115,12 @@ def test_batch_reset_variant(graph):
             for st, (n, _, _), ref in zip(states, specs, refs):
                 got = st.gather(np.arange(1 << n, dtype=np.uint64))
                 assert orc.rel_l2(got, ref) <= 1e-4, (n, rep)
+        info_reset = sv.batch_info(b)
         # no reset: the batch applies its ops to the states as they are
         sv.batch_launch(b)
+        info_plain = sv.batch_info(b)
+        assert info_reset["amps_swept"] < info_plain["amps_swept"]
+        assert info_reset["sweeps"] == info_plain["sweeps"]
         for st, (n, _, ops), ref in zip(states, specs, refs):
             twice = ref.copy()
             for qs, m in ops:
