@@ -1,0 +1,86 @@
+"""Pins of the contraction-deferral oracle (App. A: the EI and E2Q
+synthesized gates and the contraction over entanglement indices; Sec. 2:
+contraction deferral).  Each check compares the oracle with something
+other than itself: the gate applied to the product of the two tensors
+(closed form), the plain simulation of the whole circuit, brute-force sums
+on tiny tensors, and a planted label swap that must be caught."""
+import numpy as np
+import pytest
+
+from oracle import deferral as D
+from oracle import oracle as orc
+from paper_1910_09534_amd import workload as W
+
+
+def _rand(shape, rng):
+    return rng.standard_normal(shape) + 1j * rng.standard_normal(shape)
+
+
+@pytest.mark.parametrize("a,b", [(0, 3), (2, 5), (1, 4)])
+@pytest.mark.parametrize("a_first", [True, False])
+def test_one_bridging_gate_is_the_gate_on_the_product(a, b, a_first):
+    """sum_{a', a} EI(phi) E2Q(chi) = 2Q applied to phi (x) chi (the first
+    equation of App. A), for a general (non-unitary, asymmetric) 4x4 gate
+    and either order of the gate's qubits."""
+    rng = np.random.default_rng(10 * a + b + a_first)
+    phi = _rand(8, rng)                       # qubits 0, 1, 2
+    chi = _rand(8, rng)                       # qubits 3, 4, 5
+    g = _rand((4, 4), rng)
+    qs = [a, b] if a_first else [b, a]
+    t1, l1 = D.from_state(phi, [0, 1, 2])
+    t2, l2 = D.from_state(chi, [3, 4, 5])
+    t1, l1 = D.ei(t1, l1, a, 0, 1)
+    t2, l2 = D.e2q(t2, l2, qs, g, a, b, 0, 1)
+    t, lab = D.contract(t1, l1, t2, l2)
+    got = D.to_state(t, lab, list(range(6)))
+    ref = orc.apply_dense(np.kron(chi, phi), qs, g)
+    assert np.abs(got - ref).max() < 1e-12
+
+
+def test_planted_label_swap_is_caught():
+    """Control: exchanging the two entanglement indices in E2Q (a plausible
+    slip) changes the result, so the pin above can fail."""
+    rng = np.random.default_rng(3)
+    phi, chi, g = _rand(8, rng), _rand(8, rng), _rand((4, 4), rng)
+    t1, l1 = D.from_state(phi, [0, 1, 2])
+    t2, l2 = D.from_state(chi, [3, 4, 5])
+    t1, l1 = D.ei(t1, l1, 1, 0, 1)
+    t2, l2 = D.e2q(t2, l2, [1, 4], g, 1, 4, 1, 0)          # e_a and e_ap exchanged
+    t, lab = D.contract(t1, l1, t2, l2)
+    got = D.to_state(t, lab, list(range(6)))
+    ref = orc.apply_dense(np.kron(chi, phi), [1, 4], g)
+    assert np.abs(got - ref).max() > 1e-3
+
+
+@pytest.mark.parametrize("n,depth,cols", [(8, 6, 2), (12, 5, 2), (12, 4, 3)])
+def test_deferred_circuit_equals_simulation(n, depth, cols):
+    """A whole ABCDCDAB circuit as two tensors (the first `cols` grid
+    columns, the rest), every bridging gate deferred: the contraction equals
+    the plain simulation of the circuit."""
+    c = W.sycamore_circuit(n, depth, seed=200 + n + depth)
+    rows, ncol = W.grid_shape(n)
+    part1 = [q for q in range(n) if q % ncol < cols]
+    bridging = sum(1 for g in c.gates if len(g.qubits) == 2
+                   and ((g.qubits[0] in part1) != (g.qubits[1] in part1)))
+    assert bridging >= 2
+    got = D.deferred_simulate(c, part1)
+    assert np.abs(got - orc.simulate(c)).max() < 1e-12
+
+
+@pytest.mark.parametrize("n1,n2,e", [(1, 1, 1), (2, 1, 2), (1, 3, 0), (3, 2, 3)])
+def test_contract_matrix_brute_force(n1, n2, e):
+    """The GPU call's layout form, checked by explicit sums and against the
+    label contraction."""
+    rng = np.random.default_rng(n1 * 16 + n2 * 4 + e)
+    t1 = _rand((1 << e) << n1, rng)
+    t2 = _rand((1 << e) << n2, rng)
+    got = D.contract_matrix(t1, t2, n1, n2, e)
+    for x2 in range(1 << n2):
+        for x1 in range(1 << n1):
+            s = sum(t1[k * (1 << n1) + x1] * t2[k * (1 << n2) + x2] for k in range(1 << e))
+            assert abs(got[x2 * (1 << n1) + x1] - s) < 1e-12
+    # the same by labels: bits 0..n1-1 of t1 are qubits 0..n1-1, bits above are e
+    l1 = [("q", j) if j < n1 else ("e", j - n1) for j in reversed(range(n1 + e))]
+    l2 = [("q", n1 + j) if j < n2 else ("e", j - n2) for j in reversed(range(n2 + e))]
+    t, lab = D.contract(t1.reshape((2,) * (n1 + e)), l1, t2.reshape((2,) * (n2 + e)), l2)
+    assert np.abs(D.to_state(t, lab, list(range(n1 + n2))) - got).max() < 1e-12
