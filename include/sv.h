@@ -167,7 +167,7 @@ int sync_state(sv_handle h);
 int sv_reset(sv_handle h);
 
 /* last_error -- text of the most recent failure on h (or of the last failed
-   create when h is NULL).  Valid until the next call on the same handle. */
+   create or sv_contract when h is NULL).  Valid until the next call on the same handle. */
 const char* last_error(sv_handle h);
 
 /* ---- introspection and tuning (not part of the paper's operation set) ---- */
@@ -266,6 +266,25 @@ int sv_batch_sync(sv_batch b);
 int sv_batch_info(sv_batch b, int64_t info[4]);
 int sv_batch_destroy(sv_batch b);
 const char* sv_batch_error(sv_batch b);
+
+/* ---- contraction deferral ---------------------------------------------------
+ * sv_contract -- the contraction that eliminates entanglement indices (App.
+ *   A, the equation summing phi' chi' over the indices a', a introduced by
+ *   the EI and E2Q synthesized gates; Sec. 2, contraction deferral: sum over
+ *   the shared indices, outer product over the others), for two tensors
+ *   that share e entanglement indices:
+ *       out[x2 * 2^n1 + x1] = sum_{c < 2^e} t1[c * 2^n1 + x1] * t2[c * 2^n2 + x2].
+ *   t1: device buffer of 2^(n1+e) amplitudes whose index bits n1.. are the
+ *   entanglement indices (e.g. a state permuted so that they sit at the top
+ *   positions); t2 likewise with n2 open bits and the same entanglement
+ *   indices in the same order; out: device buffer of 2^(n1+n2) amplitudes
+ *   (caller-owned, overwritten, not overlapping the inputs).  dtype SV_C64
+ *   (FP32 sums, on the matrix cores when 2^n2 >= 128, 2^n1 >= 64 and
+ *   2^e >= 16) or SV_C128 (FP64 sums).  All buffers 16-byte aligned.
+ *   hip_stream: stream to run on (NULL: the null stream); asynchronous.
+ *   Errors: SV_EINVAL (NULL or misaligned buffer, n1 + n2, n1 + e or n2 + e
+ *   above 40, overlap), SV_EDEVICE; the text is last_error(NULL). */
+int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e, int dtype, void* hip_stream);
 
 #ifdef __cplusplus
 }

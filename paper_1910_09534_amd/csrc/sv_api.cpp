@@ -1325,6 +1325,26 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
     return SV_OK;
 }
 
+int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e, int dtype, void* hip_stream)
+{
+    if (!t1 || !t2 || !out) return set_err(nullptr, SV_EINVAL, "sv_contract: NULL buffer");
+    if (dtype != SV_C64 && dtype != SV_C128) return set_err(nullptr, SV_EINVAL, "sv_contract: bad dtype");
+    if (n1 < 0 || n2 < 0 || e < 0 || n1 + n2 > 40 || n1 + e > 40 || n2 + e > 40)
+        return set_err(nullptr, SV_EINVAL, "sv_contract: sizes out of range");
+    if (((uintptr_t)t1 | (uintptr_t)t2 | (uintptr_t)out) & 15)
+        return set_err(nullptr, SV_EINVAL, "sv_contract: buffers must be 16-byte aligned");
+    const size_t amp = dtype == SV_C64 ? 8 : 16;
+    const uintptr_t o0 = (uintptr_t)out, o1 = o0 + (amp << (n1 + n2));
+    for (const void* p : {t1, t2}) {
+        const int np = p == t1 ? n1 : n2;
+        const uintptr_t p0 = (uintptr_t)p, p1 = p0 + (amp << (np + e));
+        if (p0 < o1 && o0 < p1) return set_err(nullptr, SV_EINVAL, "sv_contract: output overlaps an input");
+    }
+    const hipError_t err = launch_contract((hipStream_t)hip_stream, t1, t2, out, n1, n2, e, dtype);
+    if (err != hipSuccess) return fail_dev(nullptr, "sv_contract launch", err);
+    return SV_OK;
+}
+
 int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2], double issued[2],
                      double bytes[2])
 {

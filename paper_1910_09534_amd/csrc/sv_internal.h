@@ -125,6 +125,12 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
 // choice for this support); 0 when the run does not fit a tile.
 uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support);
 
+// Contraction over entanglement indices: out[x2 2^n1 + x1] =
+// sum_e t1[e 2^n1 + x1] t2[e 2^n2 + x2] (complex64 or complex128).
+bool contract_uses_mfma(int dtype, int n1, int n2, int e);
+hipError_t launch_contract(hipStream_t st, const void* t1, const void* t2, void* out, int n1, int n2, int e,
+                           int dtype);
+
 // Zeroes every amplitude whose index has a bit outside `support`.
 hipError_t launch_zero_outside(hipStream_t st, void* psi, int dtype, int nloc, uint64_t support);
 

@@ -143,3 +143,69 @@ def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: boo
             sv.batch_destroy(b)
         for st in states:
             st.close()
+
+
+def simulate_deferred(circuit, bits: np.ndarray, part1: Sequence[int], ncycles: int, kmax: int = 5,
+                      timing: bool = False) -> Dict[str, object]:
+    """Contraction deferral (Sec. 2; App. A): the first `ncycles` cycles run
+    as two tensors (part1 and the other qubits) with EI / E2Q for every
+    bridging gate, each a complex64 state of its part plus the entanglement
+    indices; both are permuted so the entanglement indices sit at the top
+    in the same order, `sv_contract` forms the joint state, and the rest of
+    the circuit runs on it.  Returns amplitudes of `bits` (over the circuit
+    qubits), the norm and the cross-entropy sums, and the stage times."""
+    import torch
+    from . import deferral
+    t0 = time.perf_counter()
+    sp = deferral.split(circuit, part1, ncycles)
+    nt1, nt2 = sp.n1 + sp.e, sp.n2 + sp.e
+    plans = []
+    for ops, nq in ((sp.ops1, nt1), (sp.ops2, nt2)):
+        p = planner.plan(ops, kmax, nloc=nq, sparse_start=True) if ops else []
+        for o in p:
+            o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+        plans.append(p)
+    rest = planner.plan(sp.rest, kmax, nloc=circuit.n) if sp.rest else []
+    for o in rest:
+        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+    jbits = sp.joint_bits(bits)
+    t_plan = time.perf_counter() - t0
+    stream = torch.cuda.current_stream()
+    out = torch.empty(1 << circuit.n, dtype=torch.complex64, device="cuda")
+    s1 = sv.State(nt1, 0, "c64")
+    s2 = sv.State(nt2, 0, "c64")
+    h3 = None
+    try:
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        for st, p, nq, order in ((s1, plans[0], nt1, sp.order1), (s2, plans[1], nt2, sp.order2)):
+            sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(nq))
+            planner.enqueue(st.h, p, st.dtype)
+            sv.permute_qubits(st.h, order)
+        p1, _ = sv.device_buffer(s1.h)
+        p2, _ = sv.device_buffer(s2.h)
+        sv.sync_state(s1.h)
+        sv.sync_state(s2.h)
+        t2 = time.perf_counter()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record(stream)
+        sv.contract(p1, p2, out.data_ptr(), sp.n1, sp.n2, sp.e, "c64", stream.cuda_stream)
+        ev[1].record(stream)
+        h3 = sv.create_state_ext(circuit.n, 0, "c64", stream.cuda_stream, out.data_ptr(),
+                                 out.numel() * 8, keep=True)
+        if timing:
+            sv.set_option(h3, sv.SV_OPT_TIMING, 1)
+        sv.set_option(h3, sv.SV_OPT_STAGE, planner.stage_tmax(circuit.n))
+        planner.enqueue(h3, rest, sv.SV_C64)
+        amps, stats = sv.reduce_slices(h3, jbits)
+        t3 = time.perf_counter()
+        return {"amps": amps, "norm": stats[0], "xeb_sum": stats[1], "xeb_log_sum": stats[2],
+                "split": sp, "t_plan": t_plan, "t_tensors": t2 - t1,
+                "contract_ms": ev[0].elapsed_time(ev[1]), "t_run": t3 - t1,
+                "plans": [planner.stats(p) for p in plans] + [planner.stats(rest)]}
+    finally:
+        if h3 is not None:
+            sv.destroy_state(h3)
+        s1.close()
+        s2.close()
+        del out

@@ -28,7 +28,7 @@ EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "
            "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
-           "sv_batch_destroy", "sv_batch_error")
+           "sv_batch_destroy", "sv_batch_error", "sv_contract")
 SV_BATCH_GRAPH = 1
 
 
@@ -68,6 +68,7 @@ def load():
     L.sv_batch_info.argtypes = [P, P]
     L.sv_batch_destroy.argtypes = [P]
     L.sv_batch_error.argtypes = [P]
+    L.sv_contract.argtypes = [P, P, P, I, I, I, I, P]
     for name in EXPORTS:
         text = name in ("last_error", "sv_batch_error")
         getattr(L, name).restype = ctypes.c_char_p if text else ctypes.c_int
@@ -224,6 +225,12 @@ def sweep_profile(h) -> dict:
     return {kind: {"ms": float(ms[i]), "count": int(cnt[i]), "flops": float(fl[i]), "issued": float(iss[i]),
                    "bytes": float(by[i])}
             for i, kind in enumerate(("sweep", "staged"))}
+
+
+def contract(t1_ptr: int, t2_ptr: int, out_ptr: int, n1: int, n2: int, e: int, dtype, stream=None) -> None:
+    """out[x2 2^n1 + x1] = sum_c t1[c 2^n1 + x1] t2[c 2^n2 + x2] on device
+    buffers (see sv_contract in include/sv.h).  Asynchronous on `stream`."""
+    _check(lib().sv_contract(t1_ptr, t2_ptr, out_ptr, n1, n2, e, _dtype_code(dtype), stream))
 
 
 def _bcheck(rc: int, b=None):

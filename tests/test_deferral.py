@@ -84,3 +84,29 @@ def test_contract_matrix_brute_force(n1, n2, e):
     l2 = [("q", n1 + j) if j < n2 else ("e", j - n2) for j in reversed(range(n2 + e))]
     t, lab = D.contract(t1.reshape((2,) * (n1 + e)), l1, t2.reshape((2,) * (n2 + e)), l2)
     assert np.abs(D.to_state(t, lab, list(range(n1 + n2))) - got).max() < 1e-12
+
+
+@pytest.mark.parametrize("n,depth,ncycles", [(12, 6, 2), (16, 5, 3), (12, 4, 4)])
+def test_device_bookkeeping_on_the_oracle(n, depth, ncycles):
+    """The package's split (positions, EI / E2Q operator matrices, final
+    permutations, relabelled remaining gates), replayed with the oracle's
+    primitives, gives the plain simulation of the circuit."""
+    from oracle import brute
+    from paper_1910_09534_amd import deferral
+    c = W.sycamore_circuit(n, depth, seed=300 + n)
+    sp = deferral.split(c, deferral.grid_halves(n), ncycles)
+    assert sp.n_bridging >= 1
+    s1 = orc.zero_state(sp.n1 + sp.e)
+    for g in sp.ops1:
+        orc.apply_dense(s1, list(g.qubits), g.matrix)
+    s2 = orc.zero_state(sp.n2 + sp.e)
+    for g in sp.ops2:
+        orc.apply_dense(s2, list(g.qubits), g.matrix)
+    t1 = brute.permute_state(s1, sp.n1 + sp.e, sp.order1)
+    t2 = brute.permute_state(s2, sp.n2 + sp.e, sp.order2)
+    joint = D.contract_matrix(t1, t2, sp.n1, sp.n2, sp.e)
+    for g in sp.rest:
+        orc.apply_dense(joint, list(g.qubits), g.matrix)
+    ref = orc.simulate(c)
+    x = np.arange(1 << n, dtype=np.uint64)
+    assert np.abs(joint[sp.joint_bits(x).astype(np.int64)] - ref).max() < 1e-12
