@@ -248,6 +248,9 @@ def main(argv=None) -> int:
     ap.add_argument("--pins", action="store_true", help="config 3: also run the mirror pin")
     ap.add_argument("--batch-unstaged", action="store_true",
                     help="config 4: autotuned single sweeps instead of staged passes")
+    ap.add_argument("--defer-cycles", type=int, default=2, help="config 6: cycles run as two tensors")
+    ap.add_argument("--no-pipeline", action="store_true",
+                    help="config 6: skip the whole deferred run after the timed contractions (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -264,6 +267,8 @@ def main(argv=None) -> int:
         return bench_batch(args)
     if args.config == 5:
         return bench_serve(args)
+    if args.config == 6:
+        return bench_contract(args)
 
     import torch
     from paper_1910_09534_amd import planner, sv
@@ -538,6 +543,159 @@ def bench_batch(args) -> int:
     }
     print(json.dumps(line), flush=True)
     return 0
+
+
+def bench_contract(args) -> int:
+    """Contraction deferral: the bridging gates of the first cycles of an
+    ABCDCDAB circuit as EI / E2Q on two tensors (left and right grid halves),
+    then the tensor 1 x tensor 2 contraction over the entanglement indices;
+    the contraction is timed (HIP events on its stream)."""
+    import torch
+    from oracle import oracle as orc
+    from oracle import deferral as odf
+    from oracle import brute
+    from paper_1910_09534_amd import deferral, planner, runner, sv
+    from paper_1910_09534_amd import workload as W
+
+    torch.cuda.set_device(0)
+    n = args.n or 30
+    depth = 14
+    circ = W.sycamore_circuit(n, depth, seed=1006)
+    sp = deferral.split(circ, deferral.grid_halves(n), args.defer_cycles)
+    n1, n2, e = sp.n1, sp.n2, sp.e
+    nt1, nt2 = n1 + e, n2 + e
+    # the two tensors on the GPU, entanglement indices at the top positions
+    states = []
+    for ops, nq, order in ((sp.ops1, nt1, sp.order1), (sp.ops2, nt2, sp.order2)):
+        st = sv.State(nq, 0, "c64")
+        sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(nq))
+        p = planner.plan(ops, args.kmax, nloc=nq, sparse_start=True)
+        for o in p:
+            o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+        planner.enqueue(st.h, p, st.dtype)
+        sv.permute_qubits(st.h, order)
+        sv.sync_state(st.h)
+        states.append(st)
+    p1, _ = sv.device_buffer(states[0].h)
+    p2, _ = sv.device_buffer(states[1].h)
+    out = torch.empty(1 << (n1 + n2), dtype=torch.complex64, device="cuda")
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream)
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    t0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream)
+        b.record(stream)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    kms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+    flops = 8.0 * float(1 << (n1 + n2)) * float(1 << e)        # complex multiply-add per term
+    hbm = 8.0 * ((1 << nt1) + (1 << nt2) + (1 << (n1 + n2)))     # read both tensors, write the joint state
+    # sampled outputs against the oracle's own tensors (never the GPU's)
+    rng = np.random.default_rng(6)
+    xs = rng.integers(0, 1 << (n1 + n2), size=1024, dtype=np.int64)
+    got = out[torch.from_numpy(xs).cuda()].cpu().numpy().astype(np.complex128)
+    for st in states:
+        st.close()
+    t_or = time.perf_counter()
+    ot = []
+    for ops, nq, order in ((sp.ops1, nt1, sp.order1), (sp.ops2, nt2, sp.order2)):
+        s = orc.zero_state(nq)
+        for g in ops:
+            orc.apply_dense(s, list(g.qubits), g.matrix)
+        ot.append(brute.permute_state(s, nq, order).reshape(1 << e, -1))
+        del s
+    x1 = xs & ((1 << n1) - 1)
+    x2 = xs >> n1
+    ref = np.einsum("ek,ek->k", ot[0][:, x1], ot[1][:, x2])
+    t_or = time.perf_counter() - t_or
+    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+    # CPU baseline: the oracle's contraction on a bounded sample (all of
+    # tensor 1 against the first 2^k columns of tensor 2)
+    cpu = None
+    if not args.no_cpu_baseline:
+        k = 4
+        while True:
+            t1c = time.perf_counter()
+            odf.contract_matrix(ot[0].reshape(-1), np.ascontiguousarray(ot[1][:, :1 << k]).reshape(-1),
+                                n1, k, e)
+            dt = time.perf_counter() - t1c
+            if dt > args.cpu_budget / 4 or k >= n2:
+                break
+            k += 1
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([p["num_threads"] for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+        except Exception:
+            cores = None
+        cpu = {"value": 8.0 * float(1 << (n1 + k)) * float(1 << e) / dt / 1e12, "unit": "TFLOP/s",
+               "cores": cores, "kind": "oracle",
+               "sample": f"contraction of tensor 1 with the first 2^{k} of 2^{n2} columns of tensor 2 "
+                         f"(complex128 matrix product, {dt:.1f} s)"}
+    del ot
+    # the whole deferred run once, for context
+    res = None
+    if not args.no_pipeline:
+        res = runner.simulate_deferred(circ, W.bitstrings(n, 1 << 16, seed=2006), sp.part1,
+                                       args.defer_cycles, kmax=args.kmax)
+    tf = flops / (kms * 1e-3) / 1e12
+    # the kernel's own arithmetic: three real products (3M form), 6 flops
+    # per complex multiply-add; the roofline is priced on those
+    flops_3m = 0.75 * flops
+    tf3 = flops_3m / (kms * 1e-3) / 1e12
+    line = {
+        "metric": "contraction deferral: tensor 1 x tensor 2 contraction TFLOP/s "
+                  "(complex-equivalent, 8 flops per complex multiply-add)",
+        "value": tf, "unit": "TFLOP/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(1e3 * t, 3), "higher_is_better": True, "vs_baseline": None, "dtype": "c64",
+        "data": "synthetic",
+        "config": {"workload": f"{n}-qubit ABCDCDAB depth {depth}: bridging gates of the first "
+                               f"{args.defer_cycles} cycles between the grid halves as EI / E2Q, "
+                               f"two tensors of {nt1} and {nt2} qubits ({e} entanglement indices), "
+                               f"contracted into the 2^{n1 + n2} joint state",
+                   "n": n, "n1": n1, "n2": n2, "e": e, "bridging_gates": sp.n_bridging},
+        "roofline": {"bound": "mfma", "achieved": round(tf3, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf3 / FP32_PEAK_TFLOPS, 4), "traffic": contract_traffic(),
+                     "kernel": "k_contract_mfma (3M form on FP32 matrix cores)",
+                     "avg_launch_ms": round(kms, 4), "flops_per_launch": flops_3m,
+                     "flops": "6 M N K: the 3M form's three real M x N x K products",
+                     "complex_equivalent_tflops": round(tf, 2),
+                     "hbm": {"bytes_per_launch": hbm, "achieved_gbs": round(hbm / (kms * 1e-3) / 1e9, 1)}},
+        "sampled_rel_l2_vs_oracle": err, "oracle_sample_s": round(t_or, 1),
+        "pipeline": None if res is None else
+        {"t_run_s": round(res["t_run"], 3), "t_tensors_s": round(res["t_tensors"], 3),
+         "contract_ms": round(res["contract_ms"], 3), "norm": res["norm"]},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+def contract_traffic():
+    """HBM bytes per k_contract_mfma launch from the committed counter runs,
+    or None when the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", "contract_30q_traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash("paper_1910_09534_amd/csrc/sv_contract.hip"):
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def source_hash(rel: str) -> str:
+    import hashlib
+    import re
+    with open(os.path.join(ROOT, rel)) as fh:
+        src = fh.read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    src = re.sub(r"//[^\n]*", "", src)
+    return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()[:16]
 
 
 def bench_serve(args) -> int:

@@ -35,17 +35,25 @@ constexpr int kCThreads = 256;
 constexpr int kBStride = kCM + 4; // LDS row strides in complex elements (padding staggers banks)
 constexpr int kAStride = kCN + 4;
 
-__global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* __restrict__ t1,
-                                                             const float2* __restrict__ t2,
+// t1 and t2 are not __restrict__: loads through such pointers count as
+// invariant and are moved past the scheduling fence that keeps them ahead of
+// the products
+__global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* t1, const float2* t2,
                                                              float2* __restrict__ out, int n1, int n2,
-                                                             int e, uint32_t tiles_n)
+                                                             int e, uint32_t tiles_n, uint32_t group)
 {
     __shared__ __attribute__((aligned(16))) float2 Bs[2][kCK * kBStride];
     __shared__ __attribute__((aligned(16))) float2 As[2][kCK * kAStride];
     const uint64_t N = 1ull << n1, M = 1ull << n2;
     const uint32_t K = 1u << e;
-    // consecutive workgroups share an output row block (the t2 panel stays in cache)
-    const uint32_t tn = blockIdx.x % tiles_n, tm = blockIdx.x / tiles_n;
+    // grouped order: `group` consecutive row blocks sweep the column blocks
+    // together, so a t1 panel is read once per group of row blocks (per XCD
+    // L2) and the group's t2 panels stay in cache across the sweep.  (Giving
+    // each XCD a contiguous range of this order instead measured 2x the L2
+    // refills.)
+    const uint32_t per = group * tiles_n;
+    const uint32_t g = blockIdx.x / per, r = blockIdx.x % per;
+    const uint32_t tn = r / group, tm = g * group + r % group;
     const uint64_t m0 = (uint64_t)tm * kCM, n0 = (uint64_t)tn * kCN;
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -53,36 +61,37 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* __res
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 32;
     const int li = lane & 15, lk = lane >> 4;
 
-    // global -> register staging of one K chunk: 4 float4 of t2, 2 of t1 per lane
-    float4 gb[4], ga[2];
-    auto load_chunk = [&](uint32_t k0) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = tid + kCThreads * i;
-            const int k = idx >> 6, m2 = idx & 63;
-            gb[i] = *(const float4*)(t2 + (uint64_t)(k0 + k) * M + m0 + 2 * m2);
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int idx = tid + kCThreads * i;
-            const int k = idx >> 5, n2i = idx & 31;
-            ga[i] = *(const float4*)(t1 + (uint64_t)(k0 + k) * N + n0 + 2 * n2i);
-        }
-    };
-    auto park_chunk = [&](int buf) {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int idx = tid + kCThreads * i;
-            const int k = idx >> 6, m2 = idx & 63;
-            *(float4*)(&Bs[buf][k * kBStride + 2 * m2]) = gb[i];
-        }
-#pragma unroll
-        for (int i = 0; i < 2; ++i) {
-            const int idx = tid + kCThreads * i;
-            const int k = idx >> 5, n2i = idx & 31;
-            *(float4*)(&As[buf][k * kAStride + 2 * n2i]) = ga[i];
-        }
-    };
+    // global -> register staging of one K chunk: 4 float4 of t2, 2 of t1 per
+    // lane (plain unrolled loops: the arrays stay in registers)
+    const uint32_t nchunks = K / kCK;
+    // named values rather than arrays: private arrays get moved to LDS
+    float4 gb0, gb1, gb2, gb3, ga0, ga1;
+    // this lane's slots: t2 rows k = tid / 64 + 4 i, columns 2 (tid % 64);
+    // t1 rows k = tid / 32 + 8 i, columns 2 (tid % 32)
+    const int kb = tid >> 6, mb2 = 2 * (tid & 63);
+    const int ka = tid >> 5, na2 = 2 * (tid & 31);
+    const int bo = kb * kBStride + mb2, ao = ka * kAStride + na2;
+    const uint64_t bg = (uint64_t)kb * M + m0 + mb2, ag = (uint64_t)ka * N + n0 + na2;
+#define SV_CONTRACT_LOAD(kn)                                              \
+    do {                                                                  \
+        const float2* pb = t2 + bg + (uint64_t)(kn) * M;                  \
+        const float2* pa = t1 + ag + (uint64_t)(kn) * N;                  \
+        gb0 = *(const float4*)(pb);                                       \
+        gb1 = *(const float4*)(pb + 4 * M);                               \
+        gb2 = *(const float4*)(pb + 8 * M);                               \
+        gb3 = *(const float4*)(pb + 12 * M);                              \
+        ga0 = *(const float4*)(pa);                                       \
+        ga1 = *(const float4*)(pa + 8 * N);                               \
+    } while (0)
+#define SV_CONTRACT_PARK(bf)                                              \
+    do {                                                                  \
+        *(float4*)(&Bs[bf][bo]) = gb0;                                    \
+        *(float4*)(&Bs[bf][bo + 4 * kBStride]) = gb1;                     \
+        *(float4*)(&Bs[bf][bo + 8 * kBStride]) = gb2;                     \
+        *(float4*)(&Bs[bf][bo + 12 * kBStride]) = gb3;                    \
+        *(float4*)(&As[bf][ao]) = ga0;                                    \
+        *(float4*)(&As[bf][ao + 8 * kAStride]) = ga1;                     \
+    } while (0)
 
     f4v p1[4][2], p2[4][2], p3[4][2];
 #pragma unroll
@@ -94,14 +103,17 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* __res
             p3[a][b] = p1[a][b];
         }
 
-    load_chunk(0);
-    park_chunk(0);
+    SV_CONTRACT_LOAD(0);
+    SV_CONTRACT_PARK(0);
     __syncthreads();
-    const uint32_t nchunks = K / kCK;
     for (uint32_t c = 0; c < nchunks; ++c) {
         const int buf = c & 1;
-        const bool next = c + 1 < nchunks;
-        if (next) load_chunk((c + 1) * kCK);
+        // the next chunk's loads are in flight during this chunk's products
+        // (the last iteration loads its own chunk again: in bounds, unused)
+        SV_CONTRACT_LOAD((c + 1 < nchunks ? c + 1 : c) * kCK);
+        // keep the loads ahead of the products (the scheduler would sink
+        // them to their use, after the products)
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
         for (int s = 0; s < kCK / 4; ++s) {
             const int k = 4 * s + lk;
@@ -129,9 +141,15 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* __res
                     p3[a][b] = __builtin_amdgcn_mfma_f32_16x16x4f32(bs[a], as_[b], p3[a][b], 0, 0, 0);
                 }
         }
-        if (next) park_chunk(buf ^ 1);
+        // park the next chunk in the other buffer (read by nobody since the
+        // previous barrier); after the products, so that only this waits
+        // for the loads
+        __builtin_amdgcn_sched_barrier(0);
+        SV_CONTRACT_PARK(buf ^ 1);
         __syncthreads();
     }
+#undef SV_CONTRACT_LOAD
+#undef SV_CONTRACT_PARK
     // lane holds rows 4 lk + v of each 16-row block, column li of each 16-column block
 #pragma unroll
     for (int a = 0; a < 4; ++a)
@@ -179,8 +197,10 @@ hipError_t launch_contract(hipStream_t st, const void* t1, const void* t2, void*
     if (contract_uses_mfma(dtype, n1, n2, e)) {
         const uint64_t tiles = (1ull << (n2 - 7)) * (1ull << (n1 - 6));
         if (tiles > 0x7fffffffull) return hipErrorInvalidValue;
+        const uint32_t tiles_m = 1u << (n2 - 7);
+        const uint32_t group = tiles_m < 16 ? tiles_m : 16;
         hipLaunchKernelGGL(k_contract_mfma, dim3((unsigned)tiles), dim3(kCThreads), 0, st, (const float2*)t1,
-                           (const float2*)t2, (float2*)out, n1, n2, e, (uint32_t)(1ull << (n1 - 6)));
+                           (const float2*)t2, (float2*)out, n1, n2, e, (uint32_t)(1ull << (n1 - 6)), group);
         return hipGetLastError();
     }
     const uint64_t total = 1ull << (n1 + n2);

@@ -170,8 +170,12 @@ def simulate_deferred(circuit, bits: np.ndarray, part1: Sequence[int], ncycles: 
         o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     jbits = sp.joint_bits(bits)
     t_plan = time.perf_counter() - t0
-    stream = torch.cuda.current_stream()
-    out = torch.empty(1 << circuit.n, dtype=torch.complex64, device="cuda")
+    # a stream of its own: the contraction and the joint state's work are
+    # ordered on it (a NULL stream would give the joint state a stream of
+    # the library's own, unordered with the contraction)
+    stream = torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        out = torch.empty(1 << circuit.n, dtype=torch.complex64, device="cuda")
     s1 = sv.State(nt1, 0, "c64")
     s2 = sv.State(nt2, 0, "c64")
     h3 = None
@@ -198,6 +202,7 @@ def simulate_deferred(circuit, bits: np.ndarray, part1: Sequence[int], ncycles: 
         sv.set_option(h3, sv.SV_OPT_STAGE, planner.stage_tmax(circuit.n))
         planner.enqueue(h3, rest, sv.SV_C64)
         amps, stats = sv.reduce_slices(h3, jbits)
+        stream.synchronize()
         t3 = time.perf_counter()
         return {"amps": amps, "norm": stats[0], "xeb_sum": stats[1], "xeb_log_sum": stats[2],
                 "split": sp, "t_plan": t_plan, "t_tensors": t2 - t1,
