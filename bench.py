@@ -249,6 +249,8 @@ def main(argv=None) -> int:
     ap.add_argument("--batch-unstaged", action="store_true",
                     help="config 4: autotuned single sweeps instead of staged passes")
     ap.add_argument("--defer-cycles", type=int, default=2, help="config 6: cycles run as two tensors")
+    ap.add_argument("--tier-dir", default=None,
+                    help="config 3: keep the host tier in files in this directory (one per logical file)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="config 6: skip the whole deferred run after the timed contractions (profiling)")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -411,7 +413,7 @@ def bench_sliced(args) -> int:
     torch.cuda.set_device(0)
     mask = sum(1 << q for q in sched.phases[0].sliced)
     t0 = time.perf_counter()
-    st = sv.State(n, mask, "c64", tier=True)
+    st = sv.State(n, mask, "c64", tier=True, tier_dir=args.tier_dir)
     t_alloc = time.perf_counter() - t0
     print(f"# tier allocated in {t_alloc:.1f} s; {len(sched.phases)} phases", file=sys.stderr,
           flush=True)
@@ -444,7 +446,9 @@ def bench_sliced(args) -> int:
         "unit": "amp-updates/s", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": round(1e3 * t, 1),
         "higher_is_better": True, "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"{n}-qubit ABCDCDAB depth {depth}, complex64, 4 sliced qubits "
-                               f"(16 slices of 2^{n - 4}) in a host-memory tier, 2^20 bitstrings",
+                               f"(16 slices of 2^{n - 4}) in a host-memory tier"
+                               + (" backed by files (one per logical file)" if args.tier_dir else "")
+                               + ", 2^20 bitstrings",
                    "n": n, "gates": gates, "slice_sets": [list(A), list(B)],
                    "phases": len(sched.phases), "sweeps_per_slice": sum(len(p_.ops) for p_ in sched.phases),
                    "trailing_gates": len(sched.trailing_gate_ids)},

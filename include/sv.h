@@ -96,6 +96,21 @@ enum { SV_FLAG_KEEP = 0x200 };
 int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream,
                      void* dev_buf, size_t bytes, sv_handle* out);
 
+/*
+ * create_state_files -- as create_state with SV_FLAG_TIER, but the host tier
+ * lives in files on a file system (Sec. 4: the slices of the state go to
+ * secondary storage, each logical file written and read whole; App. A,
+ * the "write" and "read" modes): one file per logical file, created in
+ * directory dir (which must exist and be writable), memory-mapped shared,
+ * so the page cache moves the data to and from storage, and removed by
+ * destroy_state.  The state needs 1 <= s <= n/2 sliced qubits; the files
+ * hold 2^(n-s) amplitudes in total.  Errors: SV_EINVAL (dir NULL or empty,
+ * bad sizes), SV_EIO (a file cannot be created, sized or mapped),
+ * SV_ENOMEM, SV_EDEVICE.
+ */
+int create_state_files(int n, uint64_t slice_mask, int dtype, void* hip_stream, const char* dir,
+                       sv_handle* out);
+
 /* destroy_state -- wait for queued work, free everything the handle owns.
    Accepts a poisoned handle; NULL is a no-op.  */
 int destroy_state(sv_handle h);

@@ -9,10 +9,13 @@
 // the union of the two alternating slice sets and always read or written
 // whole): slice t is 2^s files of 2^(L - s) amplitudes, and re-choosing the
 // sliced qubits among the 2s top positions only relabels files.
+#include <fcntl.h>
 #include <hip/hip_runtime.h>
 #include <sys/mman.h>
+#include <unistd.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <deque>
 #include <new>
@@ -703,6 +706,8 @@ void release(sv_state* h)
         if (h->pinned_tier) (void)hipHostFree(p);
         else munmap(p, fbytes);
     }
+    for (int fd : h->file_fds) (void)close(fd);
+    for (const auto& path : h->file_paths) (void)unlink(path.c_str());
     for (void* p : h->slots)
         if (p) (void)hipFree(p);
     if (h->pslot) (void)hipFree(h->pslot);
@@ -734,7 +739,7 @@ void default_layout(sv_state* h)
 }
 
 int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext, size_t ext_bytes,
-                  sv_handle* out)
+                  sv_handle* out, const char* dir = nullptr)
 {
     if (!out) return set_err(nullptr, SV_EINVAL, "out is NULL");
     const int base = dtype & 0xff;
@@ -762,7 +767,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         h->own_stream = true;
     }
     const size_t total = ((size_t)1 << n) * h->amp;
-    bool tier = (dtype & SV_FLAG_TIER) != 0;
+    bool tier = (dtype & SV_FLAG_TIER) != 0 || dir != nullptr;
     if (ext) {
         if (tier) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer cannot be tiered"); }
         if (ext_bytes < total) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer too small"); }
@@ -797,7 +802,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         // (or when pinning fails); pageable files are anonymous mappings whose
         // pages stay unbacked until written.
         const size_t kPinnedBudget = (size_t)48 << 30;
-        h->pinned_tier = (fb * h->files.size() <= kPinnedBudget) && !(dtype & SV_FLAG_PAGEABLE);
+        h->pinned_tier = (fb * h->files.size() <= kPinnedBudget) && !(dtype & SV_FLAG_PAGEABLE) && !dir;
         if (h->pinned_tier) {
             for (auto& f : h->files) {
                 if (hipHostMalloc(&f, fb, hipHostMallocDefault) != hipSuccess) {
@@ -814,7 +819,31 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
                     f = nullptr;
                 }
         }
-        if (!h->pinned_tier) {
+        if (dir) {
+            // one file per logical file (Sec. 4: slices go to secondary storage
+            // as whole files), mapped shared: the page cache does the I/O
+            static std::atomic<unsigned> seq{0};
+            const unsigned id = seq.fetch_add(1);
+            for (size_t i = 0; i < h->files.size(); ++i) {
+                const std::string path = std::string(dir) + "/sv_tier_" + std::to_string((long)getpid()) + "_" +
+                                         std::to_string(id) + "_" + std::to_string(i) + ".bin";
+                const int fd = open(path.c_str(), O_RDWR | O_CREAT | O_EXCL, 0600);
+                if (fd < 0) {
+                    release(h);
+                    return set_err(nullptr, SV_EIO, "cannot create tier file " + path);
+                }
+                h->file_fds.push_back(fd);
+                h->file_paths.push_back(path);
+                void* p = MAP_FAILED;
+                if (ftruncate(fd, (off_t)fb) == 0)
+                    p = mmap(nullptr, fb, PROT_READ | PROT_WRITE, MAP_SHARED, fd, 0);
+                if (p == MAP_FAILED) {
+                    release(h);
+                    return set_err(nullptr, SV_EIO, "cannot size or map tier file " + path);
+                }
+                h->files[i] = p;
+            }
+        } else if (!h->pinned_tier) {
             for (auto& f : h->files) {
                 void* p = mmap(nullptr, fb, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS, -1, 0);
                 if (p == MAP_FAILED) {
@@ -1005,6 +1034,13 @@ extern "C" {
 int create_state(int n, uint64_t slice_mask, int dtype, void* hip_stream, sv_handle* out)
 {
     return create_common(n, slice_mask, dtype, hip_stream, nullptr, 0, out);
+}
+
+int create_state_files(int n, uint64_t slice_mask, int dtype, void* hip_stream, const char* dir,
+                       sv_handle* out)
+{
+    if (!dir || !*dir) return set_err(nullptr, SV_EINVAL, "directory is NULL or empty");
+    return create_common(n, slice_mask, dtype | SV_FLAG_TIER, hip_stream, nullptr, 0, out, dir);
 }
 
 int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream, void* dev_buf,
@@ -1239,9 +1275,17 @@ int sv_reset(sv_handle h)
     TRY(h, hipStreamSynchronize(h->s_in));
     TRY(h, hipStreamSynchronize(h->s_out));
     const size_t fb = file_amps(h) * h->amp;
-    for (void* f : h->files) {
-        if (h->pinned_tier) std::memset(f, 0, fb);
-        else (void)madvise(f, fb, MADV_DONTNEED);      // pages read back as zero
+    for (size_t i = 0; i < h->files.size(); ++i) {
+        void* f = h->files[i];
+        if (h->pinned_tier) {
+            std::memset(f, 0, fb);
+        } else if (!h->file_fds.empty()) {
+            // file blocks freed: they read back as zero
+            if (fallocate(h->file_fds[i], FALLOC_FL_PUNCH_HOLE | FALLOC_FL_KEEP_SIZE, 0, (off_t)fb) != 0)
+                std::memset(f, 0, fb);
+        } else {
+            (void)madvise(f, fb, MADV_DONTNEED);      // pages read back as zero
+        }
     }
     if (h->dtype) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
     else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }

@@ -62,7 +62,7 @@ def grid_slice_sets(n: int):
 
 def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: int = 5,
                     tier: bool = False, timing: bool = False, sched=None,
-                    pageable: bool = False) -> Dict[str, object]:
+                    pageable: bool = False, tier_dir: Optional[str] = None) -> Dict[str, object]:
     """Sliced evolution (Sec. 4): phases alternate the sliced set; each switch
     is one permute_qubits; the trailing gates on the last sliced set are
     applied by the FP64 cross-slice reduction."""
@@ -72,7 +72,7 @@ def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: 
     t_plan = time.perf_counter() - t0
     n = circuit.n
     mask = sum(1 << q for q in sched.phases[0].sliced)
-    st = sv.State(n, mask, dtype, tier=tier, pageable=pageable)
+    st = sv.State(n, mask, dtype, tier=tier, pageable=pageable, tier_dir=tier_dir)
     try:
         if timing:
             sv.set_option(st.h, sv.SV_OPT_TIMING, 1)

@@ -24,7 +24,7 @@ SV_OPT_SPARSE_START = 7
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
 
-EXPORTS = ("create_state", "create_state_ext", "destroy_state", "apply_fused", "apply_diag",
+EXPORTS = ("create_state", "create_state_ext", "create_state_files", "destroy_state", "apply_fused", "apply_diag",
            "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
@@ -46,6 +46,7 @@ def load():
     P, I, I64, U64, SZ = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64, ctypes.c_uint64, ctypes.c_size_t
     L.create_state.argtypes = [I, U64, I, P, ctypes.POINTER(P)]
     L.create_state_ext.argtypes = [I, U64, I, P, P, SZ, ctypes.POINTER(P)]
+    L.create_state_files.argtypes = [I, U64, I, P, ctypes.c_char_p, ctypes.POINTER(P)]
     L.destroy_state.argtypes = [P]
     L.apply_fused.argtypes = [P, I, P, P]
     L.apply_diag.argtypes = [P, I, P, P]
@@ -121,6 +122,14 @@ def create_state_ext(n: int, slice_mask: int, dtype, stream, dev_ptr: int, nbyte
     h = ctypes.c_void_p()
     code = _dtype_code(dtype) | (SV_FLAG_KEEP if keep else 0)
     _check(lib().create_state_ext(n, slice_mask, code, stream, dev_ptr, nbytes, ctypes.byref(h)))
+    return h.value
+
+
+def create_state_files(n: int, slice_mask: int, dtype, stream, directory: str):
+    """Tiered state whose logical files are files in `directory`."""
+    h = ctypes.c_void_p()
+    _check(lib().create_state_files(n, slice_mask, _dtype_code(dtype), stream, directory.encode(),
+                                    ctypes.byref(h)))
     return h.value
 
 
@@ -271,9 +280,12 @@ class State:
     """Owning wrapper around a handle (context manager)."""
 
     def __init__(self, n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False,
-                 pageable: bool = False):
+                 pageable: bool = False, tier_dir: Optional[str] = None):
         self.n, self.slice_mask, self.dtype = n, slice_mask, _dtype_code(dtype)
-        self.h = create_state(n, slice_mask, dtype, stream, tier, pageable)
+        if tier_dir is not None:
+            self.h = create_state_files(n, slice_mask, dtype, stream, tier_dir)
+        else:
+            self.h = create_state(n, slice_mask, dtype, stream, tier, pageable)
 
     def fused(self, qubits, matrix):
         apply_fused(self.h, qubits, matrix, self.dtype)

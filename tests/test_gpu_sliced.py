@@ -37,15 +37,18 @@ def test_sliced_circuit_vs_oracle(n, depth, dtype, tier):
         assert res["counters"]["bytes_h2d"] > 0 and res["counters"]["bytes_d2h"] > 0
 
 
-@pytest.mark.parametrize("tier", [False, True, "pageable"])
-def test_random_permutes_and_gates(tier):
+@pytest.mark.parametrize("tier", [False, True, "pageable", "files"])
+def test_random_permutes_and_gates(tier, tmp_path):
     """Random gates on the unsliced qubits between random re-layouts that
     change 0..s of the sliced qubits; every amplitude checked (complex128)."""
     _gpu()
     n, S = 12, (1, 6, 10)
     rng = np.random.default_rng(77)
     mask = sum(1 << q for q in S)
-    st = sv.State(n, mask, "c128", tier=bool(tier), pageable=(tier == "pageable"))
+    st = sv.State(n, mask, "c128", tier=bool(tier), pageable=(tier == "pageable"),
+                  tier_dir=str(tmp_path) if tier == "files" else None)
+    if tier == "files":
+        assert len(list(tmp_path.iterdir())) == (1 << len(S)) ** 2     # one file per logical file
     psi = orc.zero_state(n)
     order = st.order()
     try:
@@ -166,3 +169,39 @@ def test_injected_transfer_failure_poisons_handle(pageable, fail_at):
         assert e3.value.code == sv.SV_ESTATE
     finally:
         st.close()                                   # destroy accepts a poisoned handle
+
+
+def test_file_tier_reset_and_cleanup(tmp_path):
+    """A state whose tier lives in files: gates, sv_reset (the file blocks
+    are freed and read back as zero), gates again, every amplitude against
+    the oracle; a sliced circuit through runner.simulate_sliced on files;
+    the files are removed with the handle."""
+    _gpu()
+    n, S = 14, (2, 7, 11)
+    rng = np.random.default_rng(78)
+    st = sv.State(n, sum(1 << q for q in S), "c128", tier_dir=str(tmp_path))
+    try:
+        assert len(list(tmp_path.iterdir())) == 64
+        local = [q for q in range(n) if q not in S]
+        for rnd in range(2):
+            sv.reset(st.h)
+            psi = orc.zero_state(n)
+            for _ in range(6):
+                qs = [int(x) for x in rng.choice(local, size=3, replace=False)]
+                u = W.random_unitary(8, rng)
+                st.fused(qs, u)
+                orc.apply_dense(psi, qs, u)
+            got = st.gather(np.arange(1 << n, dtype=np.uint64))
+            assert orc.rel_l2(got, psi) <= 1e-12, rnd
+    finally:
+        st.close()
+    assert list(tmp_path.iterdir()) == []
+    n = 16
+    c = W.sycamore_circuit(n, 10, seed=5101)
+    A, B = runner.grid_slice_sets(n)
+    bits = W.bitstrings(n, 2048, seed=9)
+    res = runner.simulate_sliced(c, bits, A, B, dtype="c64", kmax=5, tier_dir=str(tmp_path))
+    ref, _ = orc.reduce_slices_ref(orc.simulate(c), (), None, bits)
+    assert orc.rel_l2(res["amps"], ref) <= TOL["c64"]
+    assert res["counters"]["bytes_h2d"] > 0
+    assert list(tmp_path.iterdir()) == []
