@@ -453,7 +453,8 @@ def bench_sliced(args) -> int:
                    "phases": len(sched.phases), "sweeps_per_slice": sum(len(p_.ops) for p_ in sched.phases),
                    "trailing_gates": len(sched.trailing_gate_ids)},
         "host_link_GBps": round((cnt["bytes_h2d"] + cnt["bytes_d2h"]) / t / 1e9, 2),
-        "tier": "pinned" if (1 << n) * 8 <= (48 << 30) else "pageable + pinned bounce buffers",
+        "tier": ("files (shared mappings) + pinned bounce buffers" if args.tier_dir else
+                 "pinned" if (1 << n) * 8 <= (48 << 30) else "pageable + pinned bounce buffers"),
         "bytes_h2d": cnt["bytes_h2d"], "bytes_d2h": cnt["bytes_d2h"],
         "zero_slices_skipped": cnt["zero_slices_skipped"],
         "dense_sweep_ms_total": round(sweep_ms, 1), "dense_sweeps": nswept,
