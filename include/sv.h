@@ -63,8 +63,13 @@ enum { SV_C64 = 0, SV_C128 = 1 };
 /* Flags OR-ed into the dtype argument of create_state. */
 enum {
     SV_FLAG_TIER = 0x100,     /* keep slices in the host tier even if they fit in HBM */
-    SV_FLAG_PAGEABLE = 0x400  /* host tier in pageable memory even if it would fit the
+    SV_FLAG_PAGEABLE = 0x400, /* host tier in pageable memory even if it would fit the
                                  pinned budget (48 GiB; larger tiers are pageable) */
+    SV_FLAG_STORE32 = 0x800   /* SV_C128 only: the host tier (implied) stores single
+                                 precision, 8 bytes per amplitude, while the device
+                                 computes in double (Sec. 5: storage in single precision,
+                                 in-memory calculations in double); every write to the
+                                 tier rounds the amplitudes to complex64 */
 };
 
 typedef struct sv_state* sv_handle;

@@ -454,6 +454,34 @@ void par_memcpy(void* dst, const void* src, size_t bytes)
     for (auto& t : th) t.join();
 }
 
+// Complex128 <-> complex64 between host buffers (files of a tier that stores
+// single precision), split over threads like par_memcpy.
+void par_widen(double* dst, const float* src, size_t count)
+{
+    auto run = [=](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; ++i) dst[i] = (double)src[i];
+    };
+    if (count < ((size_t)1 << 19)) { run(0, count); return; }
+    std::thread th[kCopyThreads];
+    const size_t part = (count + kCopyThreads - 1) / kCopyThreads;
+    for (int i = 0; i < kCopyThreads; ++i)
+        th[i] = std::thread(run, std::min(count, part * i), std::min(count, part * (i + 1)));
+    for (auto& t : th) t.join();
+}
+
+void par_narrow(float* dst, const double* src, size_t count)
+{
+    auto run = [=](size_t lo, size_t hi) {
+        for (size_t i = lo; i < hi; ++i) dst[i] = (float)src[i];
+    };
+    if (count < ((size_t)1 << 19)) { run(0, count); return; }
+    std::thread th[kCopyThreads];
+    const size_t part = (count + kCopyThreads - 1) / kCopyThreads;
+    for (int i = 0; i < kCopyThreads; ++i)
+        th[i] = std::thread(run, std::min(count, part * i), std::min(count, part * (i + 1)));
+    for (auto& t : th) t.join();
+}
+
 struct OutChunk {
     const char* src;   // device
     char* dst;         // pageable file memory
@@ -504,7 +532,8 @@ struct BouncePipe {
         auto [b, c] = inflight.front();
         inflight.pop_front();
         TRY_IO(h, hipEventSynchronize(ev_bout[b]));
-        par_memcpy(c.dst, bout[b], c.bytes);
+        if (h->store32) par_narrow((float*)c.dst, (const double*)bout[b], c.bytes / sizeof(double));
+        else par_memcpy(c.dst, bout[b], c.bytes);
         free_out[nfree_out++] = b;
         return SV_OK;
     }
@@ -555,6 +584,8 @@ struct BouncePipe {
     }
     // stage a slice in: file chunk -> bounce (host) -> slot (s_in); out-chunks
     // are pumped between chunks so both directions stay busy
+    // (offsets are in device bytes; a single-precision file holds
+    // famp / amp of them)
     int stage_in(uint64_t t, void* slot)
     {
         const size_t fb = file_amps(h) * h->amp;
@@ -566,7 +597,9 @@ struct BouncePipe {
                 next_in = (next_in + 1) % kBounce;
                 TRY_IO(h, hipEventSynchronize(ev_bin[b]));
                 CHECK_INJECTED_IO(h);
-                par_memcpy(bin[b], (const char*)h->files[t * nf + u] + off, n);
+                const char* src = (const char*)h->files[t * nf + u] + off / h->amp * h->famp;
+                if (h->store32) par_widen((double*)bin[b], (const float*)src, n / sizeof(double));
+                else par_memcpy(bin[b], src, n);
                 TRY_IO(h, hipMemcpyAsync((char*)slot + (size_t)u * fb + off, bin[b], n,
                                          hipMemcpyHostToDevice, h->s_in));
                 TRY_IO(h, hipEventRecord(ev_bin[b], h->s_in));
@@ -583,7 +616,8 @@ struct BouncePipe {
         for (int u = 0; u < nf; ++u)
             for (size_t off = 0; off < fb; off += kChunk)
                 pending.push_back({(const char*)slot + (size_t)u * fb + off,
-                                   (char*)h->files[t * nf + u] + off, std::min(kChunk, fb - off), idx, k,
+                                   (char*)h->files[t * nf + u] + off / h->amp * h->famp,
+                                   std::min(kChunk, fb - off), idx, k,
                                    u == nf - 1 && off + kChunk >= fb});
     }
 };
@@ -700,7 +734,7 @@ void release(sv_state* h)
     if (h->s_out) (void)hipStreamSynchronize(h->s_out);
     if (h->own_dev && h->dev) (void)hipFree(h->dev);
     if (h->scratch) (void)hipFree(h->scratch);
-    const size_t fbytes = h->files.empty() ? 0 : ((size_t)1 << (h->L - h->s)) * h->amp;
+    const size_t fbytes = h->files.empty() ? 0 : ((size_t)1 << (h->L - h->s)) * h->famp;
     for (void* p : h->files) {
         if (!p) continue;
         if (h->pinned_tier) (void)hipHostFree(p);
@@ -756,6 +790,8 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
     h->L = n - s;
     h->dtype = base;
     h->amp = base ? 16 : 8;
+    h->store32 = base == SV_C128 && (dtype & SV_FLAG_STORE32);
+    h->famp = h->store32 ? 8 : h->amp;
     h->slice_mask = slice_mask;
     default_layout(h);
     hipError_t e;
@@ -767,7 +803,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         h->own_stream = true;
     }
     const size_t total = ((size_t)1 << n) * h->amp;
-    bool tier = (dtype & SV_FLAG_TIER) != 0 || dir != nullptr;
+    bool tier = (dtype & SV_FLAG_TIER) != 0 || dir != nullptr || h->store32;
     if (ext) {
         if (tier) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer cannot be tiered"); }
         if (ext_bytes < total) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer too small"); }
@@ -795,14 +831,16 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
     if (tier) {
         if (s < 1 || h->L - s < 0) { release(h); return set_err(nullptr, SV_EINVAL, "tier needs 1 <= s <= n/2"); }
         const int ns = 1 << s;
-        const size_t fb = file_amps(h) * h->amp;
+        const size_t fb = file_amps(h) * h->famp;
         h->files.assign((size_t)ns * ns, nullptr);
         // Pinned memory is scarce (the driver caps it well below host RAM):
         // the tier is pinned up to kPinnedBudget and pageable beyond that
         // (or when pinning fails); pageable files are anonymous mappings whose
         // pages stay unbacked until written.
         const size_t kPinnedBudget = (size_t)48 << 30;
-        h->pinned_tier = (fb * h->files.size() <= kPinnedBudget) && !(dtype & SV_FLAG_PAGEABLE) && !dir;
+        // (a single-precision tier converts in the host copies of the bounce path)
+        h->pinned_tier = (fb * h->files.size() <= kPinnedBudget) && !(dtype & SV_FLAG_PAGEABLE) && !dir &&
+                         !h->store32;
         if (h->pinned_tier) {
             for (auto& f : h->files) {
                 if (hipHostMalloc(&f, fb, hipHostMallocDefault) != hipSuccess) {
@@ -856,7 +894,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
             }
         }
         // |0...0>: amplitude 0 lives in file (t = 0, u = 0)
-        if (base) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
+        if (h->famp == 16) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
         else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
         h->slice_zero.assign(ns, 1);
         h->slice_zero[0] = 0;
@@ -1274,7 +1312,7 @@ int sv_reset(sv_handle h)
     TRY(h, hipStreamSynchronize(h->stream));
     TRY(h, hipStreamSynchronize(h->s_in));
     TRY(h, hipStreamSynchronize(h->s_out));
-    const size_t fb = file_amps(h) * h->amp;
+    const size_t fb = file_amps(h) * h->famp;
     for (size_t i = 0; i < h->files.size(); ++i) {
         void* f = h->files[i];
         if (h->pinned_tier) {
@@ -1287,7 +1325,7 @@ int sv_reset(sv_handle h)
             (void)madvise(f, fb, MADV_DONTNEED);      // pages read back as zero
         }
     }
-    if (h->dtype) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
+    if (h->famp == 16) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
     else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
     // |0...0> sits in slice 0, file 0 only if index 0 maps there: it does in
     // every layout (all bits zero)

@@ -57,6 +57,8 @@ struct sv_state {
     // host tier
     std::vector<void*> files;             // [t * 2^s + u], 2^(L-s) amplitudes each
     bool pinned_tier = true;              // files pinned (hipHostMalloc) or pageable (mmap)
+    bool store32 = false;                 // complex128 state whose files hold complex64
+    int famp = 8;                         // bytes per amplitude in the files
     std::vector<int> file_fds;            // file-backed tier: one open file per logical file
     std::vector<std::string> file_paths;  //   (removed when the handle is destroyed)
     std::vector<uint8_t> slice_zero;      // slice known to be all zero

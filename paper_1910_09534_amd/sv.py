@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libsv.so")
 
 SV_OK, SV_EINVAL, SV_ENOMEM, SV_EDEVICE, SV_ESLICED, SV_ESTATE, SV_EIO = 0, -1, -2, -3, -4, -5, -6
 SV_C64, SV_C128 = 0, 1
-SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE = 0x100, 0x200, 0x400
+SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE, SV_FLAG_STORE32 = 0x100, 0x200, 0x400, 0x800
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
 SV_OPT_SPARSE_START = 7
 
@@ -109,10 +109,11 @@ def np_dtype(code: int):
 
 
 def create_state(n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False,
-                 pageable: bool = False):
+                 pageable: bool = False, store32: bool = False):
     """Returns an opaque handle (int)."""
     h = ctypes.c_void_p()
-    code = _dtype_code(dtype) | (SV_FLAG_TIER if tier else 0) | (SV_FLAG_PAGEABLE if pageable else 0)
+    code = _dtype_code(dtype) | (SV_FLAG_TIER if tier else 0) | (SV_FLAG_PAGEABLE if pageable else 0) | \
+        (SV_FLAG_STORE32 if store32 else 0)
     _check(lib().create_state(n, slice_mask, code, stream, ctypes.byref(h)))
     return h.value
 
@@ -125,11 +126,11 @@ def create_state_ext(n: int, slice_mask: int, dtype, stream, dev_ptr: int, nbyte
     return h.value
 
 
-def create_state_files(n: int, slice_mask: int, dtype, stream, directory: str):
+def create_state_files(n: int, slice_mask: int, dtype, stream, directory: str, store32: bool = False):
     """Tiered state whose logical files are files in `directory`."""
     h = ctypes.c_void_p()
-    _check(lib().create_state_files(n, slice_mask, _dtype_code(dtype), stream, directory.encode(),
-                                    ctypes.byref(h)))
+    code = _dtype_code(dtype) | (SV_FLAG_STORE32 if store32 else 0)
+    _check(lib().create_state_files(n, slice_mask, code, stream, directory.encode(), ctypes.byref(h)))
     return h.value
 
 
@@ -280,12 +281,12 @@ class State:
     """Owning wrapper around a handle (context manager)."""
 
     def __init__(self, n: int, slice_mask: int = 0, dtype="c64", stream=None, tier: bool = False,
-                 pageable: bool = False, tier_dir: Optional[str] = None):
+                 pageable: bool = False, tier_dir: Optional[str] = None, store32: bool = False):
         self.n, self.slice_mask, self.dtype = n, slice_mask, _dtype_code(dtype)
         if tier_dir is not None:
-            self.h = create_state_files(n, slice_mask, dtype, stream, tier_dir)
+            self.h = create_state_files(n, slice_mask, dtype, stream, tier_dir, store32)
         else:
-            self.h = create_state(n, slice_mask, dtype, stream, tier, pageable)
+            self.h = create_state(n, slice_mask, dtype, stream, tier, pageable, store32)
 
     def fused(self, qubits, matrix):
         apply_fused(self.h, qubits, matrix, self.dtype)

@@ -205,3 +205,42 @@ def test_file_tier_reset_and_cleanup(tmp_path):
     assert orc.rel_l2(res["amps"], ref) <= TOL["c64"]
     assert res["counters"]["bytes_h2d"] > 0
     assert list(tmp_path.iterdir()) == []
+
+
+@pytest.mark.parametrize("files", [False, True])
+def test_single_precision_storage(files, tmp_path):
+    """A complex128 state whose tier stores complex64 (8 bytes per
+    amplitude; device arithmetic in double): random gates between re-layouts
+    that move slices through the tier agree with the oracle to single
+    precision (every write to the tier rounds), the files hold 8 bytes per
+    amplitude, and the same run with double storage agrees to 1e-12."""
+    _gpu()
+    n, S = 14, (1, 6, 10)
+    mask = sum(1 << q for q in S)
+    results = {}
+    for store32 in (True, False):
+        rng = np.random.default_rng(91)
+        st = sv.State(n, mask, "c128", tier=True, store32=store32,
+                      tier_dir=str(tmp_path) if files else None)
+        try:
+            if files:
+                sizes = {p.stat().st_size for p in tmp_path.iterdir()}
+                assert sizes == {(1 << (n - 2 * len(S))) * (8 if store32 else 16)}
+            psi = orc.zero_state(n)
+            order = st.order()
+            for rnd in range(5):
+                sliced = set(order[n - len(S):])
+                local = [q for q in range(n) if q not in sliced]
+                for _ in range(4):
+                    qs = [int(x) for x in rng.choice(local, size=3, replace=False)]
+                    u = W.random_unitary(8, rng)
+                    st.fused(qs, u)
+                    orc.apply_dense(psi, qs, u)
+                order = [int(x) for x in rng.permutation(n)]
+                st.permute(order)
+            got = st.gather(np.arange(1 << n, dtype=np.uint64))
+        finally:
+            st.close()
+        results[store32] = orc.rel_l2(got, psi)
+    assert results[False] <= 1e-12
+    assert 1e-10 < results[True] <= 2e-6
