@@ -302,8 +302,8 @@ const char* sv_batch_error(sv_batch b);
  *   (FP32 sums, on the matrix cores when 2^n2 >= 128, 2^n1 >= 64 and
  *   2^e >= 16) or SV_C128 (FP64 sums).  All buffers 16-byte aligned.
  *   hip_stream: stream to run on (NULL: the null stream); asynchronous.
- *   Errors: SV_EINVAL (NULL or misaligned buffer, n1 + n2, n1 + e or n2 + e
- *   above 40, overlap), SV_EDEVICE; the text is last_error(NULL). */
+ *   Errors: SV_EINVAL (NULL or misaligned buffer, e above 30, n1 + n2, n1 + e
+ *   or n2 + e above 40, overlap), SV_EDEVICE; the text is last_error(NULL). */
 int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e, int dtype, void* hip_stream);
 
 #ifdef __cplusplus

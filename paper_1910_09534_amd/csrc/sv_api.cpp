@@ -1411,7 +1411,7 @@ int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e
 {
     if (!t1 || !t2 || !out) return set_err(nullptr, SV_EINVAL, "sv_contract: NULL buffer");
     if (dtype != SV_C64 && dtype != SV_C128) return set_err(nullptr, SV_EINVAL, "sv_contract: bad dtype");
-    if (n1 < 0 || n2 < 0 || e < 0 || n1 + n2 > 40 || n1 + e > 40 || n2 + e > 40)
+    if (n1 < 0 || n2 < 0 || e < 0 || e > 30 || n1 + n2 > 40 || n1 + e > 40 || n2 + e > 40)
         return set_err(nullptr, SV_EINVAL, "sv_contract: sizes out of range");
     if (((uintptr_t)t1 | (uintptr_t)t2 | (uintptr_t)out) & 15)
         return set_err(nullptr, SV_EINVAL, "sv_contract: buffers must be 16-byte aligned");

@@ -67,6 +67,8 @@ def test_contract_rejects_bad_arguments():
         sv.contract(a.data_ptr(), b.data_ptr(), o.data_ptr(), 30, 20, 4, "c64")       # too large
     with pytest.raises(sv.SVError):
         sv.contract(a.data_ptr(), b.data_ptr(), o.data_ptr(), 6, 6, -1, "c64")
+    with pytest.raises(sv.SVError):
+        sv.contract(a.data_ptr(), b.data_ptr(), o.data_ptr(), 2, 2, 31, "c64")       # e above 30
 
 
 @pytest.mark.parametrize("n,depth,ncycles", [(16, 8, 2), (16, 6, 4), (20, 8, 3)])
