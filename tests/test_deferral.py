@@ -110,3 +110,49 @@ def test_device_bookkeeping_on_the_oracle(n, depth, ncycles):
     ref = orc.simulate(c)
     x = np.arange(1 << n, dtype=np.uint64)
     assert np.abs(joint[sp.joint_bits(x).astype(np.int64)] - ref).max() < 1e-12
+
+
+def test_device_bookkeeping_any_gate_order():
+    """Bridging gates listed in either qubit order, several on the same
+    qubit, general (non-unitary) matrices, and gates after the deferred
+    prefix: the package's split replayed on the oracle equals applying the
+    gates in sequence."""
+    from oracle import brute
+    from paper_1910_09534_amd import deferral
+    rng = np.random.default_rng(12)
+    n = 9
+    part1 = [0, 2, 3, 7]
+    part2 = [q for q in range(n) if q not in part1]
+    bridging = {5: (0, 1), 13: (5, 3), 22: (2, 8), 31: (6, 2)}   # either order, qubit 2 twice
+    gates = []
+    for i in range(40):
+        if i in bridging:
+            qs = bridging[i]
+        else:
+            side = part1 if rng.random() < 0.5 else part2
+            k = int(rng.integers(1, 3))
+            qs = tuple(int(x) for x in rng.choice(side, size=k, replace=False))
+        gates.append(W.Gate(qs, _rand((1 << len(qs), 1 << len(qs)), rng), "g", i // 4))
+    c = W.Circuit(n, gates, 10)
+    ref = orc.zero_state(n)
+    for g in gates:
+        orc.apply_dense(ref, list(g.qubits), g.matrix)
+    for ncycles in (3, 6, 10):
+        sp = deferral.split(c, part1, ncycles)
+        firsts = {g.qubits[0] in part1 for g in gates[:4 * ncycles] if len(g.qubits) == 2
+                  and (g.qubits[0] in part1) != (g.qubits[1] in part1)}
+        if ncycles == 10:
+            assert firsts == {True, False}              # both orders occur
+        s1 = orc.zero_state(sp.n1 + sp.e)
+        for g in sp.ops1:
+            orc.apply_dense(s1, list(g.qubits), g.matrix)
+        s2 = orc.zero_state(sp.n2 + sp.e)
+        for g in sp.ops2:
+            orc.apply_dense(s2, list(g.qubits), g.matrix)
+        joint = D.contract_matrix(brute.permute_state(s1, sp.n1 + sp.e, sp.order1),
+                                  brute.permute_state(s2, sp.n2 + sp.e, sp.order2), sp.n1, sp.n2, sp.e)
+        for g in sp.rest:
+            orc.apply_dense(joint, list(g.qubits), g.matrix)
+        x = np.arange(1 << n, dtype=np.uint64)
+        got = joint[sp.joint_bits(x).astype(np.int64)]
+        assert np.abs(got - ref).max() <= 1e-9 * np.abs(ref).max()
