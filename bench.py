@@ -414,6 +414,7 @@ def bench_sliced(args) -> int:
     mask = sum(1 << q for q in sched.phases[0].sliced)
     t0 = time.perf_counter()
     st = sv.State(n, mask, "c64", tier=True, tier_dir=args.tier_dir)
+    sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(n - len(sched.phases[0].sliced)))
     t_alloc = time.perf_counter() - t0
     print(f"# tier allocated in {t_alloc:.1f} s; {len(sched.phases)} phases", file=sys.stderr,
           flush=True)

@@ -1468,7 +1468,8 @@ int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nl
         for (int p = 0; p < 64; ++p) t += in2[p];
         if (t < 9) t = 9;
         ks[cnt] = q.k;
-        if (t > stage_t || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > 80 * 1024) break;
+        if (t > stage_t || t > stage_max_t() || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > stage_lds_limit(t))
+            break;
         for (int p = 0; p < 64; ++p) in[p] = in2[p];
         ++cnt;
     }

@@ -113,9 +113,15 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // taken as zero instead of read.  *tile_mask_out: the tile's positions;
 // *amps_out: amplitudes visited.
 int stage_lds_bytes(int t, int nops, const int* ks);
+// LDS budget of a tile of t positions (80 KiB up to 13: two workgroups per
+// CU; 160 KiB at 14: one 512-lane workgroup per CU).
+int stage_lds_limit(int t);
 // Sets the staged kernels' LDS attribute for every tile width (idempotent;
 // launch_stage does it on first use, graph capture needs it beforehand).
 hipError_t stage_prepare();
+// Widest tile the device runs: 14, or 13 where a workgroup cannot have the
+// whole LDS of a CU.
+int stage_max_t();
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out, uint64_t support = ~0ull, bool garbage = false,

@@ -26,9 +26,13 @@
 namespace sv {
 
 constexpr int kStageMaxOps = 8;
-constexpr int kStageMaxT = 13;
-constexpr int kStageMaxLds = 80 * 1024;     // two workgroups per CU
-constexpr int kStageThreads = 256;          // lanes per workgroup (four waves)
+constexpr int kStageMaxT = 14;
+constexpr int kStageMaxLds = 80 * 1024;     // tiles of up to 13 positions: two 256-lane workgroups per CU
+constexpr int kStageMaxLds14 = 160 * 1024;  // 14 positions: one 512-lane workgroup per CU
+
+// LDS a tile of t positions may use, and its workgroup size
+static inline int stage_lds_limit_t(int t) { return t >= 14 ? kStageMaxLds14 : kStageMaxLds; }
+static inline int stage_threads(int t) { return t >= 14 ? 512 : 256; }
 
 struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
@@ -42,7 +46,7 @@ struct StageK {
     // zero but their memory may hold older values: tile-local index bits
     // (bit b = position P[b]) of such elements, cleared in LDS
     uint32_t newmask_t;
-    uint64_t dep_lane[8];                    // global offset of element bit b (lane bits, b < 8)
+    uint64_t dep_lane[9];                    // global offset of element bit b (lane bits: 8, or 9 at t = 14)
     uint64_t dep_i[32];                      // global offset of element bits 8.. (i = e >> 8)
     int t;
     int nops;
@@ -128,14 +132,14 @@ __device__ __forceinline__ void stage_units(const f4 (&av)[3][MfmaShape<K>::RB][
             }
 }
 
-template <int K>
+template <int K, int NT>
 __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __restrict__ As,
                                             float2* __restrict__ T, int wave)
 {
     using S = MfmaShape<K>;
     constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
     const int lane = threadIdx.x & 63;
-    constexpr int nw = kStageThreads / 64;
+    constexpr int nw = NT / 64;
     const int j = lane & 15, h = lane >> 4;
     int bit[K], low[K];
 #pragma unroll
@@ -209,9 +213,13 @@ __host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
 }
 
 template <int TW, bool WIDE, bool ZERO>
-__global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ psi, StageK a)
+__global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restrict__ psi, StageK a)
 {
-    constexpr int PER = 1 << (TW - 8);
+    // lanes NT (2^LB); element i of lane l is tile-local index l + NT i, whose
+    // LDS slot is lslot(l) + ES i
+    constexpr int NT = TW >= 14 ? 512 : 256, LB = TW >= 14 ? 9 : 8;
+    constexpr int PER = 1 << (TW - LB);
+    constexpr int ES = NT + NT / 16;
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -222,7 +230,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 2 * RB * KQ * 256;
         float* dst = (float*)(Abase) + a.op_aoff[o];
         const float2* mat = a.op_mat[o];
-        for (int i = threadIdx.x; i < NA; i += kStageThreads) {
+        for (int i = threadIdx.x; i < NA; i += NT) {
             const int s4 = i & 3, l = (i >> 2) & 63, blk = i >> 8;
             const int sq = blk % KQ, rb = (blk / KQ) % RB, p = blk / (KQ * RB);
             const int R = 16 * rb + (l & 15);
@@ -232,7 +240,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         }
     }
     uint64_t dl = 0;
-    for (int b = 0; b < 8; ++b)
+    for (int b = 0; b < LB; ++b)
         if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
     const uint32_t dlb = (uint32_t)(dl * sizeof(float2));       // used when !WIDE
     // element i of this lane in the tile at uniform index base tb
@@ -241,7 +249,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         return (float2*)((char*)(psi + (tb + a.dep_i[i])) + dlb);
     };
 
-    const int ls = lslot(threadIdx.x);                          // + lslot(256 i) = 272 i
+    const int ls = lslot(threadIdx.x);                          // + lslot(NT i) = ES i
     float2 xr[PER];
     // |0...0>: only element 0 of tile 0 (lane 0, i = 0) is non-zero
     auto load_tile = [&](uint64_t tile, uint64_t tb) {
@@ -256,7 +264,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
     };
     auto park = [&]() {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) T[ls + 272 * i] = xr[i];
+        for (int i = 0; i < PER; ++i) T[ls + ES * i] = xr[i];
     };
     double nacc = 0.0;                                           // this lane's sum of |psi|^2
     uint64_t tile = blockIdx.x;
@@ -274,7 +282,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
             // tile elements on positions no operation has reached were read
             // from memory that may hold older values: they are zero (a
             // variant of its own: the check in the loop of every pass costs)
-            for (int j = threadIdx.x; j < (1 << TW); j += kStageThreads)
+            for (int j = threadIdx.x; j < (1 << TW); j += NT)
                 if (j & a.newmask_t) T[lslot(j)] = float2{0.f, 0.f};
             __syncthreads();
         }
@@ -284,21 +292,21 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         if (next) load_tile(nt, nb);
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
-            if (a.op_k[o] == 5) stage_block<5>(a, o, As, T, wave);
-            else stage_block<4>(a, o, As, T, wave);
+            if (a.op_k[o] == 5) stage_block<5, NT>(a, o, As, T, wave);
+            else stage_block<4, NT>(a, o, As, T, wave);
             __syncthreads();
         }
         if (a.norm_out) {
 #pragma unroll
             for (int i = 0; i < PER; ++i) {
-                const float2 v = T[ls + 272 * i];
+                const float2 v = T[ls + ES * i];
                 *elem(tb, i) = v;
                 nacc = fma((double)v.x, (double)v.x, nacc);
                 nacc = fma((double)v.y, (double)v.y, nacc);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + 272 * i];
+            for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + ES * i];
         }
         __syncthreads();
         if (next) {
@@ -312,7 +320,7 @@ __global__ __launch_bounds__(kStageThreads) void k_stage(float2* __restrict__ ps
         double* sh = (double*)smem;
         sh[threadIdx.x] = nacc;
         __syncthreads();
-        for (int h = kStageThreads / 2; h > 0; h >>= 1) {
+        for (int h = NT / 2; h > 0; h >>= 1) {
             if ((int)threadIdx.x < h) sh[threadIdx.x] += sh[threadIdx.x + h];
             __syncthreads();
         }
@@ -329,7 +337,7 @@ int stage_lds_bytes(int t, int nops, const int* ks)
     return tile_f4 * 16 + floats * 4;
 }
 
-// the variant for a tile of t positions (9..13), 64-bit lane offsets, and
+// the variant for a tile of t positions (9..14), 64-bit lane offsets, and
 // clearing of stale elements
 static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
 {
@@ -343,24 +351,48 @@ static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
         SV_STAGE_CASE(11)
         SV_STAGE_CASE(12)
         SV_STAGE_CASE(13)
+        SV_STAGE_CASE(14)
     }
 #undef SV_STAGE_CASE
     return nullptr;
 }
 
+// 14-position tiles need the whole LDS of a CU for one workgroup; where the
+// device refuses that, tiles stop at 13 positions
+static std::atomic<bool> g_stage14{false};
+
 hipError_t stage_prepare()
 {
     static std::atomic<bool> done{false};
     if (done) return hipSuccess;
-    for (int t = 9; t <= kStageMaxT; ++t)
+    for (int t = 9; t <= 13; ++t)
         for (int v = 0; v < 4; ++v) {
             void (*k)(float2*, StageK) = stage_kernel(t, v & 1, v & 2);
             const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      kStageMaxLds);
             if (e != hipSuccess) return e;
         }
+    bool ok14 = true;
+    for (int v = 0; v < 4 && ok14; ++v) {
+        void (*k)(float2*, StageK) = stage_kernel(14, v & 1, v & 2);
+        ok14 = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds14) ==
+               hipSuccess;
+    }
+    if (!ok14) (void)hipGetLastError();
+    g_stage14 = ok14;
     done = true;
     return hipSuccess;
+}
+
+int stage_max_t()
+{
+    if (stage_prepare() != hipSuccess) return 13;
+    return g_stage14 ? kStageMaxT : 13;
+}
+
+int stage_lds_limit(int t)
+{
+    return stage_lds_limit_t(t);
 }
 
 // Tile positions of a staged pass, ascending, into P (returns t, or -1 when
@@ -369,11 +401,13 @@ hipError_t stage_prepare()
 // 16-group units per tile for the workgroup's four waves (8 for k = 5 at
 // t = 12), and the tile's contiguous runs are longer.  Only positions
 // inside the support widen it: one outside would double the amplitudes
-// visited (beyond the 9 the kernel needs).
+// visited (beyond the 9 the kernel needs).  Widening stops at 13: a
+// 14-position tile (one workgroup per CU) is used only when the targets
+// need it.
 static int stage_positions(int nloc, int nops, const int* ks, const int* const* pos, int t_max,
                            uint64_t support, int* P)
 {
-    if (t_max > kStageMaxT) t_max = kStageMaxT;
+    if (t_max > stage_max_t()) t_max = stage_max_t();
     if (nops < 1 || nops > kStageMaxOps) return -1;
     bool in[64] = {};
     for (int p = 0; p < 4; ++p) in[p] = true;
@@ -383,17 +417,18 @@ static int stage_positions(int nloc, int nops, const int* ks, const int* const* 
     }
     int cnt = 0;
     for (int p = 0; p < 64; ++p) cnt += in[p];
+    const int widen_to = t_max < 13 ? t_max : 13;
     for (int round = 0; round < 2; ++round)
-        for (int p = 0; p < nloc && cnt < (round ? 9 : t_max); ++p) {
+        for (int p = 0; p < nloc && cnt < (round ? 9 : widen_to); ++p) {
             if (in[p] || (round == 0 && !((support >> p) & 1))) continue;
-            if (stage_lds_bytes(cnt + 1, nops, ks) > kStageMaxLds) break;
+            if (stage_lds_bytes(cnt + 1, nops, ks) > stage_lds_limit_t(cnt + 1)) break;
             in[p] = true;
             ++cnt;
         }
     int t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;
-    if (t > t_max || t < 9 || nloc < t) return -1;
+    if (t > t_max || t < 9 || nloc < t || stage_lds_bytes(t, nops, ks) > stage_lds_limit_t(t)) return -1;
     return t;
 }
 
@@ -433,11 +468,12 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.newmask_t = 0;
     for (int b = 0; b < t; ++b)
         if ((newmask >> P[b]) & 1) a.newmask_t |= 1u << b;
-    for (int b = 0; b < 8; ++b) a.dep_lane[b] = 1ull << P[b];
-    for (int i = 0; i < (1 << (t - 8)); ++i) {
+    const int lb = t >= 14 ? 9 : 8;                             // lane bits of the tile index
+    for (int b = 0; b < lb; ++b) a.dep_lane[b] = 1ull << P[b];
+    for (int i = 0; i < (1 << (t - lb)); ++i) {
         uint64_t d = 0;
-        for (int b = 8; b < t; ++b)
-            if ((i >> (b - 8)) & 1) d |= 1ull << P[b];
+        for (int b = lb; b < t; ++b)
+            if ((i >> (b - lb)) & 1) d |= 1ull << P[b];
         a.dep_i[i] = d;
     }
     int aoff = 0;
@@ -460,10 +496,10 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
         for (int j = 0; j < ks[o]; ++j) a.op_lowmask_bits[o][j] = lb[j];
     }
     const int lds = stage_lds_bytes(t, nops, ks);
-    if (lds > kStageMaxLds) return hipErrorInvalidValue;
+    if (lds > stage_lds_limit_t(t)) return hipErrorInvalidValue;
     // byte offset of the lane part of an element address
     uint64_t dl_max = 0;
-    for (int b = 0; b < 8; ++b) dl_max |= a.dep_lane[b];
+    for (int b = 0; b < lb; ++b) dl_max |= a.dep_lane[b];
     const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
     void (*kern)(float2*, StageK) = stage_kernel(t, wide, a.newmask_t != 0);
     if (!kern) return hipErrorInvalidValue;
@@ -479,7 +515,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
     a.tstep = spread_bits(grid, a.tmask);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(kStageThreads), lds, st, (float2*)psi, a);
+    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(stage_threads(t)), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     if (norm_blocks) *norm_blocks = norm_out ? (int)grid : 0;
     if (tile_mask_out) *tile_mask_out = pmask;

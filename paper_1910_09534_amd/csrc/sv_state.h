@@ -29,8 +29,8 @@ int materialize_e0(sv_state* h);
 
 // Staged run starting at ops[i]: consecutive 4/5-qubit dense ops (none with
 // a diagonal to fold after it when fold is set) whose positions, with
-// positions 0..3, fit a tile of at most stage_t (and nloc) positions within
-// the LDS budget, at most kStageRunMax ops.  Returns the op count (0 when
+// positions 0..3, fit a tile of at most stage_t (and nloc, and the device's
+// widest) positions within the LDS budget, at most kStageRunMax ops.  Returns the op count (0 when
 // ops[i] cannot start one) and their widths in ks.
 constexpr int kStageRunMax = 8;
 int form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks);

@@ -254,18 +254,34 @@ def fuse_grow(gates, kmax: int, window: int = 4, last_gain: float = 0.0) -> List
 # Staged-pass formation on the device (mirrored here for planning): a run
 # holds at most STAGE_MAX_OPS 4/5-qubit blocks, the tile at most STAGE_T
 # positions (0..3 always), and the LDS budget covers the tile (2^t complex64
-# plus one pad per 16) and Re/Im of every block's matrix.
-STAGE_T = 13
+# plus one pad per 16) and Re/Im of every block's matrix: STAGE_LDS up to
+# 13 positions (two workgroups per CU), STAGE_LDS14 at 14 (one 512-lane
+# workgroup per CU).  Tiles are widened to 13 positions at most; 14 only
+# when a run's targets need them.
+STAGE_T = 14
 STAGE_MAX_OPS = 8
 STAGE_LDS = 80 * 1024
+STAGE_LDS14 = 160 * 1024
+
+
+def _lds_limit(t: int) -> int:
+    return STAGE_LDS14 if t >= 14 else STAGE_LDS
+
+
+# Widest tile for states of more than 2^STAGE_WIDE_MAX_N amplitudes: 14
+# positions (fewer passes) measured faster for states of up to 2^28
+# amplitudes (batches of 20-28 qubits: 311 against 289 circuits/s) and
+# slower at 2^30 (47.8 against 47.4 ms per 30-qubit step), where the
+# 13-position tiles with two workgroups per CU overlap better.
+STAGE_WIDE_MAX_N = 28
 
 
 def stage_tmax(nloc: int) -> int:
     """Tile limit for a state of 2^nloc amplitudes: at most nloc - 9
     positions, so that a pass has at least 512 tiles (two workgroups per
-    CU); 0 (no staged passes) below 9.  Callers pass it to the device as
-    SV_OPT_STAGE for the state."""
-    t = min(STAGE_T, nloc - 9)
+    CU), 14 up to 2^28 amplitudes and 13 above; 0 (no staged passes) below
+    9.  Callers pass it to the device as SV_OPT_STAGE for the state."""
+    t = min(STAGE_T if nloc <= STAGE_WIDE_MAX_N else 13, nloc - 9)
     return t if t >= 9 else 0
 
 
@@ -280,7 +296,7 @@ def _stageable(o: "Op") -> bool:
 
 def _fits(pos: set, ks: Sequence[int], tmax: int) -> bool:
     t = max(9, len(pos))
-    return t <= tmax and len(ks) <= STAGE_MAX_OPS and _stage_lds(t, ks) <= STAGE_LDS
+    return t <= tmax and len(ks) <= STAGE_MAX_OPS and _stage_lds(t, ks) <= _lds_limit(t)
 
 
 def stage_runs(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) -> List[List[int]]:
@@ -426,11 +442,11 @@ def sparse_passes(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[in
         t = bin(P).count("1")
         for rnd in (0, 1):
             for p_ in range(nloc):
-                if t >= (9 if rnd else tmax):
+                if t >= (9 if rnd else min(tmax, 13)):
                     break
                 if (P >> p_) & 1 or (rnd == 0 and not (S >> p_) & 1):
                     continue
-                if _stage_lds(t + 1, ks) > STAGE_LDS:
+                if _stage_lds(t + 1, ks) > _lds_limit(t + 1):
                     break
                 P |= 1 << p_
                 t += 1

@@ -73,6 +73,8 @@ def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: 
     n = circuit.n
     mask = sum(1 << q for q in sched.phases[0].sliced)
     st = sv.State(n, mask, dtype, tier=tier, pageable=pageable, tier_dir=tier_dir)
+    if dtype == "c64":   # the phases were planned for this tile limit
+        sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(n - len(sched.phases[0].sliced)))
     try:
         if timing:
             sv.set_option(st.h, sv.SV_OPT_TIMING, 1)

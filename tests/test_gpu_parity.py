@@ -269,7 +269,8 @@ def test_staged_multiblock_pass(n):
     assert orc.rel_l2(outs[12], outs[0]) <= 1e-6
 
 
-@pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12), (13, 13), (19, 13)])
+@pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12), (13, 13), (19, 13),
+                                    (14, 14), (21, 14)])
 def test_staged_pass_any_positions(n, tmax):
     """Staged passes over blocks whose targets lie anywhere (no position
     limit), with tiles widened to the largest width allowed: equal to one
@@ -464,7 +465,7 @@ def test_sparse_support_follows_permutes(reset):
     assert orc.rel_l2(got, ref) <= 1e-5
 
 
-@pytest.mark.parametrize("n,depth", [(20, 12), (22, 10)])
+@pytest.mark.parametrize("n,depth", [(20, 12), (22, 10), (24, 10)])
 def test_sparse_start_plan_visits_as_modelled(n, depth):
     """A circuit planned for a run from |0...0> after sv_reset: the state
     equals the oracle's, and the amplitudes the passes visit equal the
