@@ -95,7 +95,8 @@ int create_state(int n, uint64_t slice_mask, int dtype, void* hip_stream, sv_han
  * e.g. a torch tensor), which the handle neither frees nor reallocates.
  * The buffer is initialised to |0...0> unless dtype has SV_FLAG_KEEP set, in
  * which case its current contents (in the initial layout) are the state.
- * All slices are resident.  Errors: SV_EINVAL (buffer NULL or too small).
+ * All slices are resident.  Errors: SV_EINVAL (buffer NULL, too small or
+ * not 16-byte aligned).
  */
 enum { SV_FLAG_KEEP = 0x200 };
 int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream,

@@ -807,6 +807,7 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
     if (ext) {
         if (tier) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer cannot be tiered"); }
         if (ext_bytes < total) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer too small"); }
+        if ((uintptr_t)ext & 15) { release(h); return set_err(nullptr, SV_EINVAL, "external buffer not 16-byte aligned"); }
         h->dev = ext;
         h->dev_bytes = ext_bytes;
     } else if (!tier) {

@@ -9,7 +9,9 @@
 // positions P[0] < ... < P[t-1] (P[0..3] = 0..3; free low positions widen
 // the tile to 13 when the LDS budget allows).  A tile is the 2^t amplitudes whose other bits equal the
 // tile id.  A persistent workgroup (256 lanes) loops over tiles:
-//   1. the next tile's loads are issued (into registers);
+//   1. the next tile's loads are issued (into registers; each lane holds
+//      pairs of adjacent amplitudes, 16 bytes per access: position 0 is
+//      always a tile position);
 //   2. each block runs on the LDS tile: pairs of 16-group units per wave
 //      through the three real products of the matrix-core form
 //      (v_mfma_f32_16x16x4f32, same operand layout as the single sweep),
@@ -215,11 +217,9 @@ __host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
 template <int TW, bool WIDE, bool ZERO>
 __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restrict__ psi, StageK a)
 {
-    // lanes NT (2^LB); element i of lane l is tile-local index l + NT i, whose
-    // LDS slot is lslot(l) + ES i
+    // lanes NT (2^LB), PER amplitudes per lane in PER / 2 adjacent pairs
     constexpr int NT = TW >= 14 ? 512 : 256, LB = TW >= 14 ? 9 : 8;
     constexpr int PER = 1 << (TW - LB);
-    constexpr int ES = NT + NT / 16;
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -239,32 +239,36 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
             dst[i] = p == 0 ? m.x : m.y;
         }
     }
+    // element pair m of lane l: tile-local indices (l << 1) + 2 NT m + {0, 1}
+    // (tile bit 0 is position 0: the pair is two adjacent amplitudes, one
+    // 16-byte access); their LDS slots are lslot(2 l) + ES2 m + {0, 1}
+    constexpr int PP = PER / 2, ES2 = 2 * NT + (2 * NT) / 16;
     uint64_t dl = 0;
     for (int b = 0; b < LB; ++b)
         if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
     const uint32_t dlb = (uint32_t)(dl * sizeof(float2));       // used when !WIDE
-    // element i of this lane in the tile at uniform index base tb
-    auto elem = [&](uint64_t tb, int i) -> float2* {
-        if (WIDE) return psi + (tb + dl + a.dep_i[i]);
-        return (float2*)((char*)(psi + (tb + a.dep_i[i])) + dlb);
+    auto elem = [&](uint64_t tb, int m) -> float4* {
+        if (WIDE) return (float4*)(psi + (tb + dl + a.dep_i[m]));
+        return (float4*)((char*)(psi + (tb + a.dep_i[m])) + dlb);
     };
-
-    const int ls = lslot(threadIdx.x);                          // + lslot(NT i) = ES i
-    float2 xr[PER];
-    // |0...0>: only element 0 of tile 0 (lane 0, i = 0) is non-zero
+    const int ls = lslot(2 * threadIdx.x);
+    float4 xr[PP];
     auto load_tile = [&](uint64_t tile, uint64_t tb) {
         if (a.from_e0) {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) xr[i] = float2{0.f, 0.f};
+            for (int m = 0; m < PP; ++m) xr[m] = float4{0.f, 0.f, 0.f, 0.f};
             if (tile == 0 && threadIdx.x == 0) xr[0].x = 1.f;
         } else {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) xr[i] = *elem(tb, i);
+            for (int m = 0; m < PP; ++m) xr[m] = *elem(tb, m);
         }
     };
     auto park = [&]() {
 #pragma unroll
-        for (int i = 0; i < PER; ++i) T[ls + ES * i] = xr[i];
+        for (int m = 0; m < PP; ++m) {
+            T[ls + ES2 * m] = float2{xr[m].x, xr[m].y};
+            T[ls + ES2 * m + 1] = float2{xr[m].z, xr[m].w};
+        }
     };
     double nacc = 0.0;                                           // this lane's sum of |psi|^2
     uint64_t tile = blockIdx.x;
@@ -298,15 +302,20 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
         }
         if (a.norm_out) {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) {
-                const float2 v = T[ls + ES * i];
-                *elem(tb, i) = v;
-                nacc = fma((double)v.x, (double)v.x, nacc);
-                nacc = fma((double)v.y, (double)v.y, nacc);
+            for (int m = 0; m < PP; ++m) {
+                const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
+                *elem(tb, m) = float4{v0.x, v0.y, v1.x, v1.y};
+                nacc = fma((double)v0.x, (double)v0.x, nacc);
+                nacc = fma((double)v0.y, (double)v0.y, nacc);
+                nacc = fma((double)v1.x, (double)v1.x, nacc);
+                nacc = fma((double)v1.y, (double)v1.y, nacc);
             }
         } else {
 #pragma unroll
-            for (int i = 0; i < PER; ++i) *elem(tb, i) = T[ls + ES * i];
+            for (int m = 0; m < PP; ++m) {
+                const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
+                *elem(tb, m) = float4{v0.x, v0.y, v1.x, v1.y};
+            }
         }
         __syncthreads();
         if (next) {
@@ -469,11 +478,13 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     for (int b = 0; b < t; ++b)
         if ((newmask >> P[b]) & 1) a.newmask_t |= 1u << b;
     const int lb = t >= 14 ? 9 : 8;                             // lane bits of the tile index
-    for (int b = 0; b < lb; ++b) a.dep_lane[b] = 1ull << P[b];
-    for (int i = 0; i < (1 << (t - lb)); ++i) {
+    // tile bit 0 (position 0) pairs adjacent amplitudes; lane bit b is tile
+    // bit b + 1; pair index bit c is tile bit lb + 1 + c
+    for (int b = 0; b < lb; ++b) a.dep_lane[b] = 1ull << P[b + 1];
+    for (int i = 0; i < (1 << (t - lb - 1)); ++i) {
         uint64_t d = 0;
-        for (int b = lb; b < t; ++b)
-            if ((i >> (b - lb)) & 1) d |= 1ull << P[b];
+        for (int b = lb + 1; b < t; ++b)
+            if ((i >> (b - lb - 1)) & 1) d |= 1ull << P[b];
         a.dep_i[i] = d;
     }
     int aoff = 0;

@@ -213,6 +213,18 @@ def test_sliced_resident_reduce_with_trailing():
     assert orc.rel_l2(gath, psi[bits.astype(np.int64)]) <= 1e-12
 
 
+def test_external_buffer_alignment():
+    """An external state buffer must be 16-byte aligned (staged passes move
+    pairs of adjacent amplitudes with 16-byte accesses)."""
+    torch = _torch()
+    t = torch.zeros((1 << 10) + 2, dtype=torch.complex64, device="cuda")
+    with pytest.raises(sv.SVError) as e:
+        sv.create_state_ext(10, 0, "c64", None, t.data_ptr() + 8, (1 << 10) * 8)
+    assert e.value.code == sv.SV_EINVAL
+    h = sv.create_state_ext(10, 0, "c64", None, t.data_ptr() + 16, (1 << 10) * 8)
+    sv.destroy_state(h)
+
+
 def test_dense_on_sliced_qubit_rejected():
     _torch()
     h = sv.create_state(8, 1 << 3, "c64")
