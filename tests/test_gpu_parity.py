@@ -534,3 +534,42 @@ def test_norm_folded_into_last_staged_pass(last):
             assert sv.counters(h)["staged_blocks"] >= 2
     finally:
         sv.destroy_state(h)
+
+
+def test_headline_configuration_full_size():
+    """The 30-qubit depth-14 workload in the launch configuration the
+    benchmark times (resident complex64 state in a torch buffer, sv_reset,
+    the plan for a run from |0...0>, staged passes, FP64 reduction of 2^16
+    bitstrings), checked by properties that hold at any size: the norm is 1,
+    the Porter-Thomas moments of the sampled probabilities (mean N p = 1,
+    mean (N p)^2 = 2), two steps are bitwise identical, and the circuit
+    followed by its inverse returns |0...0>."""
+    torch = _torch()
+    from paper_1910_09534_amd import planner
+    circ = W.config_circuit(2)
+    bits = W.config_bitstrings(2)
+    n = circ.n
+    ops = planner.plan(circ.gates, 5, sparse_start=True)
+    inv = [W.Gate(g.qubits, np.conj(g.matrix).T) for g in reversed(circ.gates)]
+    inv_ops = planner.plan(inv, 5)
+    buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
+    h = sv.create_state_ext(n, 0, "c64", None, buf.data_ptr(), buf.numel() * 8)
+    try:
+        outs = []
+        for _ in range(2):
+            sv.reset(h)
+            planner.enqueue(h, ops, sv.SV_C64)
+            amps, stats = sv.reduce_slices(h, bits)
+            outs.append(amps)
+        assert np.array_equal(outs[0], outs[1])
+        assert abs(stats[0] - 1.0) <= 1e-5
+        p = (np.abs(outs[0]) ** 2) * float(1 << n)
+        assert abs(p.mean() - 1.0) <= 0.03
+        assert abs((p ** 2).mean() - 2.0) <= 0.2
+        planner.enqueue(h, inv_ops, sv.SV_C64)          # U^-1 U |0...0>
+        back = sv.gather_amplitudes(h, np.array([0, 1, 12345, (1 << n) - 1], dtype=np.uint64))
+        assert abs(abs(back[0]) - 1.0) <= 1e-4
+        assert np.abs(back[1:]).max() <= 1e-4
+    finally:
+        sv.destroy_state(h)
+        del buf
