@@ -144,7 +144,10 @@ int apply_diag(sv_handle h, int m, const int* qubits, const void* phases);
  * all2all rows give the new index order).  order[p] = logical qubit placed
  * at physical position p (p = 0 least significant); the top s positions
  * become the sliced qubits.  Flushes queued work.  Results of later calls
- * are unaffected (operations address logical qubits).
+ * are unaffected (operations address logical qubits).  A resident state
+ * that is still |0...0> with nothing queued (after sv_reset, or created and
+ * not yet operated on) only takes the new layout: no data moves.  Choosing
+ * the layout there decides which positions the first operations touch.
  * Errors: SV_EINVAL (not a permutation), SV_ENOMEM (no room for the
  * re-arrangement), SV_EDEVICE / SV_EIO (handle poisoned).
  */

@@ -1174,6 +1174,15 @@ int permute_qubits(sv_handle h, const int* order)
     for (int q = 0; q < h->n; ++q) same = same && (npos[q] == h->pos[q]);
     if (same) return SV_OK;
 
+    // |0...0> is the same in every layout: a resident state that is still
+    // |0...0> (reset, or no operation since it was created as |0...0>) only
+    // takes the new layout
+    if (!h->tier && h->ops.empty() && (h->e0_pending || h->support == 0)) {
+        h->pos = npos;
+        for (int p = 0; p < h->n; ++p) h->order[p] = order[p];
+        return SV_OK;
+    }
+
     if (!h->tier) {
         int rc = flush(h);
         if (rc) return rc;

@@ -477,6 +477,39 @@ def test_sparse_support_follows_permutes(reset):
     assert orc.rel_l2(got, ref) <= 1e-5
 
 
+@pytest.mark.parametrize("when", ["fresh", "reset", "reset-twice"])
+def test_permute_of_zero_state_is_a_relabel(when):
+    """A permute of a resident |0...0> with nothing queued moves no data (no
+    permute sweep is counted) but takes the new layout: later operations,
+    gathers and a second permute see the qubits where the layout put them.
+    "reset" leaves stale values in the buffer, which must not show."""
+    n = 18
+    rng = np.random.default_rng(90 + len(when))
+    U = lambda k: W.random_unitary(1 << k, rng)
+    st = sv.State(n, 0, "c64")
+    try:
+        if when != "fresh":
+            st.fused([0, 1, 2, 3, 4], U(5).astype(np.complex64))
+            st.sync()
+            sv.reset(st.h)
+        p0 = sv.counters(st.h)["perm_sweeps"]
+        st.permute([int(x) for x in rng.permutation(n)])
+        if when == "reset-twice":
+            st.permute(list(range(n))[::-1])
+        assert sv.counters(st.h)["perm_sweeps"] == p0
+        ref = orc.zero_state(n)
+        for qs, k in (([3, 9, 14, 17], 4), ([0, 1, 2, 3, 4], 5), ([9, 10, 11, 12], 4)):
+            m = U(k)
+            st.fused(qs, m.astype(np.complex64))
+            orc.apply_dense(ref, qs, m)
+        st.permute(list(range(n)))           # the state is no longer |0...0>: data moves
+        assert sv.counters(st.h)["perm_sweeps"] == p0 + 1
+        got = st.gather(np.arange(1 << n, dtype=np.uint64))
+    finally:
+        st.close()
+    assert orc.rel_l2(got, ref) <= 1e-5
+
+
 @pytest.mark.parametrize("n,depth", [(20, 12), (22, 10), (24, 10)])
 def test_sparse_start_plan_visits_as_modelled(n, depth):
     """A circuit planned for a run from |0...0> after sv_reset: the state
