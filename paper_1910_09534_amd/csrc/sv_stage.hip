@@ -260,7 +260,10 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
             if (tile == 0 && threadIdx.x == 0) xr[0].x = 1.f;
         } else {
 #pragma unroll
-            for (int m = 0; m < PP; ++m) xr[m] = *elem(tb, m);
+            for (int m = 0; m < PP; ++m) {
+                const f4 v = __builtin_nontemporal_load((const f4*)elem(tb, m));
+                xr[m] = float4{v.x, v.y, v.z, v.w};
+            }
         }
     };
     auto park = [&]() {
@@ -281,6 +284,10 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
     // Per tile: issue the next tile's loads, run the blocks on the LDS tile,
     // store it, then park the next tile.  Its loads precede this tile's
     // stores, so parking waits for the loads only, never for the stores.
+    // The state streams through once per pass: its loads and stores are
+    // non-temporal, and the waves raise their issue priority while they
+    // issue them, so that the memory requests of one workgroup go out ahead
+    // of the matrix-core work of the other on the same CU.
     for (; tile < a.tiles; tile += gridDim.x) {
         if (ZERO) {
             // tile elements on positions no operation has reached were read
@@ -293,18 +300,21 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
         const uint64_t nt = tile + gridDim.x;
         const uint64_t nb = ((tb | ~a.tmask) + a.tstep) & a.tmask;
         const bool next = nt < a.tiles;
+        __builtin_amdgcn_s_setprio(1);
         if (next) load_tile(nt, nb);
+        __builtin_amdgcn_s_setprio(0);
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
             if (a.op_k[o] == 5) stage_block<5, NT>(a, o, As, T, wave);
             else stage_block<4, NT>(a, o, As, T, wave);
             __syncthreads();
         }
+        __builtin_amdgcn_s_setprio(1);
         if (a.norm_out) {
 #pragma unroll
             for (int m = 0; m < PP; ++m) {
                 const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
-                *elem(tb, m) = float4{v0.x, v0.y, v1.x, v1.y};
+                __builtin_nontemporal_store(f4{v0.x, v0.y, v1.x, v1.y}, (f4*)elem(tb, m));
                 nacc = fma((double)v0.x, (double)v0.x, nacc);
                 nacc = fma((double)v0.y, (double)v0.y, nacc);
                 nacc = fma((double)v1.x, (double)v1.x, nacc);
@@ -314,13 +324,14 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
 #pragma unroll
             for (int m = 0; m < PP; ++m) {
                 const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
-                *elem(tb, m) = float4{v0.x, v0.y, v1.x, v1.y};
+                __builtin_nontemporal_store(f4{v0.x, v0.y, v1.x, v1.y}, (f4*)elem(tb, m));
             }
         }
         __syncthreads();
         if (next) {
             park();
         }
+        __builtin_amdgcn_s_setprio(0);
         __syncthreads();
         tb = nb;
     }
