@@ -213,7 +213,8 @@ enum {
                               run of consecutive 4/5-qubit complex64 blocks in one pass
                               over HBM (14: one 512-lane workgroup per CU holding the
                               whole LDS, used only when a run's targets need 14
-                              positions); 0: one pass per block */
+                              positions); 0: one pass per block; other values:
+                              SV_EINVAL */
     SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer
                               from now on (n >= 1) is not issued and reports SV_EIO,
                               poisoning the handle; 0 (default): off */

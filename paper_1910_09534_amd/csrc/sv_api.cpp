@@ -1376,10 +1376,17 @@ int sv_set_option(sv_handle h, int option, int64_t value)
     CHECK_HANDLE(h);
     switch (option) {
         case SV_OPT_TIMING: h->timing = value != 0; return SV_OK;
-        case SV_OPT_MFMA: h->mfma_min_k = (int)value; return SV_OK;
+        case SV_OPT_MFMA:
+            if (value < 0 || value > 64) return set_err(h, SV_EINVAL, "SV_OPT_MFMA: k out of range");
+            h->mfma_min_k = (int)value;
+            return SV_OK;
         case SV_OPT_FOLD_DIAG: h->fold = value != 0; return SV_OK;
         case SV_OPT_SLOTS: return set_err(h, SV_EINVAL, "slot count is fixed at creation");
-        case SV_OPT_STAGE: h->stage_t = (int)value; return SV_OK;
+        case SV_OPT_STAGE:
+            if (value != 0 && (value < 9 || value > 14))
+                return set_err(h, SV_EINVAL, "SV_OPT_STAGE: 0 or 9..14 positions");
+            h->stage_t = (int)value;
+            return SV_OK;
         case SV_OPT_FAIL_IO: h->fail_io_at = value; return SV_OK;
         case SV_OPT_SPARSE_START: h->sparse_start = value != 0; return SV_OK;
     }

@@ -87,7 +87,7 @@ struct sv_state {
     // options and accounting
     bool timing = false, fold = true;
     int mfma_min_k = 4;
-    int stage_t = 13;
+    int stage_t = 13;            // widest tile of staged multi-block passes (0: off)
     bool e0_pending = false;     // resident state is |0...0> but not yet written (sv_reset)
     // Resident states after sv_reset: every amplitude whose index has a bit
     // outside `support` is zero (the positions no operation has touched since
@@ -96,7 +96,7 @@ struct sv_state {
     uint64_t support = ~0ull;
     bool garbage = false;
     bool sparse_start = true;
-    int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO                     // max tile width of staged multi-block sweeps (0: off)
+    int64_t fail_io_at = 0;               // failure injection: remaining transfers before a forced SV_EIO
     int nslots = 3;
     std::vector<hipEvent_t> tev_pool;
     struct TimedLaunch {

@@ -242,6 +242,13 @@ def test_dense_on_sliced_qubit_rejected():
         with pytest.raises(sv.SVError) as e:
             sv.gather_amplitudes(h, np.array([256], dtype=np.uint64))
         assert e.value.code == sv.SV_EINVAL
+        for opt, bad in ((sv.SV_OPT_STAGE, 8), (sv.SV_OPT_STAGE, 15), (sv.SV_OPT_STAGE, -1),
+                         (sv.SV_OPT_MFMA, -1), (99, 1)):
+            with pytest.raises(sv.SVError) as e:
+                sv.set_option(h, opt, bad)
+            assert e.value.code == sv.SV_EINVAL
+        for good in (0, 9, 14):
+            sv.set_option(h, sv.SV_OPT_STAGE, good)
         a = sv.gather_amplitudes(h, np.array([0, 1], dtype=np.uint64))
         assert abs(a[0] - 1) == 0 and a[1] == 0
     finally:
