@@ -25,6 +25,8 @@
 
 #include "sv_device.h"
 
+#include <type_traits>
+
 namespace sv {
 
 constexpr int kStageMaxOps = 8;
@@ -282,8 +284,7 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
     }
     __syncthreads();
     // Per tile: issue the next tile's loads, run the blocks on the LDS tile,
-    // store it, then park the next tile.  Its loads precede this tile's
-    // stores, so parking waits for the loads only, never for the stores.
+    // then store it while parking the next tile in its place.
     // The state streams through once per pass: its loads and stores are
     // non-temporal, and the waves raise their issue priority while they
     // issue them, so that the memory requests of one workgroup go out ahead
@@ -309,27 +310,35 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
             else stage_block<4, NT>(a, o, As, T, wave);
             __syncthreads();
         }
+        // Each lane parks the next tile's pairs in the very slots it has just
+        // read for its stores (no other lane touches them), pair by pair, so
+        // the wait for a pair's load never covers the stores issued before it.
         __builtin_amdgcn_s_setprio(1);
-        if (a.norm_out) {
+        auto store_park = [&](auto park_next, auto sum_norm) {
 #pragma unroll
             for (int m = 0; m < PP; ++m) {
                 const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
+                if constexpr (decltype(park_next)::value) {
+                    T[ls + ES2 * m] = float2{xr[m].x, xr[m].y};
+                    T[ls + ES2 * m + 1] = float2{xr[m].z, xr[m].w};
+                }
                 __builtin_nontemporal_store(f4{v0.x, v0.y, v1.x, v1.y}, (f4*)elem(tb, m));
-                nacc = fma((double)v0.x, (double)v0.x, nacc);
-                nacc = fma((double)v0.y, (double)v0.y, nacc);
-                nacc = fma((double)v1.x, (double)v1.x, nacc);
-                nacc = fma((double)v1.y, (double)v1.y, nacc);
+                if constexpr (decltype(sum_norm)::value) {
+                    nacc = fma((double)v0.x, (double)v0.x, nacc);
+                    nacc = fma((double)v0.y, (double)v0.y, nacc);
+                    nacc = fma((double)v1.x, (double)v1.x, nacc);
+                    nacc = fma((double)v1.y, (double)v1.y, nacc);
+                }
             }
-        } else {
-#pragma unroll
-            for (int m = 0; m < PP; ++m) {
-                const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
-                __builtin_nontemporal_store(f4{v0.x, v0.y, v1.x, v1.y}, (f4*)elem(tb, m));
-            }
-        }
-        __syncthreads();
+        };
+        using yes = std::true_type;
+        using no = std::false_type;
         if (next) {
-            park();
+            if (a.norm_out) store_park(yes{}, yes{});
+            else store_park(yes{}, no{});
+        } else {
+            if (a.norm_out) store_park(no{}, yes{});
+            else store_park(no{}, no{});
         }
         __builtin_amdgcn_s_setprio(0);
         __syncthreads();
