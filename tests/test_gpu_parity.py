@@ -545,13 +545,14 @@ def test_sparse_start_plan_visits_as_modelled(n, depth):
         sv.destroy_state(h)
 
 
-@pytest.mark.parametrize("last", ["staged", "single", "single-dense"])
-def test_norm_folded_into_last_staged_pass(last):
+@pytest.mark.parametrize("last,n", [("staged", 15), ("single", 15), ("single-dense", 15), ("staged", 23)])
+def test_norm_folded_into_last_staged_pass(last, n):
     """When the queue ends with a staged pass, that pass also sums |psi|^2
     (FP64, per workgroup) and the reduction uses those sums; the norm and
-    the amplitudes equal the oracle's either way."""
-    n = 15
-    rng = np.random.default_rng({"staged": 21, "single": 22, "single-dense": 23}[last])
+    the amplitudes equal the oracle's either way.  At 23 qubits every
+    workgroup takes two tiles (the second parked while the first is
+    stored)."""
+    rng = np.random.default_rng({"staged": 21, "single": 22, "single-dense": 23}[last] + n)
     psi = W.random_state(n, rng)
     h, t = state_from_numpy(psi, "c64")
     ops = [([4, 5, 6, 7, 8], W.random_unitary(32, rng)), ([6, 7, 8, 9], W.random_unitary(16, rng)),
