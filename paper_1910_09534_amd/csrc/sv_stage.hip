@@ -268,11 +268,24 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
             }
         }
     };
+    // pair m as parked: with ZERO, elements on positions no operation has
+    // reached are zero (memory there may hold older values)
+    auto parked = [&](int m, float2& e0, float2& e1) {
+        e0 = float2{xr[m].x, xr[m].y};
+        e1 = float2{xr[m].z, xr[m].w};
+        if (ZERO) {
+            const uint32_t pi = (uint32_t)((threadIdx.x << 1) + 2 * NT * m);
+            if (pi & a.newmask_t) e0 = float2{0.f, 0.f};
+            if ((pi | 1u) & a.newmask_t) e1 = float2{0.f, 0.f};
+        }
+    };
     auto park = [&]() {
 #pragma unroll
         for (int m = 0; m < PP; ++m) {
-            T[ls + ES2 * m] = float2{xr[m].x, xr[m].y};
-            T[ls + ES2 * m + 1] = float2{xr[m].z, xr[m].w};
+            float2 e0, e1;
+            parked(m, e0, e1);
+            T[ls + ES2 * m] = e0;
+            T[ls + ES2 * m + 1] = e1;
         }
     };
     double nacc = 0.0;                                           // this lane's sum of |psi|^2
@@ -290,14 +303,6 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
     // issue them, so that the memory requests of one workgroup go out ahead
     // of the matrix-core work of the other on the same CU.
     for (; tile < a.tiles; tile += gridDim.x) {
-        if (ZERO) {
-            // tile elements on positions no operation has reached were read
-            // from memory that may hold older values: they are zero (a
-            // variant of its own: the check in the loop of every pass costs)
-            for (int j = threadIdx.x; j < (1 << TW); j += NT)
-                if (j & a.newmask_t) T[lslot(j)] = float2{0.f, 0.f};
-            __syncthreads();
-        }
         const uint64_t nt = tile + gridDim.x;
         const uint64_t nb = ((tb | ~a.tmask) + a.tstep) & a.tmask;
         const bool next = nt < a.tiles;
@@ -319,8 +324,10 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
             for (int m = 0; m < PP; ++m) {
                 const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
                 if constexpr (decltype(park_next)::value) {
-                    T[ls + ES2 * m] = float2{xr[m].x, xr[m].y};
-                    T[ls + ES2 * m + 1] = float2{xr[m].z, xr[m].w};
+                    float2 e0, e1;
+                    parked(m, e0, e1);
+                    T[ls + ES2 * m] = e0;
+                    T[ls + ES2 * m + 1] = e1;
                 }
                 __builtin_nontemporal_store(f4{v0.x, v0.y, v1.x, v1.y}, (f4*)elem(tb, m));
                 if constexpr (decltype(sum_norm)::value) {
