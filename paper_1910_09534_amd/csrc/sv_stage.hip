@@ -48,7 +48,7 @@ struct StageK {
     uint64_t tstep;
     // amplitudes on tile positions no earlier operation has reached are
     // zero but their memory may hold older values: tile-local index bits
-    // (bit b = position P[b]) of such elements, cleared in LDS
+    // (bit b = position P[b]) of such elements, parked in LDS as zeros
     uint32_t newmask_t;
     uint64_t dep_lane[9];                    // global offset of element bit b (lane bits: 8, or 9 at t = 14)
     uint64_t dep_i[32];                      // global offset of element bits 8.. (i = e >> 8)
@@ -374,7 +374,7 @@ int stage_lds_bytes(int t, int nops, const int* ks)
 }
 
 // the variant for a tile of t positions (9..14), 64-bit lane offsets, and
-// clearing of stale elements
+// zeroing of stale elements
 static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
 {
 #define SV_STAGE_CASE(T)                                                     \
