@@ -520,18 +520,18 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
         a.op_mat[o] = (const float2*)mats[o];
         a.op_aoff[o] = aoff;
         aoff += 2 * (1 << (2 * ks[o]));
-        int lb[kMaxDense];
+        int tbit[kMaxDense];
         for (int j = 0; j < ks[o]; ++j) {
             int b = 0;
             while (P[b] != pos[o][j]) ++b;
             a.op_bits[o][j] = b;
-            lb[j] = b;
+            tbit[j] = b;
         }
         for (int j = 1; j < ks[o]; ++j)
-            for (int l = j; l > 0 && lb[l - 1] > lb[l]; --l) {
-                const int tmp = lb[l]; lb[l] = lb[l - 1]; lb[l - 1] = tmp;
+            for (int l = j; l > 0 && tbit[l - 1] > tbit[l]; --l) {
+                const int tmp = tbit[l]; tbit[l] = tbit[l - 1]; tbit[l - 1] = tmp;
             }
-        for (int j = 0; j < ks[o]; ++j) a.op_lowmask_bits[o][j] = lb[j];
+        for (int j = 0; j < ks[o]; ++j) a.op_lowmask_bits[o][j] = tbit[j];
     }
     const int lds = stage_lds_bytes(t, nops, ks);
     if (lds > stage_lds_limit_t(t)) return hipErrorInvalidValue;
