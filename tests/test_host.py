@@ -90,6 +90,21 @@ def test_cfg2_plan_counts():
     assert st["dense"] <= 40
 
 
+def test_cfg2_sparse_plan_shape():
+    """Regression pin on the 30-qubit depth-14 plan that the benchmark runs
+    from |0...0>: every gate once, at most 17 HBM passes, and the passes
+    visit at most 63 % of what as many full passes would (the device's
+    visit counter is checked against this model in a GPU test)."""
+    c = W.config_circuit(2)
+    tmax = planner.stage_tmax(c.n)
+    ops = planner.plan(c.gates, 5, sparse_start=True)
+    assert sum(o.ngates for o in ops) == 621
+    passes = planner.sparse_passes(ops, c.n, None, tmax)
+    assert len(passes) <= 17
+    visited = sum(1 << lv for _, lv in passes) / (len(passes) * (1 << c.n))
+    assert visited <= 0.63
+
+
 def _declared_functions():
     names = []
     for f in os.listdir(os.path.join(ROOT, "include")):
