@@ -95,6 +95,10 @@ def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: 
         st.close()
 
 
+# host threads issuing the per-state reductions after a batch
+REDUCE_THREADS = 8
+
+
 def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: bool = True,
               repeats: int = 1, plans=None, staged: bool = False) -> Dict[str, object]:
     """Many independent circuits as one batched execution (one graph launch
@@ -126,16 +130,22 @@ def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: boo
         times = []
         outs = None
         import torch
-        for rep in range(repeats):
-            # from a reset every state starts as |0...0> unwritten: the batch
-            # then runs its reset variant (no fill ahead, sparse first passes)
-            for st in states:
-                sv.reset(st.h)
-            torch.cuda.synchronize()
-            t1 = time.perf_counter()
-            sv.batch_launch(b)
-            outs = [sv.reduce_slices(st.h, bits) for st, bits in zip(states, bits_list)]
-            times.append(time.perf_counter() - t1)
+        from concurrent.futures import ThreadPoolExecutor
+        # the per-state reductions run from a few host threads: each call
+        # waits for its own results, and the library takes calls on
+        # different states concurrently (their streams are independent)
+        with ThreadPoolExecutor(max_workers=REDUCE_THREADS) as pool:
+            list(pool.map(lambda _: None, range(REDUCE_THREADS)))      # start the threads
+            for rep in range(repeats):
+                # from a reset every state starts as |0...0> unwritten: the batch
+                # then runs its reset variant (no fill ahead, sparse first passes)
+                for st in states:
+                    sv.reset(st.h)
+                torch.cuda.synchronize()
+                t1 = time.perf_counter()
+                sv.batch_launch(b)
+                outs = list(pool.map(lambda sb: sv.reduce_slices(sb[0].h, sb[1]), zip(states, bits_list)))
+                times.append(time.perf_counter() - t1)
         info = sv.batch_info(b)
         return {"amps": [o[0] for o in outs], "stats": [o[1] for o in outs], "times": times,
                 "t_plan": t_plan, "info": info,
