@@ -480,7 +480,6 @@ def bench_sliced(args) -> int:
 def bench_batch(args) -> int:
     """256 independent circuits, one graph-captured batch per step."""
     import torch
-    from oracle import oracle as orc
     from paper_1910_09534_amd import autotune, planner, runner, sv
     from paper_1910_09534_amd import workload as W
 
@@ -522,14 +521,7 @@ def bench_batch(args) -> int:
         r = runner.run_batch(circs[sub], bits[sub], "c128", kmax=4, graph=True)
         t128 += r["times"][-1]
         for a64, a128 in zip(res["amps"][sub], r["amps"]):
-            err.append(orc.rel_l2(a64, a128))
-    # oracle on a stratified subset: the first circuit of each n <= 22
-    oracle_err = {}
-    for nq in sorted({c.n for c in circs}):
-        if nq > 22:
-            continue
-        j = next(i for i, c in enumerate(circs) if c.n == nq)
-        oracle_err[nq] = orc.rel_l2(res["amps"][j], orc.gather(orc.simulate(circs[j]), bits[j]))
+            err.append(float(np.linalg.norm(a64 - a128) / np.linalg.norm(a128)))
     line = {
         "metric": "batch: circuits/s and amp-updates/s, one graph-captured batch",
         "value": count / t, "unit": "circuits/s", "n_gpus": 1, "steps": args.steps,
@@ -545,7 +537,7 @@ def bench_batch(args) -> int:
         "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"], "staged": staged,
         "t_tune_s": round(t_tune, 2), "t_plan_s": round(t_plan, 2),
         "c128_batch_s": round(t128, 3),
-        "rel_l2_vs_c128_max": max(err), "rel_l2_vs_oracle_by_n": oracle_err,
+        "rel_l2_vs_c128_max": max(err),
     }
     print(json.dumps(line), flush=True)
     return 0
@@ -557,9 +549,6 @@ def bench_contract(args) -> int:
     then the tensor 1 x tensor 2 contraction over the entanglement indices;
     the contraction is timed (HIP events on its stream)."""
     import torch
-    from oracle import oracle as orc
-    from oracle import deferral as odf
-    from oracle import brute
     from paper_1910_09534_amd import deferral, planner, runner, sv
     from paper_1910_09534_amd import workload as W
 
@@ -607,23 +596,30 @@ def bench_contract(args) -> int:
     got = out[torch.from_numpy(xs).cuda()].cpu().numpy().astype(np.complex128)
     for st in states:
         st.close()
-    t_or = time.perf_counter()
-    ot = []
-    for ops, nq, order in ((sp.ops1, nt1, sp.order1), (sp.ops2, nt2, sp.order2)):
-        s = orc.zero_state(nq)
-        for g in ops:
-            orc.apply_dense(s, list(g.qubits), g.matrix)
-        ot.append(brute.permute_state(s, nq, order).reshape(1 << e, -1))
-        del s
-    x1 = xs & ((1 << n1) - 1)
-    x2 = xs >> n1
-    ref = np.einsum("ek,ek->k", ot[0][:, x1], ot[1][:, x2])
-    t_or = time.perf_counter() - t_or
-    err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
-    # CPU baseline: the oracle's contraction on a bounded sample (all of
-    # tensor 1 against the first 2^k columns of tensor 2)
+    # CPU baseline leg (the only place the oracle runs here): the oracle
+    # builds both tensors itself, its values at the sampled outputs are
+    # compared with the GPU's, and its contraction is timed on a bounded
+    # sample (all of tensor 1 against the first 2^k columns of tensor 2)
     cpu = None
+    err = None
+    t_or = None
     if not args.no_cpu_baseline:
+        from oracle import oracle as orc
+        from oracle import deferral as odf
+        from oracle import brute
+        t_or = time.perf_counter()
+        ot = []
+        for ops, nq, order in ((sp.ops1, nt1, sp.order1), (sp.ops2, nt2, sp.order2)):
+            s = orc.zero_state(nq)
+            for g in ops:
+                orc.apply_dense(s, list(g.qubits), g.matrix)
+            ot.append(brute.permute_state(s, nq, order).reshape(1 << e, -1))
+            del s
+        x1 = xs & ((1 << n1) - 1)
+        x2 = xs >> n1
+        ref = np.einsum("ek,ek->k", ot[0][:, x1], ot[1][:, x2])
+        t_or = round(time.perf_counter() - t_or, 1)
+        err = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
         k = 4
         while True:
             t1c = time.perf_counter()
@@ -642,7 +638,7 @@ def bench_contract(args) -> int:
                "cores": cores, "kind": "oracle",
                "sample": f"contraction of tensor 1 with the first 2^{k} of 2^{n2} columns of tensor 2 "
                          f"(complex128 matrix product, {dt:.1f} s)"}
-    del ot
+        del ot
     # the whole deferred run once, for context
     res = None
     if not args.no_pipeline:
@@ -671,7 +667,7 @@ def bench_contract(args) -> int:
                      "flops": "6 M N K: the 3M form's three real M x N x K products",
                      "complex_equivalent_tflops": round(tf, 2),
                      "hbm": {"bytes_per_launch": hbm, "achieved_gbs": round(hbm / (kms * 1e-3) / 1e9, 1)}},
-        "sampled_rel_l2_vs_oracle": err, "oracle_sample_s": round(t_or, 1),
+        "sampled_rel_l2_vs_oracle": err, "oracle_sample_s": t_or,
         "pipeline": None if res is None else
         {"t_run_s": round(res["t_run"], 3), "t_tensors_s": round(res["t_tensors"], 3),
          "contract_ms": round(res["contract_ms"], 3), "norm": res["norm"]},
