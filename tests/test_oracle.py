@@ -270,3 +270,35 @@ def test_permute_reference_by_loops():
     # applying the layout map twice with the inverse order returns the input
     back = brute.permute_state(out, n, [order.index(p) for p in range(n)])
     assert np.array_equal(back, psi)
+
+
+# ---- cross-entropy sums (defined in FP64 over the returned bitstrings) ------
+
+def test_xeb_sums_closed_forms():
+    """Sum_x N p(x) and sum_x ln(N p(x)), p = |a(x)|^2, N = 2^n, pinned by
+    states whose probabilities are known exactly: the uniform superposition
+    (N p = 1 for every x, whatever the phases), |0...0> (N p = N at x = 0,
+    zero elsewhere), and a hand-computed two-amplitude case.  A wrong N
+    (2^(n-1), 2^n - 1), a log in another base, |a| instead of |a|^2 or a
+    mean instead of a sum fails one of them."""
+    rng = np.random.default_rng(3)
+    for n in (1, 5, 12, 30):
+        N = float(1 << n)
+        cnt = 37
+        phases = np.exp(2j * math.pi * rng.random(cnt))
+        amps = phases / math.sqrt(N)
+        s1, s2 = orc.xeb_sums(n, amps)
+        assert abs(s1 - cnt) <= 1e-12 * cnt
+        assert abs(s2) <= 1e-12 * cnt
+        # |0...0>: only x = 0 carries probability 1
+        zero = np.array([1.0 + 0j, 1.0 + 0j, 1.0 + 0j])
+        s1, s2 = orc.xeb_sums(n, zero)
+        assert s1 == 3 * N
+        assert abs(s2 - 3 * n * math.log(2)) <= 1e-12 * (1 + abs(s2))
+        s1, s2 = orc.xeb_sums(n, np.array([1.0 + 0j, 0j]))
+        assert s1 == N and s2 == -math.inf
+    # n = 3: a = sqrt(2/8) e^{0.3i}, 0.5 sqrt(1/8) e^{-1.1i}  ->  N p = 2, 1/4
+    amps = np.array([math.sqrt(2 / 8) * cmath.exp(0.3j), 0.5 * math.sqrt(1 / 8) * cmath.exp(-1.1j)])
+    s1, s2 = orc.xeb_sums(3, amps)
+    assert abs(s1 - 2.25) <= 1e-15
+    assert abs(s2 - math.log(0.5)) <= 1e-15
