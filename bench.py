@@ -213,9 +213,7 @@ def time_dense_start(h, circ, bits, args) -> float:
     state (no sparse start after the reset), the plan ranked for that."""
     import torch
     from paper_1910_09534_amd import planner, sv
-    dense_ops = planner.plan(circ.gates, args.kmax)
-    for o in dense_ops:
-        o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
+    dense_ops = planner.pack(planner.plan(circ.gates, args.kmax), sv.SV_C64)
 
     def dense_step():
         sv.reset(h)
@@ -227,10 +225,32 @@ def time_dense_start(h, circ, bits, args) -> float:
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        dense_step()
+        amps, stats = dense_step()
     torch.cuda.synchronize()
     sv.set_option(h, sv.SV_OPT_SPARSE_START, 1)
-    return 1e3 * (time.perf_counter() - t0) / args.steps
+    return 1e3 * (time.perf_counter() - t0) / args.steps, amps, stats
+
+
+GOLDEN_HEADLINE = os.path.join(ROOT, "tests", "golden", "headline_30q_d14.npz")
+
+
+def accuracy_vs_stored(amps, stats, bits):
+    """Relative L2 error of the step's amplitudes against the complex128
+    amplitudes the CPU oracle stored for the same circuit and bitstrings
+    (tests/golden/make_golden.py); norm and cross-entropy sums beside it.
+    Computed after the timed region; None if the file is absent."""
+    if not os.path.exists(GOLDEN_HEADLINE):
+        return None
+    g = np.load(GOLDEN_HEADLINE)
+    if not np.array_equal(g["bitstrings"], bits):
+        return None
+    ref = g["amps"]
+    err = float(np.linalg.norm(amps - ref) / np.linalg.norm(ref))
+    return {"rel_l2_vs_oracle": err, "tolerance": 1e-4,
+            "norm": stats[0], "norm_oracle": float(g["norm"]),
+            "sum_Np": stats[1], "sum_Np_oracle": float(g["xeb"][0]),
+            "sum_ln_Np": stats[2], "sum_ln_Np_oracle": float(g["xeb"][1]),
+            "oracle": "complex128 CPU oracle, one gate at a time (stored amplitudes)"}
 
 
 def main(argv=None) -> int:
@@ -289,10 +309,11 @@ def main(argv=None) -> int:
     buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
     h = sv.create_state_ext(n, 0, "c64", stream, buf.data_ptr(), buf.numel() * 8)
+    packed = planner.pack(ops, sv.SV_C64)          # the whole plan queued by one library call
 
     def step():
         sv.reset(h)
-        planner.enqueue(h, ops, sv.SV_C64)
+        planner.enqueue(h, packed, sv.SV_C64)
         return sv.reduce_slices(h, bits)
 
     for _ in range(args.warmup):
@@ -320,9 +341,11 @@ def main(argv=None) -> int:
 
     # for comparison: every pass over the whole state (no sparse start
     # after the reset), with the plan ranked for that
-    dense_ms = None
+    accuracy = accuracy_vs_stored(amps, stats, bits)
+    dense_ms = dense_acc = None
     if not args.no_dense_start:
-        dense_ms = time_dense_start(h, circ, bits, args)
+        dense_ms, damps, dstats = time_dense_start(h, circ, bits, args)
+        dense_acc = accuracy_vs_stored(damps, dstats, bits)
 
     def kind_roof(kind):
         p = prof[kind]
@@ -382,8 +405,10 @@ def main(argv=None) -> int:
                    "k_hist": pst["k_hist"]},
         "hbm_frac_run": round(run_hbm_frac, 4),
         "amps_visited_frac": round(visited / (passes * float(1 << n)), 4),
+        "accuracy": accuracy,
         "dense_start": None if dense_ms is None else
-        {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3)},
+        {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3),
+         "rel_l2_vs_oracle": dense_acc and dense_acc["rel_l2_vs_oracle"]},
         "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,

@@ -139,6 +139,23 @@ int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix);
 int apply_diag(sv_handle h, int m, const int* qubits, const void* phases);
 
 /*
+ * apply_ops -- queue a planned sequence of operations in one call (Sec. 5:
+ * a subcircuit runs as its list of aggregate kernels, applied in order;
+ * App. A: the listing gives each subcircuit as such a list of rows).
+ * Operation i is kinds[i] = SV_OP_FUSED (as apply_fused) or SV_OP_DIAG (as
+ * apply_diag) on widths[i] qubits.  qubits: the operations' qubit lists,
+ * concatenated; data: their matrices (2^k x 2^k, row-major) or phase tables
+ * (2^m entries), concatenated, in the state dtype with no padding.  Every
+ * operation is validated before any is queued: on an error nothing is
+ * queued.  Inputs are copied; the caller may free them on return.
+ * Errors: SV_EINVAL (count < 0, a NULL array with count > 0, an unknown
+ * kind, or any error apply_fused / apply_diag would report), SV_ESLICED.
+ */
+enum { SV_OP_FUSED = 0, SV_OP_DIAG = 1 };
+int apply_ops(sv_handle h, int count, const int* kinds, const int* widths, const int* qubits,
+              const void* data);
+
+/*
  * permute_qubits -- choose a new layout (Sec. 4: switching subcircuits
  * reorganises which indices are local and which are global; the listing's
  * all2all rows give the new index order).  order[p] = logical qubit placed

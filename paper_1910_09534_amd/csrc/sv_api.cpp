@@ -192,7 +192,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
             double* norm_out = nullptr, int* norm_blocks = nullptr)
 {
     if (norm_blocks) *norm_blocks = 0;
-    const char* dbase = (const char*)h->d_arena;
+    const char* dbase = (const char*)h->d_arena_use;
     const size_t nops = h->ops.size();
     for (size_t i = 0; i < nops; ++i) {
         const Op& op = h->ops[i];
@@ -312,10 +312,18 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
     return SV_OK;
 }
 
-int upload_arena(sv_state* h)
+int upload_arena(sv_state* h, const WorkBufs* wb = nullptr)
 {
     const size_t bytes = h->arena.size();
     if (bytes == 0) return SV_OK;
+    if (wb) {
+        // caller-provided device memory; the copy reads the queue's own host
+        // buffer, which nothing changes before the caller's call returns
+        if (bytes > wb->arena_cap) return set_err(h, SV_EINVAL, "queued matrices exceed the work area");
+        TRY(h, hipMemcpyAsync(wb->arena, h->arena.data(), bytes, hipMemcpyHostToDevice, h->stream));
+        h->d_arena_use = wb->arena;
+        return SV_OK;
+    }
     if (h->ev_arena) TRY(h, hipEventSynchronize(h->ev_arena));   // pinned staging reusable
     if (h->h_arena_cap < bytes) {
         if (h->h_arena) pool_free(h->h_arena, h->h_arena_cap, true);
@@ -330,6 +338,7 @@ int upload_arena(sv_state* h)
     if (rc) return rc;
     std::memcpy(h->h_arena, h->arena.data(), bytes);
     TRY(h, hipMemcpyAsync(h->d_arena, h->h_arena, bytes, hipMemcpyHostToDevice, h->stream));
+    h->d_arena_use = h->d_arena;
     if (!h->ev_arena) TRY(h, hipEventCreateWithFlags(&h->ev_arena, hipEventDisableTiming));
     TRY(h, hipEventRecord(h->ev_arena, h->stream));
     return SV_OK;
@@ -701,11 +710,11 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
     return tier_pass_pageable(h, write_back, std::forward<F>(visit));
 }
 
-int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr)
+int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr, const WorkBufs* wb = nullptr)
 {
     if (norm_blocks) *norm_blocks = 0;
     if (h->ops.empty()) return materialize_state(h);
-    int rc = upload_arena(h);
+    int rc = upload_arena(h, wb);
     if (rc) return rc;
     if (!h->tier) {
         void* cur = h->dev;
@@ -941,16 +950,16 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
 }
 
 // FP64 host reduction helpers ------------------------------------------------
-int finish_sum(sv_state* h, hipStream_t st, int nblocks, int width, double* host_out)
+int finish_sum(sv_state* h, hipStream_t st, const WorkBufs& w, int nblocks, int width, double* host_out)
 {
-    TRY(h, launch_finish_sum(st, (const double*)h->d_part, nblocks, width, (double*)h->d_small));
-    TRY(h, hipMemcpyAsync(host_out, h->d_small, sizeof(double) * width, hipMemcpyDeviceToHost, st));
+    TRY(h, launch_finish_sum(st, (const double*)w.part, nblocks, width, (double*)w.small));
+    TRY(h, hipMemcpyAsync(host_out, w.small, sizeof(double) * width, hipMemcpyDeviceToHost, st));
     TRY(h, hipStreamSynchronize(st));
     return SV_OK;
 }
 
 int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* bits, void* out,
-              double* stats)
+              double* stats, const WorkBufs* wb = nullptr)
 {
     CHECK_HANDLE(h);
     if (count < 0 || (count > 0 && (!bits || !out))) return set_err(h, SV_EINVAL, "bad output arguments");
@@ -960,12 +969,18 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
     int rc;
     const int ns = 1 << h->s;
     const size_t cnt = (size_t)std::max<int64_t>(count, 1);
-    if ((rc = ensure_dev(h, &h->d_bits, &h->d_bits_cap, cnt * 8))) return rc;
-    if ((rc = ensure_dev(h, &h->d_acc, &h->d_acc_cap, cnt * 16))) return rc;
-    if ((rc = ensure_dev(h, &h->d_part, &h->d_part_cap, 4096 * 2 * sizeof(double)))) return rc;
-    // T (all columns, gathered per physical slice) + per-slice norms
-    if ((rc = ensure_dev(h, &h->d_tcol, &h->d_tcol_cap, (size_t)ns * ns * 16 + (size_t)ns * 8))) return rc;
-    if ((rc = ensure_dev(h, &h->d_rowmap, &h->d_rowmap_cap, (size_t)ns * 4))) return rc;
+    WorkBufs w;
+    if (wb) {
+        w = *wb;
+    } else {
+        if ((rc = ensure_dev(h, &h->d_bits, &h->d_bits_cap, cnt * 8))) return rc;
+        if ((rc = ensure_dev(h, &h->d_acc, &h->d_acc_cap, cnt * 16))) return rc;
+        if ((rc = ensure_dev(h, &h->d_part, &h->d_part_cap, kPartDoubles * sizeof(double)))) return rc;
+        // T (all columns, gathered per physical slice) + per-slice norms
+        if ((rc = ensure_dev(h, &h->d_tcol, &h->d_tcol_cap, (size_t)ns * ns * 16 + (size_t)ns * 8))) return rc;
+        if ((rc = ensure_dev(h, &h->d_rowmap, &h->d_rowmap_cap, (size_t)ns * 4))) return rc;
+        w = WorkBufs{h->d_bits, h->d_acc, h->d_part, h->d_tcol, h->d_rowmap, h->d_small, nullptr, 0};
+    }
 
     // logical bitstring -> physical index
     std::vector<int> from(h->n), to(h->n);
@@ -995,33 +1010,33 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
             }
     }
     hipStream_t st = h->stream;
-    double* d_snorm = (double*)((char*)h->d_tcol + (size_t)ns * ns * 16);
+    double* d_snorm = (double*)((char*)w.tcol + (size_t)ns * ns * 16);
     if (count > 0) {
-        TRY(h, hipMemcpyAsync(h->d_bits, bits, (size_t)count * 8, hipMemcpyHostToDevice, st));
-        TRY(h, hipMemsetAsync(h->d_acc, 0, (size_t)count * 16, st));
+        TRY(h, hipMemcpyAsync(w.bits, bits, (size_t)count * 8, hipMemcpyHostToDevice, st));
+        TRY(h, hipMemsetAsync(w.acc, 0, (size_t)count * 16, st));
     }
-    TRY(h, hipMemcpyAsync(h->d_rowmap, rowmap.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
-    if (T) TRY(h, hipMemcpyAsync(h->d_tcol, tcols.data(), tcols.size() * 8, hipMemcpyHostToDevice, st));
+    TRY(h, hipMemcpyAsync(w.rowmap, rowmap.data(), (size_t)ns * 4, hipMemcpyHostToDevice, st));
+    if (T) TRY(h, hipMemcpyAsync(w.tcol, tcols.data(), tcols.size() * 8, hipMemcpyHostToDevice, st));
     TRY(h, hipMemsetAsync(d_snorm, 0, (size_t)ns * 8, st));
     int folded_blocks = 0;
     // nothing below synchronises the host per slice: the tier pipeline keeps
     // staging the next slice while this one is reduced
     auto visit = [&](int t, const void* slice_buf) -> int {
-        const void* tc = T ? (const void*)((const char*)h->d_tcol + (size_t)t * ns * 16) : nullptr;
+        const void* tc = T ? (const void*)((const char*)w.tcol + (size_t)t * ns * 16) : nullptr;
         TRY(h, launch_accumulate(st, slice_buf, h->dtype, h->L, (uint64_t)t, l2p, count,
-                                 (const uint64_t*)h->d_bits, tc, (const int*)h->d_rowmap,
-                                 (double*)h->d_acc));
+                                 (const uint64_t*)w.bits, tc, (const int*)w.rowmap,
+                                 (double*)w.acc));
         if (stats) {
             int nb = folded_blocks;      // partials already written by the last staged pass
             if (nb == 0)
-                TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)h->d_part, &nb));
-            TRY(h, launch_finish_sum(st, (const double*)h->d_part, nb, 1, d_snorm + t));
+                TRY(h, launch_norm_partials(st, slice_buf, h->dtype, h->L, (double*)w.part, &nb));
+            TRY(h, launch_finish_sum(st, (const double*)w.part, nb, 1, d_snorm + t));
         }
         return SV_OK;
     };
     if (!h->tier) {
         // unsliced: the norm rides on the queue's last staged pass when it has one
-        rc = (stats && ns == 1) ? flush(h, (double*)h->d_part, &folded_blocks) : flush(h);
+        rc = (stats && ns == 1) ? flush(h, (double*)w.part, &folded_blocks, wb) : flush(h, nullptr, nullptr, wb);
         if (rc) return rc;
         for (int t = 0; t < ns && !rc; ++t)
             rc = visit(t, (const char*)h->dev + ((size_t)t << h->L) * h->amp);
@@ -1040,16 +1055,16 @@ int do_reduce(sv_state* h, const void* trailing, int64_t count, const uint64_t* 
     }
     if (rc) return rc;
     if (count > 0)
-        TRY(h, hipMemcpyAsync(out, h->d_acc, (size_t)count * 16, hipMemcpyDeviceToHost, st));
+        TRY(h, hipMemcpyAsync(out, w.acc, (size_t)count * 16, hipMemcpyDeviceToHost, st));
     if (stats) {
         std::vector<double> snorm(ns, 0.0);
         TRY(h, hipMemcpyAsync(snorm.data(), d_snorm, (size_t)ns * 8, hipMemcpyDeviceToHost, st));
         double x[2] = {0.0, 0.0};
         if (count > 0) {
             int nb = 0;
-            TRY(h, launch_xeb_partials(st, (const double*)h->d_acc, count, (double)h->n,
-                                       (double*)h->d_part, &nb));
-            rc = finish_sum(h, st, nb, 2, x);
+            TRY(h, launch_xeb_partials(st, (const double*)w.acc, count, (double)h->n,
+                                       (double*)w.part, &nb));
+            rc = finish_sum(h, st, w, nb, 2, x);
             if (rc) return rc;
         }
         TRY(h, hipStreamSynchronize(st));
@@ -1156,6 +1171,46 @@ int apply_diag(sv_handle h, int m, const int* qubits, const void* phases)
     op.off = push_arena(h, phases, ((size_t)1 << m) * h->amp);
     h->ops.push_back(op);
     if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
+    return SV_OK;
+}
+
+int apply_ops(sv_handle h, int count, const int* kinds, const int* widths, const int* qubits,
+              const void* data)
+{
+    CHECK_HANDLE(h);
+    if (count < 0) return set_err(h, SV_EINVAL, "negative operation count");
+    if (count == 0) return SV_OK;
+    if (!kinds || !widths || !qubits || !data) return set_err(h, SV_EINVAL, "NULL operation array");
+    // every operation is checked before any is queued
+    const int kmax = h->dtype ? 5 : 6;
+    size_t qo = 0;
+    for (int i = 0; i < count; ++i) {
+        const int k = widths[i];
+        int rc;
+        if (kinds[i] == SV_OP_FUSED) {
+            rc = check_qubit_list(h, k, qubits + qo, kmax);
+            if (rc) return rc;
+            if (k > h->L) return set_err(h, SV_EINVAL, "block wider than the local qubits");
+            for (int j = 0; j < k; ++j)
+                if (h->pos[qubits[qo + j]] >= h->L) return set_err(h, SV_ESLICED, "dense op on a sliced qubit");
+        } else if (kinds[i] == SV_OP_DIAG) {
+            rc = check_qubit_list(h, k, qubits + qo, kMaxDiag);
+            if (rc) return rc;
+        } else {
+            return set_err(h, SV_EINVAL, "unknown operation kind");
+        }
+        qo += (size_t)k;
+    }
+    qo = 0;
+    const char* d = (const char*)data;
+    for (int i = 0; i < count; ++i) {
+        const int k = widths[i];
+        const int rc = kinds[i] == SV_OP_FUSED ? apply_fused(h, k, qubits + qo, d)
+                                               : apply_diag(h, k, qubits + qo, d);
+        if (rc) return rc;
+        d += (kinds[i] == SV_OP_FUSED ? ((size_t)1 << (2 * k)) : ((size_t)1 << k)) * h->amp;
+        qo += (size_t)k;
+    }
     return SV_OK;
 }
 
@@ -1491,4 +1546,10 @@ int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nl
         ++cnt;
     }
     return cnt;
+}
+
+int sv::reduce_with(sv_state* h, const void* trailing, int64_t count, const uint64_t* bits, void* out,
+                    double* stats, const WorkBufs* wb)
+{
+    return do_reduce(h, trailing, count, bits, out, stats, wb);
 }

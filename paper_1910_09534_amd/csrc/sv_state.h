@@ -27,6 +27,26 @@ struct Op {
 // otherwise); on the handle's stream.
 int materialize_e0(sv_state* h);
 
+// Device work buffers of a reduction (and the matrices of the queue it
+// flushes) taken from caller-provided memory instead of the handle's pool:
+// the entry point that allocates nothing hands these in.
+struct WorkBufs {
+    void* bits;          // count uint64 bitstrings
+    void* acc;           // count complex128 accumulators
+    void* part;          // kPartDoubles FP64 partial sums
+    void* tcol;          // T columns (ns * ns complex128) + ns FP64 slice norms
+    void* rowmap;        // ns int
+    void* small;         // 8 doubles
+    void* arena;         // queued matrices / tables
+    size_t arena_cap;
+};
+constexpr size_t kPartDoubles = 4096 * 2;
+
+// The reduction behind reduce_slices with its work buffers taken from wb
+// (nullptr: the handle's own, allocated on demand).
+int reduce_with(sv_state* h, const void* trailing, int64_t count, const uint64_t* bits, void* out,
+                double* stats, const WorkBufs* wb);
+
 // Staged run starting at ops[i]: consecutive 4/5-qubit dense ops (none with
 // a diagonal to fold after it when fold is set) whose positions, with
 // positions 0..3, fit a tile of at most stage_t (and nloc, and the device's
@@ -72,6 +92,7 @@ struct sv_state {
     std::vector<uint8_t> arena;
     void* d_arena = nullptr;
     size_t d_arena_cap = 0;
+    const void* d_arena_use = nullptr;    // where the last upload put the queue's matrices
     void* h_arena = nullptr;
     size_t h_arena_cap = 0;
     hipEvent_t ev_arena = nullptr;

@@ -713,13 +713,34 @@ def stats(ops: Sequence[Op]) -> Dict[str, object]:
             "flops_per_amp": sum((8 * (1 << len(o.qubits)) - 2) for o in ops if o.kind == "dense")}
 
 
-def enqueue(state_handle, ops: Sequence[Op], dtype) -> None:
-    """Hand a planned op list to the library (argument marshalling only)."""
+class PackedPlan(list):
+    """pack()'s result: PackedOps items and permute ops, in plan order."""
+
+
+def pack(ops: Sequence[Op], dtype) -> PackedPlan:
+    """The op list as library calls: runs of dense / diagonal ops packed for
+    one apply_ops call each, permutes as their own items."""
     from . import sv
+    out, run = PackedPlan(), []
     for o in ops:
-        if o.kind == "dense":
-            sv.apply_fused(state_handle, o.qubits, o.matrix, dtype)
-        elif o.kind == "diag":
-            sv.apply_diag(state_handle, o.qubits, o.matrix, dtype)
+        if o.kind in ("dense", "diag"):
+            run.append((o.kind, o.qubits, o.matrix))
+            continue
+        if run:
+            out.append(sv.PackedOps(run, dtype))
+            run = []
+        out.append(o)
+    if run:
+        out.append(sv.PackedOps(run, dtype))
+    return out
+
+
+def enqueue(state_handle, ops, dtype) -> None:
+    """Hand a planned op list (or its pack()) to the library (argument
+    marshalling only)."""
+    from . import sv
+    for it in (ops if isinstance(ops, PackedPlan) else pack(ops, dtype)):
+        if isinstance(it, sv.PackedOps):
+            sv.apply_ops(state_handle, it)
         else:
-            sv.permute_qubits(state_handle, o.order)
+            sv.permute_qubits(state_handle, it.order)

@@ -20,12 +20,13 @@ SV_C64, SV_C128 = 0, 1
 SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE, SV_FLAG_STORE32 = 0x100, 0x200, 0x400, 0x800
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
 SV_OPT_SPARSE_START = 7
+SV_OP_FUSED, SV_OP_DIAG = 0, 1
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
                SV_ESLICED: "SV_ESLICED", SV_ESTATE: "SV_ESTATE", SV_EIO: "SV_EIO"}
 
 EXPORTS = ("create_state", "create_state_ext", "create_state_files", "destroy_state", "apply_fused", "apply_diag",
-           "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
+           "apply_ops", "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
            "sv_batch_destroy", "sv_batch_error", "sv_contract")
@@ -50,6 +51,7 @@ def load():
     L.destroy_state.argtypes = [P]
     L.apply_fused.argtypes = [P, I, P, P]
     L.apply_diag.argtypes = [P, I, P, P]
+    L.apply_ops.argtypes = [P, I, P, P, P, P]
     L.permute_qubits.argtypes = [P, P]
     L.gather_amplitudes.argtypes = [P, I64, P, P]
     L.reduce_slices.argtypes = [P, P, I64, P, P, P]
@@ -152,6 +154,32 @@ def apply_diag(h, qubits: Sequence[int], phases: np.ndarray, dtype) -> int:
     rc = lib().apply_diag(h, len(q), _ptr(q), _ptr(d))
     _check(rc, h)
     return rc
+
+
+class PackedOps:
+    """An operation list laid out for apply_ops: kinds, widths, concatenated
+    qubit lists and concatenated matrices / phase tables in one dtype."""
+
+    def __init__(self, ops, dtype):
+        code = _dtype_code(dtype)
+        dt = np_dtype(code)
+        kinds, widths, qubits, data = [], [], [], []
+        for kind, qs, m in ops:
+            kinds.append(SV_OP_FUSED if kind == "dense" else SV_OP_DIAG)
+            widths.append(len(qs))
+            qubits.extend(int(q) for q in qs)
+            data.append(np.ascontiguousarray(m, dtype=dt).ravel())
+        self.count = len(kinds)
+        self.kinds = np.array(kinds, dtype=np.int32)
+        self.widths = np.array(widths, dtype=np.int32)
+        self.qubits = np.array(qubits, dtype=np.int32)
+        self.data = np.concatenate(data) if data else np.zeros(1, dtype=dt)
+
+
+def apply_ops(h, packed: PackedOps) -> None:
+    """Queue a whole PackedOps list with one library call."""
+    _check(lib().apply_ops(h, packed.count, _ptr(packed.kinds), _ptr(packed.widths), _ptr(packed.qubits),
+                           _ptr(packed.data)), h)
 
 
 def permute_qubits(h, order: Sequence[int]) -> None:

@@ -260,3 +260,27 @@ def test_plan_sparse_start_is_exact_and_modelled():
     assert all(lv <= c.n for _, lv in passes)
     dense = planner.plan(c.gates, 5, nloc=c.n)
     assert planner.sparse_cost(ops, c.n, None, tmax) <= planner.sparse_cost(dense, c.n, None, tmax) + 1e-9
+
+
+def test_pack_lays_out_ops_for_apply_ops():
+    """pack(): runs of dense / diagonal ops become one apply_ops call each
+    (kinds, widths, concatenated qubits and matrices in the state dtype, no
+    padding); a permute ends a run and stays its own call."""
+    from paper_1910_09534_amd import sv
+    rng = np.random.default_rng(5)
+    ops = [planner.Op("dense", (3, 1), W.random_unitary(4, rng)),
+           planner.Op("diag", (0, 2, 5), W.random_phases(8, rng)),
+           planner.Op("perm", order=[1, 0, 2, 3, 4, 5]),
+           planner.Op("dense", (4,), W.random_unitary(2, rng))]
+    items = planner.pack(ops, "c64")
+    assert isinstance(items, planner.PackedPlan) and len(items) == 3
+    a, p, b = items
+    assert isinstance(a, sv.PackedOps) and p is ops[2] and isinstance(b, sv.PackedOps)
+    assert a.count == 2 and a.kinds.tolist() == [sv.SV_OP_FUSED, sv.SV_OP_DIAG]
+    assert a.widths.tolist() == [2, 3] and a.qubits.tolist() == [3, 1, 0, 2, 5]
+    assert a.data.dtype == np.complex64 and a.data.size == 16 + 8
+    assert np.array_equal(a.data[:16], ops[0].matrix.astype(np.complex64).ravel())
+    assert np.array_equal(a.data[16:], ops[1].matrix.astype(np.complex64))
+    assert b.count == 1 and b.qubits.tolist() == [4]
+    c = planner.pack(ops[:2], "c128")
+    assert len(c) == 1 and c[0].data.dtype == np.complex128
