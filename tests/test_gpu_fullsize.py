@@ -99,10 +99,12 @@ def test_headline_vs_stored_oracle(start):
 
 @pytest.mark.parametrize("sparse", [1, 0])
 def test_wide_lane_offsets_30q(sparse):
-    """Two 5-qubit blocks on positions 25..29 of a 30-qubit complex64 state:
-    the staged tile is positions 0..3 and 25..29, so its lane bits reach
-    position 29 and element offsets need 64 bits.  The 32 amplitudes whose
-    set bits lie in 25..29 equal a 5-qubit oracle run; others stay zero."""
+    """Two 5-qubit blocks on positions 25..29 of a 30-qubit complex64 state
+    holding stale values.  From a sparse start the staged tile is positions
+    0..3 and 25..29, so its lane bits reach position 29 and element offsets
+    need 64 bits; with every pass over the whole state the tile widens with
+    positions 4..7.  The 32 amplitudes whose set bits lie in 25..29 equal a
+    5-qubit oracle run; others are zero."""
     torch = _torch()
     n = 30
     rng = np.random.default_rng(2929)
@@ -110,6 +112,7 @@ def test_wide_lane_offsets_30q(sparse):
     us = [W.random_unitary(32, rng) for _ in range(2)]
     buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     buf.fill_(1.0 + 1.0j)                                   # stale contents
+    torch.cuda.synchronize()                                # the library runs on a stream of its own
     h = sv.create_state_ext(n, 0, "c64", torch.cuda.current_stream().cuda_stream, buf.data_ptr(),
                             buf.numel() * 8, keep=True)
     try:
