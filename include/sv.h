@@ -194,6 +194,30 @@ int gather_amplitudes(sv_handle h, int64_t count, const uint64_t* bitstrings, vo
 int reduce_slices(sv_handle h, const void* trailing_c128, int64_t count,
                   const uint64_t* bitstrings, void* out_c128, double stats[3]);
 
+/*
+ * reduce_slices_noalloc -- reduce_slices for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation).  Same arguments, results and errors as
+ * reduce_slices, but no device or pinned memory is allocated or freed: the
+ * work buffers of the reduction and the device copy of the queued matrices
+ * live in one fixed device array of the library (about 32 MiB, held on each
+ * GPU the library runs on until the process ends).  Limits: a resident
+ * state (not the host tier), SV_OPT_TIMING off, count <=
+ * SV_NOALLOC_MAX_BITSTRINGS, at most SV_NOALLOC_MAX_SLICED sliced qubits,
+ * queued matrices and tables of at most SV_NOALLOC_MAX_QUEUED_BYTES; beyond
+ * them: SV_EINVAL, nothing run.  All calls on one GPU share the array: the
+ * library lets one such call per GPU run at a time (calls from other
+ * threads wait), and the array keeps nothing from one call to the next.
+ * The state itself must have been created beforehand (creation allocates).
+ */
+enum {
+    SV_NOALLOC_MAX_BITSTRINGS = 1 << 20,
+    SV_NOALLOC_MAX_SLICED = 6,
+    SV_NOALLOC_MAX_QUEUED_BYTES = 8 << 20
+};
+int reduce_slices_noalloc(sv_handle h, const void* trailing_c128, int64_t count,
+                          const uint64_t* bitstrings, void* out_c128, double stats[3]);
+
 /* sync_state -- run everything queued and wait for it.  */
 int sync_state(sv_handle h);
 

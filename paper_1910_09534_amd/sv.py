@@ -29,7 +29,7 @@ EXPORTS = ("create_state", "create_state_ext", "create_state_files", "destroy_st
            "apply_ops", "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
-           "sv_batch_destroy", "sv_batch_error", "sv_contract")
+           "sv_batch_destroy", "sv_batch_error", "sv_contract", "reduce_slices_noalloc")
 SV_BATCH_GRAPH = 1
 
 
@@ -55,6 +55,7 @@ def load():
     L.permute_qubits.argtypes = [P, P]
     L.gather_amplitudes.argtypes = [P, I64, P, P]
     L.reduce_slices.argtypes = [P, P, I64, P, P, P]
+    L.reduce_slices_noalloc.argtypes = [P, P, I64, P, P, P]
     L.sync_state.argtypes = [P]
     L.sv_reset.argtypes = [P]
     L.last_error.argtypes = [P]
@@ -202,6 +203,21 @@ def reduce_slices(h, bitstrings: np.ndarray, trailing: Optional[np.ndarray] = No
     t = None if trailing is None else np.ascontiguousarray(trailing, dtype=np.complex128)
     _check(lib().reduce_slices(h, None if t is None else _ptr(t), b.size, _ptr(b), _ptr(out),
                                _ptr(stats)), h)
+    return out, tuple(float(x) for x in stats)
+
+
+NOALLOC_MAX_BITSTRINGS, NOALLOC_MAX_SLICED, NOALLOC_MAX_QUEUED_BYTES = 1 << 20, 6, 8 << 20
+
+
+def reduce_slices_noalloc(h, bitstrings: np.ndarray, trailing: Optional[np.ndarray] = None):
+    """As reduce_slices, through the entry point that allocates no device
+    memory (its work buffers are a fixed array of the library)."""
+    b = np.ascontiguousarray(bitstrings, dtype=np.uint64)
+    out = np.empty(b.size, dtype=np.complex128)
+    stats = np.zeros(3, dtype=np.float64)
+    t = None if trailing is None else np.ascontiguousarray(trailing, dtype=np.complex128)
+    _check(lib().reduce_slices_noalloc(h, None if t is None else _ptr(t), b.size, _ptr(b), _ptr(out),
+                                       _ptr(stats)), h)
     return out, tuple(float(x) for x in stats)
 
 
