@@ -563,14 +563,15 @@ def _nloc_of(gates) -> int:
 
 
 def plan_fast(gates, kmax: int, pos_of=None, nloc: Optional[int] = None,
-              sparse_start: bool = False) -> List[Op]:
+              sparse_start: bool = False, tmax: Optional[int] = None) -> List[Op]:
     """One staged aggregation (grow-based, window 4, last qubit only when it
     adds 40 % more gate weight), widened and ordered for staged passes: for
     request paths where planning time counts (tens of ms for ~600 gates).
     sparse_start: the same aggregation also of the gates in the Fiedler
-    orders of `support_order`, the cheapest by `sparse_cost` kept."""
+    orders of `support_order`, the cheapest by `sparse_cost` kept.
+    tmax: widest staged tile (default stage_tmax(nloc); 0 = no staging)."""
     n_loc = _nloc_of(gates) if nloc is None else nloc
-    tmax = stage_tmax(n_loc)
+    tmax = stage_tmax(n_loc) if tmax is None else tmax
     gain = 0.4 if kmax >= 5 and tmax else 0.0
     ops = fuse_grow(gates, kmax, window=4, last_gain=gain)
     if not tmax:

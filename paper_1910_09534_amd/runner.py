@@ -100,20 +100,29 @@ REDUCE_THREADS = 8
 
 
 def run_batch(circuits, bits_list, dtype="c64", kmax=5, mfma_min_k=4, graph: bool = True,
-              repeats: int = 1, plans=None, staged: bool = False) -> Dict[str, object]:
+              repeats: int = 1, plans=None, staged: bool = False, stage_t=None) -> Dict[str, object]:
     """Many independent circuits as one batched execution (one graph launch
-    per run).  kmax / mfma_min_k: an int, or a dict n -> value (autotuned).
-    staged (complex64): each state's runs of 4/5-qubit blocks go through
-    staged passes (tile limit planner.stage_tmax(n)), planned for them.
-    Each repeat resets every state and replays the batch; the returned
-    amplitudes are those of the last repeat."""
+    per run).  kmax / mfma_min_k / stage_t: an int, or a dict n -> value
+    (autotuned).  staged (complex64): each state's runs of 4/5-qubit blocks
+    go through staged passes (tile limit stage_t, default
+    planner.stage_tmax(n)), planned for them.  Each repeat resets every
+    state and replays the batch; the returned amplitudes are those of the
+    last repeat."""
     kof = (lambda n: kmax[n]) if isinstance(kmax, dict) else (lambda n: kmax)
     mof = (lambda n: mfma_min_k[n]) if isinstance(mfma_min_k, dict) else (lambda n: mfma_min_k)
     staged = staged and dtype == "c64"
-    tmax = (lambda n: planner.stage_tmax(n)) if staged else (lambda n: 0)
+    if not staged:
+        tmax = lambda n: 0                                            # noqa: E731
+    elif isinstance(stage_t, dict):
+        tmax = lambda n: stage_t[n]                                   # noqa: E731
+    elif stage_t is not None:
+        tmax = lambda n: min(int(stage_t), n - 9)                     # noqa: E731
+    else:
+        tmax = planner.stage_tmax
     t0 = time.perf_counter()
     if plans is None:
-        plans = [planner.plan_fast(c.gates, kof(c.n), nloc=c.n, sparse_start=True) if tmax(c.n) > 0
+        plans = [planner.plan_fast(c.gates, kof(c.n), nloc=c.n, sparse_start=True, tmax=tmax(c.n))
+                 if tmax(c.n) > 0
                  else planner.plan(c.gates, kof(c.n), staged=False) for c in circuits]
     t_plan = time.perf_counter() - t0
     states = []

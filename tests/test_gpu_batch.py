@@ -160,3 +160,25 @@ def test_batch_rejects_bad_inputs():
             sv.batch_prepare([a.h, t.h])          # tiered state
     finally:
         a.close(); c.close(); t.close()
+
+
+def test_tuned_staged_batch_matches_c128_batch_and_oracle():
+    """The staged batch with the fusion width and tile limit chosen per qubit
+    count by the autotuner (timed on this GPU): every result within the
+    complex64 tolerance of the complex128 batch of the same circuits and of
+    the oracle; the tuned choices are among the candidates."""
+    _gpu()
+    from paper_1910_09534_amd import autotune
+    tuned = autotune.tune_staged([19, 21], kmaxes=(4, 5, 6), tiles=(10, 12), depth=8, reps=1)
+    assert set(tuned["kmax"].values()) <= {4, 5, 6} and set(tuned["stage_t"].values()) <= {10, 12}
+    pairs = [(c, b) for c, b in zip(*_batch(count=8, nmin=19, nmax=21, seed=29)) if c.n in (19, 21)]
+    assert pairs
+    circs, bits = [p[0] for p in pairs], [p[1] for p in pairs]
+    res = runner.run_batch(circs, bits, "c64", kmax=tuned["kmax"], graph=True, repeats=2, staged=True,
+                           stage_t=tuned["stage_t"])
+    r128 = runner.run_batch(circs, bits, "c128", kmax=4, graph=True)
+    for c, b, a64, a128 in zip(circs, bits, res["amps"], r128["amps"]):
+        assert orc.rel_l2(a64, a128) <= 1e-4
+        ref = orc.gather(orc.simulate(c), b)
+        assert orc.rel_l2(a128, ref) <= 1e-12
+        assert orc.rel_l2(a64, ref) <= 1e-4
