@@ -49,9 +49,9 @@ def test_budget_is_respected():
     peak = []
     orig = srv._worker
 
-    def spy(slot, req, t_admit, t0):
+    def spy(*args):
         peak.append(srv.mem_used)
-        return orig(slot, req, t_admit, t0)
+        return orig(*args)
     srv._worker = spy
     srv.serve(reqs)
     assert max(peak) <= budget

@@ -284,3 +284,35 @@ def test_pack_lays_out_ops_for_apply_ops():
     assert b.count == 1 and b.qubits.tolist() == [4]
     c = planner.pack(ops[:2], "c128")
     assert len(c) == 1 and c[0].data.dtype == np.complex128
+
+
+def test_buddy_arena_blocks_disjoint_and_merge_back():
+    """The serving arena's buddy allocator: random admissions and releases
+    of power-of-two states never overlap, stay inside the arena, refuse what
+    does not fit, and merge back into whole top blocks when all are freed."""
+    from paper_1910_09534_amd.serve import BuddyArena
+    rng = np.random.default_rng(11)
+    a = BuddyArena(None, budget_bytes=7 * (1 << 30) + 12345, max_block=1 << 30, min_block=1 << 19)
+    assert a.top == 1 << 30 and a.count == 7 and a.size == 7 << 30
+    live = {}
+    for step in range(4000):
+        if live and rng.random() < 0.45:
+            off = list(live)[int(rng.integers(len(live)))]
+            a.release(off, live.pop(off))
+            continue
+        nbytes = 1 << int(rng.integers(16, 31))
+        off = a.alloc(nbytes)
+        if off is None:                                     # refused only when no block is large enough
+            assert not any(v for bs, v in a.free.items() if bs >= a.block_size(nbytes))
+            continue
+        b = a.block_size(nbytes)
+        assert off % b == 0 and 0 <= off and off + b <= a.size
+        for o2, n2 in live.items():
+            b2 = a.block_size(n2)
+            assert off + b <= o2 or o2 + b2 <= off, "blocks overlap"
+        live[off] = nbytes
+    for off, nb in list(live.items()):
+        a.release(off, nb)
+    assert a.free.get(a.top) == {i * a.top for i in range(7)}
+    assert all(not v for b, v in a.free.items() if b != a.top)
+    assert a.alloc((1 << 30) + 1) is None
