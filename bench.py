@@ -38,7 +38,8 @@ Other workloads (one JSON line each, same fields where they apply):
 
   --config 4   batch of 256 independent ABCDCDAB circuits (n ~ U{20..28},
                depth ~ U{10..20}, complex64) recorded as one graph-captured
-               batch; fusion width and kernel form autotuned per qubit count;
+               batch; fusion width (k in 3..6) and staged tile limit (12..14
+               positions) autotuned per qubit count on this GPU;
                1024 bitstrings per circuit; compared with the complex128 batch.
 
   --config 5   serving: seeded trace of 1000 Poisson arrivals at 50 req/s,
@@ -231,6 +232,61 @@ def time_dense_start(h, circ, bits, args) -> float:
     return 1e3 * (time.perf_counter() - t0) / args.steps, amps, stats
 
 
+def bench_c128(circ, bits, args, steps: int = 3):
+    """The same 30-qubit workload in complex128 (FP64 arithmetic, the paper's
+    in-memory precision, Sec. 5) on the same GPU: blocks of at most kmax
+    qubits as single sweeps on the vector units (HBM bound: 32 bytes per
+    amplitude per sweep), FP64 reduction; amplitudes against the stored
+    oracle amplitudes (tolerance 1e-12).  Returns a dict for the line."""
+    import torch
+    from paper_1910_09534_amd import planner, sv
+    n = circ.n
+    buf = torch.empty(1 << n, dtype=torch.complex128, device="cuda")
+    stream = torch.cuda.current_stream().cuda_stream
+    h = sv.create_state_ext(n, 0, "c128", stream, buf.data_ptr(), buf.numel() * 16)
+    best = None
+    try:
+        for kmax in ([args.c128_kmax] if args.c128_kmax else [4, 5]):
+            ops = planner.plan(circ.gates, kmax, staged=False)
+            packed = planner.pack(ops, sv.SV_C128)
+
+            def step():
+                sv.reset(h)
+                planner.enqueue(h, packed, sv.SV_C128)
+                return sv.reduce_slices(h, bits)
+
+            step()
+            sv.sweep_profile(h)
+            sv.set_option(h, sv.SV_OPT_TIMING, 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                amps, stats = step()
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            prof = sv.sweep_profile(h)["sweep"]
+            sv.set_option(h, sv.SV_OPT_TIMING, 0)
+            ms = 1e3 * t / steps
+            gbs = prof["bytes"] / (prof["ms"] * 1e-3) / 1e9 if prof["ms"] else 0.0
+            r = {"kmax": kmax, "ms_per_step": round(ms, 2), "value": len(circ.gates) * float(1 << n) / (ms * 1e-3),
+                 "unit": "amp-updates/s", "dtype": "c128", "steps": steps, "sweeps": prof["count"] // steps,
+                 "roofline": {"bound": "hbm", "kernel": "k_dense<double> (one dense block per HBM pass, FP64)",
+                              "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(gbs / HBM_PEAK_GBS, 4),
+                              "avg_launch_ms": round(prof["ms"] / max(prof["count"], 1), 4),
+                              "share_of_step": round(prof["ms"] / (steps * ms), 4)},
+                 "accuracy": accuracy_vs_stored(amps, stats, bits)}
+            if r["accuracy"]:
+                r["accuracy"]["tolerance"] = 1e-12
+            if best is None or r["ms_per_step"] < best["ms_per_step"]:
+                best = r
+    finally:
+        sv.destroy_state(h)
+        del buf
+        torch.cuda.empty_cache()
+    return best
+
+
 GOLDEN_HEADLINE = os.path.join(ROOT, "tests", "golden", "headline_30q_d14.npz")
 
 
@@ -268,11 +324,22 @@ def main(argv=None) -> int:
     ap.add_argument("--pins", action="store_true", help="config 3: also run the mirror pin")
     ap.add_argument("--batch-unstaged", action="store_true",
                     help="config 4: autotuned single sweeps instead of staged passes")
+    ap.add_argument("--slots", type=int, default=0, help="config 5: slot streams (default 8)")
+    ap.add_argument("--tune-cache", default=None,
+                    help="config 4: JSON file of tuned fusion widths and tile limits (read if present, else written)")
     ap.add_argument("--defer-cycles", type=int, default=2, help="config 6: cycles run as two tensors")
     ap.add_argument("--tier-dir", default=None,
                     help="config 3: keep the host tier in files in this directory (one per logical file)")
     ap.add_argument("--no-pipeline", action="store_true",
                     help="config 6: skip the whole deferred run after the timed contractions (profiling)")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the serving summary in the default line")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests of the serving summary in the default line")
+    ap.add_argument("--no-c128", action="store_true",
+                    help="skip the complex128 form of the default workload")
+    ap.add_argument("--c128-kmax", type=int, default=0,
+                    help="fusion width of the complex128 form (0: try 4 and 5, keep the faster)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run only a plain 4 GiB device-to-device copy (counter calibration)")
     args = ap.parse_args(argv)
@@ -291,6 +358,11 @@ def main(argv=None) -> int:
         return bench_serve(args)
     if args.config == 6:
         return bench_contract(args)
+
+    # planning processes for the serving summary, started before this
+    # process touches the GPU
+    from paper_1910_09534_amd import serve as serve_mod
+    pool = None if args.no_serve else serve_mod.planning_pool(PLAN_WORKERS)
 
     import torch
     from paper_1910_09534_amd import planner, sv
@@ -388,6 +460,12 @@ def main(argv=None) -> int:
     del buf
     torch.cuda.empty_cache()
 
+    c128 = None if args.no_c128 else bench_c128(circ, bits, args)
+    serving = None
+    if pool is not None:
+        serving = serve_summary(pool, args.kmax, count=args.serve_requests)
+        pool.shutdown()
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(circ, args.cpu_budget)
@@ -412,6 +490,8 @@ def main(argv=None) -> int:
         "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,
+        "c128": c128,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -514,25 +594,34 @@ def bench_batch(args) -> int:
     circs = [W.sycamore_circuit(s["n"], s["depth"], s["seed"]) for s in specs]
     bits = [W.bitstrings(s["n"], 1024, s["bit_seed"]) for s in specs]
     t0 = time.perf_counter()
+    ns = sorted({c.n for c in circs})
     if args.batch_unstaged:
-        tuned = autotune.tune(sorted({c.n for c in circs}))
+        tuned = autotune.tune(ns)
+        tuned["stage_t"] = {n: 0 for n in ns}
+    elif args.tune_cache and os.path.exists(args.tune_cache):
+        tuned = autotune.load(args.tune_cache)
     else:
-        # staged passes for every state (n >= 18): k <= 5 on the matrix cores
-        ns = sorted({c.n for c in circs})
-        tuned = {"kmax": {n: 5 for n in ns}, "mfma_min_k": {n: 4 for n in ns}}
+        # fusion width k in {3..6} and staged tile limit in {12, 13, 14} per
+        # qubit count, timed on this GPU
+        tuned = autotune.tune_staged(ns)
+        if args.tune_cache:
+            autotune.save(tuned, args.tune_cache)
+    tuned.setdefault("mfma_min_k", {n: 4 for n in ns})
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
     staged = not args.batch_unstaged
     # one staged aggregation per circuit (plan_fast): within ~2 % of the full
     # candidate search by the cost model, at 1/35 of its planning time
-    plans = [planner.plan_fast(c.gates, 5, nloc=c.n, sparse_start=True) if staged and planner.stage_tmax(c.n) > 0
-             else planner.plan(c.gates, tuned["kmax"][c.n], staged=False) for c in circs]
+    plans = [planner.plan_fast(c.gates, tuned["kmax"][c.n], nloc=c.n, sparse_start=True,
+                               tmax=tuned["stage_t"][c.n])
+             if staged else planner.plan(c.gates, tuned["kmax"][c.n], staged=False) for c in circs]
     for p in plans:
         for o in p:
             o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     t_plan = time.perf_counter() - t0
     res = runner.run_batch(circs, bits, "c64", kmax=tuned["kmax"], mfma_min_k=tuned["mfma_min_k"],
-                           graph=True, repeats=args.warmup + args.steps, plans=plans, staged=staged)
+                           graph=True, repeats=args.warmup + args.steps, plans=plans, staged=staged,
+                           stage_t=tuned["stage_t"] if staged else None)
     times = res["times"][args.warmup:]
     t = sum(times) / len(times)
     gate_amps = sum(len(c.gates) * float(1 << c.n) for c in circs)
@@ -559,7 +648,8 @@ def bench_batch(args) -> int:
         "amp_updates_per_s": gate_amps / t,
         "amps_visited_per_batch": swept,
         "hbm_GBps_visited": 16.0 * swept / t / 1e9,
-        "kmax_by_n": tuned["kmax"], "mfma_min_k_by_n": tuned["mfma_min_k"], "staged": staged,
+        "kmax_by_n": tuned["kmax"], "stage_t_by_n": tuned["stage_t"], "mfma_min_k_by_n": tuned["mfma_min_k"],
+        "staged": staged, "tuned_ms_by_n": tuned.get("ms"),
         "t_tune_s": round(t_tune, 2), "t_plan_s": round(t_plan, 2),
         "c128_batch_s": round(t128, 3),
         "rel_l2_vs_c128_max": max(err),
@@ -725,27 +815,68 @@ def source_hash(rel: str) -> str:
     return hashlib.sha256(" ".join(src.split()).encode()).hexdigest()[:16]
 
 
+PLAN_WORKERS = 12          # planning processes of the server (the GPU machine grants 16 CPUs)
+SERVE_SLOTS = 8
+SERVE_BUDGET = int(250e9)  # HBM budget of the request states
+
+
+def _build_requests(trace):
+    from paper_1910_09534_amd import serve
+    from paper_1910_09534_amd import workload as W
+    return [serve.Request(t["j"], t["t"], W.sycamore_circuit(t["n"], t["depth"], t["seed"]),
+                          W.bitstrings(t["n"], 1024, t["bit_seed"])) for t in trace]
+
+
+def serve_trace(pool, arena, kmax, count, rate=50.0, slots=None, seed=1005):
+    """The seeded serving trace (Poisson arrivals at `rate`, n ~ U{16..32},
+    depth ~ U{8..20}, 1024 bitstrings + norm each) through the server, states
+    in `arena` (the 250 GB HBM budget); returns (server, results, summary)."""
+    from paper_1910_09534_amd import serve
+    from paper_1910_09534_amd import workload as W
+    reqs = _build_requests(W.serving_trace(count, rate=rate, seed=seed))
+    # warm the kernels on a few small requests
+    serve.Server(slots=slots or SERVE_SLOTS, kmax=kmax, planner_pool=pool, arena=arena).serve(
+        _build_requests(W.serving_trace(8, rate=1000.0, seed=77, nmin=16, nmax=20)), realtime=False)
+    srv = serve.Server(slots=slots or SERVE_SLOTS, kmax=kmax, planner_pool=pool, arena=arena)
+    res = srv.serve(reqs)
+    return srv, res, serve.summarize(res)
+
+
+def serve_summary(pool, kmax, count):
+    """Serving half of the metric for the default line: the first `count`
+    requests of the seeded 50 req/s trace."""
+    import torch
+    from paper_1910_09534_amd import serve
+    arena = serve.BuddyArena(torch, SERVE_BUDGET)
+    srv, res, s = serve_trace(pool, arena, kmax, count)
+    del arena, srv
+    torch.cuda.empty_cache()
+    mu = s["circuits_per_s"]
+    return {"metric": "served circuits/s and p50/p99 latency (continuous batching)",
+            "value": mu, "unit": "circuits/s", "requests": count, "arrival_rate": 50.0,
+            "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
+            "makespan_s": s["makespan_s"],
+            "mean_wait_admit_s": s["mean_wait_admit_s"], "mean_wait_plan_s": s["mean_wait_plan_s"],
+            "mean_queue_s": s["mean_queue_s"], "mean_run_s": s["mean_run_s"], "device_busy": s["device_busy"],
+            # measured: arrival rate over the completion rate the server sustained
+            "offered_load_rho_measured": 50.0 / mu, "max_inflight": srv.max_inflight,
+            "max_norm_error": float(max(abs(r.norm - 1) for r in res)),
+            "planning": f"{PLAN_WORKERS} processes, from arrival", "slots": SERVE_SLOTS}
+
+
 def bench_serve(args) -> int:
     import torch
     from paper_1910_09534_amd import serve
     from paper_1910_09534_amd import workload as W
 
+    pool = serve.planning_pool(PLAN_WORKERS)          # before the GPU is touched
     torch.cuda.set_device(0)
     count = args.n or 1000
-
-    def build(trace):
-        return [serve.Request(t["j"], t["t"], W.sycamore_circuit(t["n"], t["depth"], t["seed"]),
-                              W.bitstrings(t["n"], 1024, t["bit_seed"])) for t in trace]
-
+    build = _build_requests
+    arena = serve.BuddyArena(torch, SERVE_BUDGET)
     t0 = time.perf_counter()
-    reqs = build(W.serving_trace(count, rate=50.0))
-    t_gen = time.perf_counter() - t0
-    # warm the kernels and the allocator on a few small requests
-    serve.Server(budget_bytes=250e9, slots=8, kmax=args.kmax).serve(
-        build(W.serving_trace(8, rate=1000.0, seed=77, nmin=16, nmax=20)), realtime=False)
-    srv = serve.Server(budget_bytes=250e9, slots=8, kmax=args.kmax)
-    res = srv.serve(reqs)
-    s50 = serve.summarize(res)
+    srv, res, s50 = serve_trace(pool, arena, args.kmax, count, slots=args.slots)
+    t_run = time.perf_counter() - t0
     norms = np.array([r.norm for r in res])
     mu = s50["circuits_per_s"]
     line = {
@@ -754,18 +885,23 @@ def bench_serve(args) -> int:
         "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"{count} Poisson arrivals at 50 req/s, n ~ U{{16..32}}, "
                                "depth ~ U{8..20}, 1024 bitstrings + norm each, 250 GB HBM budget",
-                   "requests": count, "slots": 8, "kmax": args.kmax},
+                   "requests": count, "slots": args.slots or SERVE_SLOTS, "kmax": args.kmax},
         "p50_latency_s": s50["p50_latency_s"], "p99_latency_s": s50["p99_latency_s"],
         "mean_latency_s": s50["mean_latency_s"], "makespan_s": s50["makespan_s"],
-        "offered_load_rho": 50.0 / mu, "max_inflight": srv.max_inflight,
-        "max_norm_error": float(np.abs(norms - 1).max()), "t_trace_gen_s": round(t_gen, 1),
+        "mean_wait_admit_s": s50["mean_wait_admit_s"], "mean_wait_plan_s": s50["mean_wait_plan_s"],
+        "mean_queue_s": s50["mean_queue_s"], "mean_run_s": s50["mean_run_s"], "device_busy": s50["device_busy"],
+        # measured: arrival rate over the completion rate the server sustained
+        "offered_load_rho_measured": 50.0 / mu, "max_inflight": srv.max_inflight,
+        "max_norm_error": float(np.abs(norms - 1).max()), "t_run_s": round(t_run, 1),
+        "planning": f"{PLAN_WORKERS} processes, from arrival",
     }
     # extra: a lighter trace at about 80% of the measured capacity
     lam = 0.8 * mu
     light = build(W.serving_trace(min(count, 300), rate=lam, seed=1505))
-    srv2 = serve.Server(budget_bytes=250e9, slots=8, kmax=args.kmax)
+    srv2 = serve.Server(slots=args.slots or SERVE_SLOTS, kmax=args.kmax, planner_pool=pool, arena=arena)
     s80 = serve.summarize(srv2.serve(light))
     line["extra_rho_0.8"] = {"rate": lam, "requests": len(light), **s80}
+    pool.shutdown()
     print(json.dumps(line), flush=True)
     return 0
 
