@@ -48,7 +48,11 @@ Other workloads (one JSON line each, same fields where they apply):
                continuous batching over 8 slot streams; circuits/s and
                p50 / p99 latency (plus a lighter trace at about 80% load).
 
-Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5] [--config 2|3|4|5]
+  --config 7   resident re-layouts of the 30-qubit complex64 state (random,
+               reversed and half-swapped orders), HBM roofline of the
+               tiled permutation kernel.
+
+Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 1] [--kmax 5] [--config 2|3|4|5|6|7]
 """
 from __future__ import annotations
 
@@ -358,6 +362,8 @@ def main(argv=None) -> int:
         return bench_serve(args)
     if args.config == 6:
         return bench_contract(args)
+    if args.config == 7:
+        return bench_permute(args)
 
     # planning processes for the serving summary, started before this
     # process touches the GPU
@@ -792,6 +798,63 @@ def bench_contract(args) -> int:
     return 0
 
 
+def bench_permute(args) -> int:
+    """Resident re-layouts (Sec. 4: the index permutes that re-choose the
+    sliced qubits; here the whole 30-qubit complex64 state is re-laid out in
+    HBM): random orders, the reversal, and the swap of the low and high
+    halves, each timed with HIP events on the state's stream (the tiled
+    permutation kernel; the handle's two buffers swap roles, nothing is
+    copied back).  HBM roofline: 16 bytes per amplitude per permute."""
+    import torch
+    from paper_1910_09534_amd import sv
+    from paper_1910_09534_amd import workload as W
+    torch.cuda.set_device(0)
+    n = args.n or 30
+    stream = torch.cuda.Stream()
+    st = sv.State(n, 0, "c64", stream=stream.cuda_stream)
+    rng = np.random.default_rng(7)
+    for q0 in range(0, n, 5):                               # blocks covering every qubit: a dense state
+        qs = list(range(q0, min(q0 + 5, n)))
+        st.fused(qs, W.random_unitary(1 << len(qs), rng))
+    bits = W.bitstrings(n, 1 << 12, seed=70)
+    ref = st.gather(bits)
+    orders = {"random": [int(x) for x in rng.permutation(n)], "reverse": list(range(n))[::-1],
+              "halves": list(range(n // 2, n)) + list(range(n // 2))}
+    ident = list(range(n))
+    res = {}
+    all_ms = []
+    for name, order in orders.items():
+        ms = []
+        for _ in range(args.warmup + args.steps):
+            for target in (order, ident):
+                a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                a.record(stream)
+                st.permute(target)
+                b.record(stream)
+                b.synchronize()
+                ms.append(a.elapsed_time(b))
+        ms = ms[2 * args.warmup:]
+        all_ms += ms
+        avg = sum(ms) / len(ms)
+        res[name] = {"ms": round(avg, 4), "GBps": round(16.0 * (1 << n) / (avg * 1e-3) / 1e9, 1)}
+    exact = bool(np.array_equal(st.gather(bits), ref))
+    st.close()
+    avg = sum(all_ms) / len(all_ms)
+    gbs = 16.0 * (1 << n) / (avg * 1e-3) / 1e9
+    line = {"metric": "resident permute: GB/s of the re-layout", "value": gbs, "unit": "GB/s", "n_gpus": 1,
+            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(avg, 4), "higher_is_better": True,
+            "dtype": "c64", "data": "synthetic",
+            "config": {"workload": f"{n}-qubit complex64 state (dense), permutes to random / reversed / "
+                                   "half-swapped orders and back", "n": n},
+            "per_order": res, "amplitudes_unchanged": exact,
+            "roofline": {"bound": "hbm", "kernel": "k_bitperm_tiled (LDS-tiled bit permutation)",
+                         "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": round(gbs / HBM_PEAK_GBS, 4),
+                         "traffic": profile_traffic("permute_30q_traffic.json", "paper_1910_09534_amd/csrc/sv_kernels.hip")}}
+    print(json.dumps(line), flush=True)
+    return 0
+
+
 def contract_traffic():
     """HBM bytes per k_contract_mfma launch from the committed counter runs,
     or None when the kernel source changed since."""
@@ -801,6 +864,19 @@ def contract_traffic():
     with open(path) as f:
         d = json.load(f)
     if d.get("source_hash") != source_hash("paper_1910_09534_amd/csrc/sv_contract.hip"):
+        return None
+    return d.get("traffic_bytes_per_launch")
+
+
+def profile_traffic(name: str, source: str):
+    """HBM bytes per launch from a committed counter summary under
+    profiles/, or None when the kernel source changed since."""
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != source_hash(source):
         return None
     return d.get("traffic_bytes_per_launch")
 

@@ -161,7 +161,10 @@ int apply_ops(sv_handle h, int count, const int* kinds, const int* widths, const
  * all2all rows give the new index order).  order[p] = logical qubit placed
  * at physical position p (p = 0 least significant); the top s positions
  * become the sliced qubits.  Flushes queued work.  Results of later calls
- * are unaffected (operations address logical qubits).  A resident state
+ * are unaffected (operations address logical qubits).  For a resident state
+ * the library allocated, the re-laid-out amplitudes may end up in another
+ * buffer of the handle (sv_device_buffer gives the current one); a state in
+ * a caller's buffer (create_state_ext) keeps it.  A resident state
  * that is still |0...0> with nothing queued (after sv_reset, or created and
  * not yet operated on) only takes the new layout: no data moves.  Choosing
  * the layout there decides which positions the first operations touch.
@@ -318,6 +321,8 @@ int sv_sweep_profile(sv_handle h, double ms[2], int64_t count[2], double flops[2
  * sv_batch_launch  -- enqueue the batch after the work already queued on the
  *   states' streams; later work on those streams waits for it.  Asynchronous.
  *   Runs the reset variant when every state is reset and not yet used.
+ *   SV_EINVAL if a state has queued operations or was permuted since the
+ *   batch was prepared (the recorded launches address its old layout).
  * sv_batch_sync    -- wait for the last launch.
  * sv_batch_info    -- [0] launches per run, [1] sweeps per run, [2]
  *   amplitudes the sweeps visit per run, [3] 1 if captured in a graph;

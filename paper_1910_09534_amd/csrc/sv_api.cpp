@@ -1253,8 +1253,13 @@ int permute_qubits(sv_handle h, const int* order)
         for (int q = 0; q < h->n; ++q) { from[q] = npos[q]; to[q] = h->pos[q]; }
         const BitRuns r = make_runs(h->n, from.data(), to.data());
         TRY(h, launch_bitperm(h->stream, h->dev, h->scratch, h->dtype, h->n, r));
-        TRY(h, hipMemcpyAsync(h->dev, h->scratch, ((size_t)1 << h->n) * h->amp,
-                              hipMemcpyDeviceToDevice, h->stream));
+        if (h->own_dev) {
+            std::swap(h->dev, h->scratch);       // both buffers are the handle's own
+        } else {
+            // the amplitudes stay in the caller's buffer
+            TRY(h, hipMemcpyAsync(h->dev, h->scratch, ((size_t)1 << h->n) * h->amp,
+                                  hipMemcpyDeviceToDevice, h->stream));
+        }
         // the positions that can be non-zero move with their qubits
         uint64_t moved = 0;
         for (int q = 0; q < h->n; ++q)

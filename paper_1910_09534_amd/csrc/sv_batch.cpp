@@ -50,6 +50,10 @@ struct Launch {
 
 struct sv_batch_s {
     std::vector<sv_state*> states;
+    // each state's buffer and layout when the batch was prepared: the
+    // recorded launches address both
+    std::vector<void*> devs;
+    std::vector<std::vector<int>> orders;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* d_arena = nullptr;
@@ -145,6 +149,10 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
     sv_batch_s* b = new (std::nothrow) sv_batch_s();
     if (!b) return berr(nullptr, SV_ENOMEM, "host allocation failed");
     b->states.assign(handles, handles + count);
+    for (int i = 0; i < count; ++i) {
+        b->devs.push_back(handles[i]->dev);
+        b->orders.push_back(handles[i]->order);
+    }
     hipError_t e;
     if (hip_stream) {
         b->stream = (hipStream_t)hip_stream;
@@ -390,6 +398,8 @@ int sv_batch_launch(sv_batch b)
         sv_state* h = b->states[i];
         if (h->poisoned) return SV_ESTATE;
         if (!h->ops.empty()) return berr(b, SV_EINVAL, "state has operations queued after the batch was prepared");
+        if (h->dev != b->devs[i] || h->order != b->orders[i])
+            return berr(b, SV_EINVAL, "state was re-laid out (permute_qubits) after the batch was prepared");
         // otherwise a deferred reset is written on the state's stream, ahead of the batch
         if (!reset && (h->e0_pending || h->garbage)) {
             const int rc = materialize_e0(h);

@@ -36,6 +36,17 @@ __device__ __forceinline__ uint64_t apply_runs(uint64_t v, const RunsK& r)
     return out;
 }
 
+static uint64_t apply_runs_host(uint64_t v, const BitRuns& r)
+{
+    uint64_t out = 0;
+    for (int i = 0; i < r.count; ++i) {
+        const uint64_t b = v & r.mask[i];
+        const int s = r.shift[i];
+        out |= s >= 0 ? (b << s) : (b >> (-s));
+    }
+    return out;
+}
+
 static RunsK to_k(const BitRuns& b)
 {
     RunsK r;
@@ -354,11 +365,138 @@ __global__ __launch_bounds__(256) void k_bitperm(const V* __restrict__ in, V* __
         out[o] = in[apply_runs(o, dst_to_src)];
 }
 
+// Tiled bit permutation.  A tile is the 2^t elements whose source bits
+// outside T are fixed, where T holds the lowest source bits and the source
+// bits of the lowest destination bits: the tile is read in source order
+// (runs of 2^a consecutive elements), parked in LDS, and written in
+// destination order (again runs of 2^a consecutive elements), so both the
+// reads and the writes are whole cache lines whichever bits move where.
+// Element e of the tile (bit j <-> source bit T_j, ascending) goes to LDS
+// slot e + e / 32; write-order element f (bit j <-> destination bit U_j,
+// ascending) reads slot of e(f).  Every map is linear over disjoint bits, so
+// each splits into a per-lane part (bits 0..7) and a per-iteration part.
+constexpr int kPermT = 12;                 // widest tile (2^12 elements)
+struct PermK {
+    int t;                                 // tile bits
+    int nfree;                             // source bits outside the tile
+    uint64_t free_src[64];                 // source offset of tile-id bit i
+    uint64_t free_dst[64];                 // destination offset of the same bit
+    uint64_t lane_src[8], lane_dst[8];     // offsets of lane bit b (read order / write order)
+    uint32_t lane_e[8];                    // tile-local source index of write-order lane bit b
+    uint64_t it_src[1 << (kPermT - 8)], it_dst[1 << (kPermT - 8)];
+    uint32_t it_e[1 << (kPermT - 8)];
+};
+
+__device__ __forceinline__ uint32_t pslot(uint32_t e) { return e + (e >> 5); }
+
+typedef float pf2 __attribute__((ext_vector_type(2)));
+typedef double pd2 __attribute__((ext_vector_type(2)));
+
+template <typename V>
+__global__ __launch_bounds__(256) void k_bitperm_tiled(const V* __restrict__ in, V* __restrict__ out, PermK p)
+{
+    extern __shared__ unsigned char permlds[];
+    V* T = (V*)permlds;
+    const uint64_t tile = blockIdx.x;
+    uint64_t sb = 0, db = 0;
+    for (int i = 0; i < p.nfree; ++i)
+        if ((tile >> i) & 1) {
+            sb |= p.free_src[i];
+            db |= p.free_dst[i];
+        }
+    const int tid = threadIdx.x;
+    uint64_t ls = 0, ld = 0;
+    uint32_t le = 0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b)
+        if ((tid >> b) & 1) {
+            ls |= p.lane_src[b];
+            ld |= p.lane_dst[b];
+            le |= p.lane_e[b];
+        }
+    const int iters = 1 << (p.t - 8);
+    for (int k = 0; k < iters; ++k) {
+        const uint32_t e = (uint32_t)tid + 256u * k;
+        T[pslot(e)] = __builtin_nontemporal_load(in + (sb + ls + p.it_src[k]));
+    }
+    __syncthreads();
+    const uint32_t sle = pslot(le);
+    for (int k = 0; k < iters; ++k)
+        __builtin_nontemporal_store(T[sle + pslot(p.it_e[k])], out + (db + ld + p.it_dst[k]));
+}
+
 hipError_t launch_bitperm(hipStream_t st, const void* in, void* out, int dtype, int nbits,
                           const BitRuns& dst_to_src)
 {
     const uint64_t count = 1ull << nbits;
     const RunsK r = to_k(dst_to_src);
+    // source bit of each destination bit, and the reverse
+    int src_of[64], dst_of[64];
+    for (int d = 0; d < nbits; ++d) {
+        const uint64_t sv = apply_runs_host(1ull << d, dst_to_src);
+        src_of[d] = sv ? __builtin_ctzll(sv) : -1;
+    }
+    bool ok = nbits >= 9 && nbits <= 63;
+    for (int d = 0; d < nbits && ok; ++d) ok = src_of[d] >= 0 && src_of[d] < nbits;
+    if (ok) {
+        for (int d = 0; d < nbits; ++d) dst_of[src_of[d]] = d;
+        const int esz = dtype == 0 ? 8 : 16;
+        const int tmax = esz == 8 ? kPermT : kPermT - 1;
+        const int t = nbits < tmax ? nbits : tmax;
+        const int a = t / 2 < 6 ? t / 2 : 6;                   // contiguous run bits
+        bool inT[64] = {};
+        int cnt = 0;
+        auto add = [&](int b) { if (!inT[b]) { inT[b] = true; ++cnt; } };
+        for (int b = 0; b < a; ++b) add(b);
+        for (int d = 0; d < a; ++d) add(src_of[d]);
+        for (int b = 0; b < nbits && cnt < t; ++b) add(b);
+        PermK p{};
+        p.t = cnt;
+        int T[64], U[64], nt = 0;
+        for (int b = 0; b < nbits; ++b)
+            if (inT[b]) T[nt++] = b;
+        int nu = 0;
+        for (int d = 0; d < nbits; ++d)
+            if (inT[src_of[d]]) U[nu++] = d;
+        int tpos_of_src[64];
+        for (int j = 0; j < nt; ++j) tpos_of_src[T[j]] = j;
+        p.nfree = 0;
+        for (int b = 0; b < nbits; ++b)
+            if (!inT[b]) {
+                p.free_src[p.nfree] = 1ull << b;
+                p.free_dst[p.nfree] = 1ull << dst_of[b];
+                ++p.nfree;
+            }
+        for (int b = 0; b < 8; ++b) {
+            p.lane_src[b] = 1ull << T[b];
+            p.lane_dst[b] = 1ull << U[b];
+            p.lane_e[b] = 1u << tpos_of_src[src_of[U[b]]];
+        }
+        for (int k = 0; k < (1 << (p.t - 8)); ++k) {
+            uint64_t s_ = 0, d_ = 0;
+            uint32_t e_ = 0;
+            for (int c = 0; 8 + c < p.t; ++c)
+                if ((k >> c) & 1) {
+                    s_ |= 1ull << T[8 + c];
+                    d_ |= 1ull << U[8 + c];
+                    e_ |= 1u << tpos_of_src[src_of[U[8 + c]]];
+                }
+            p.it_src[k] = s_;
+            p.it_dst[k] = d_;
+            p.it_e[k] = e_;
+        }
+        const uint64_t tiles = count >> p.t;
+        const size_t lds = (size_t)((1u << p.t) + ((1u << p.t) >> 5)) * esz;
+        if (tiles <= 0x7fffffffull) {
+            if (dtype == 0)
+                hipLaunchKernelGGL(k_bitperm_tiled<pf2>, dim3((unsigned)tiles), dim3(256), lds, st,
+                                   (const pf2*)in, (pf2*)out, p);
+            else
+                hipLaunchKernelGGL(k_bitperm_tiled<pd2>, dim3((unsigned)tiles), dim3(256), lds, st,
+                                   (const pd2*)in, (pd2*)out, p);
+            return hipGetLastError();
+        }
+    }
     const dim3 grid(grid_for(count, 256)), block(256);
     if (dtype == 0)
         hipLaunchKernelGGL(k_bitperm<float2>, grid, block, 0, st, (const float2*)in, (float2*)out, count, r);

@@ -158,6 +158,18 @@ def test_batch_rejects_bad_inputs():
             sv.batch_prepare([a.h, a.h])          # duplicate
         with pytest.raises(sv.SVError):
             sv.batch_prepare([a.h, t.h])          # tiered state
+        # a state re-laid out after the batch was prepared is refused at launch
+        u = W.random_unitary(4, np.random.default_rng(2)).astype(np.complex64)
+        a.fused([0, 1], u)
+        b = sv.batch_prepare([a.h])
+        try:
+            a.fused([2, 3], u)
+            a.sync()
+            a.permute(list(range(10))[::-1])
+            with pytest.raises(sv.SVError):
+                sv.batch_launch(b)
+        finally:
+            sv.batch_destroy(b)
     finally:
         a.close(); c.close(); t.close()
 

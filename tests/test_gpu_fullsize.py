@@ -219,3 +219,31 @@ def test_batch_qubit_counts_vs_stored_oracle():
         print(f"batch {c.n}q d{c.depth}: rel_l2={err:.3e}", flush=True)
         assert err <= TOL64
     assert res["info"]["graph"] == 1
+
+
+@pytest.mark.parametrize("dtype,n", [("c64", 30), ("c128", 28)])
+def test_permute_full_size_preserves_amplitudes(dtype, n):
+    """A dense state of 2^30 (complex64) or 2^28 (complex128) amplitudes,
+    re-laid-out by random permutations, a reversal and a swap of the low and
+    high halves of the positions: the amplitudes of 2^16 logical bitstrings
+    are bitwise the same after every permute (a permute moves amplitudes,
+    it computes nothing)."""
+    _torch()
+    rng = np.random.default_rng(n)
+    st = sv.State(n, 0, dtype)
+    try:
+        for q0 in range(0, n, 5):                            # blocks covering every qubit: a dense state
+            qs = list(range(q0, min(q0 + 5, n)))
+            st.fused(qs, W.random_unitary(1 << len(qs), rng))
+        bits = W.bitstrings(n, 1 << 16, seed=n + 1)
+        ref = st.gather(bits)
+        assert np.count_nonzero(ref) > 0
+        orders = [[int(x) for x in rng.permutation(n)] for _ in range(2)]
+        orders += [list(range(n))[::-1], list(range(n // 2, n)) + list(range(n // 2))]
+        for order in orders:
+            st.permute(order)
+            assert st.order() == order
+            got = st.gather(bits)
+            assert np.array_equal(got, ref)
+    finally:
+        st.close()
