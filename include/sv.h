@@ -117,6 +117,26 @@ int create_state_ext(int n, uint64_t slice_mask, int dtype, void* hip_stream,
 int create_state_files(int n, uint64_t slice_mask, int dtype, void* hip_stream, const char* dir,
                        sv_handle* out);
 
+/*
+ * sv_checkpoint -- make a state whose host tier lives in files a restart
+ * point (Sec. 4: each phase ends with every logical file written whole to
+ * secondary storage, so the files are a complete copy of the state): every
+ * queued operation is applied and written back, the files are flushed to
+ * storage, and a small metadata file (sv_checkpoint.meta: sizes, layout,
+ * slices known to be zero, file names, and the caller's tag, e.g. the index
+ * of the next phase) replaces the previous one atomically.  Errors:
+ * SV_EINVAL (the tier is not in files), SV_EIO, SV_EDEVICE.
+ *
+ * open_state_files -- a new handle on the state of the last checkpoint in
+ * dir: the existing files, mapped shared, with the checkpoint's layout;
+ * *tag receives its tag (tag may be NULL).  The new handle owns the files
+ * (destroy_state removes them and the metadata unless SV_OPT_KEEP_FILES).
+ * Errors: SV_EINVAL (dir or out NULL, malformed metadata), SV_EIO (no
+ * checkpoint, a file missing or of the wrong size), SV_ENOMEM, SV_EDEVICE.
+ */
+int sv_checkpoint(sv_handle h, int64_t tag);
+int open_state_files(const char* dir, void* hip_stream, sv_handle* out, int64_t* tag);
+
 /* destroy_state -- wait for queued work, free everything the handle owns.
    Accepts a poisoned handle; NULL is a no-op.  */
 int destroy_state(sv_handle h);
@@ -262,6 +282,9 @@ enum {
     SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer
                               from now on (n >= 1) is not issued and reports SV_EIO,
                               poisoning the handle; 0 (default): off */
+    SV_OPT_KEEP_FILES = 8,  /* states whose tier is in files: 1 = destroy_state keeps the
+                              files and the checkpoint (so a later open_state_files
+                              can resume); 0 (default) = they are removed */
     SV_OPT_SPARSE_START = 7 /* 1 (default): a resident state created as |0...0> or
                               reset with sv_reset is non-zero only on index bits some
                               operation has targeted since; staged passes visit only

@@ -12,6 +12,7 @@
 #include <fcntl.h>
 #include <hip/hip_runtime.h>
 #include <sys/mman.h>
+#include <sys/stat.h>
 #include <unistd.h>
 
 #include <algorithm>
@@ -20,7 +21,10 @@
 #include <deque>
 #include <new>
 #include <thread>
+#include <cctype>
+#include <cerrno>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <vector>
@@ -735,6 +739,17 @@ int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr, c
     return SV_OK;
 }
 
+// checkpoint metadata of a file-backed tier, in the tier's directory
+const char* const kCheckpointName = "sv_checkpoint.meta";
+
+// What open_state_files restores: the layout, the slices known to be zero
+// and the names of the existing files.
+struct Restore {
+    std::vector<int> order;
+    std::vector<uint8_t> slice_zero;
+    std::vector<std::string> names;
+};
+
 void release(sv_state* h)
 {
     if (!h) return;
@@ -750,7 +765,10 @@ void release(sv_state* h)
         else munmap(p, fbytes);
     }
     for (int fd : h->file_fds) (void)close(fd);
-    for (const auto& path : h->file_paths) (void)unlink(path.c_str());
+    if (!h->keep_files) {
+        for (const auto& path : h->file_paths) (void)unlink(path.c_str());
+        if (!h->tier_dir.empty()) (void)unlink((h->tier_dir + "/" + kCheckpointName).c_str());
+    }
     for (void* p : h->slots)
         if (p) (void)hipFree(p);
     if (h->pslot) (void)hipFree(h->pslot);
@@ -782,7 +800,7 @@ void default_layout(sv_state* h)
 }
 
 int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext, size_t ext_bytes,
-                  sv_handle* out, const char* dir = nullptr)
+                  sv_handle* out, const char* dir = nullptr, const Restore* rs = nullptr)
 {
     if (!out) return set_err(nullptr, SV_EINVAL, "out is NULL");
     const int base = dtype & 0xff;
@@ -872,24 +890,31 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
             // as whole files), mapped shared: the page cache does the I/O
             static std::atomic<unsigned> seq{0};
             const unsigned id = seq.fetch_add(1);
+            h->tier_dir = dir;
+            if (rs) h->keep_files = true;       // until opened, the files are the checkpoint's
             for (size_t i = 0; i < h->files.size(); ++i) {
-                const std::string path = std::string(dir) + "/sv_tier_" + std::to_string((long)getpid()) + "_" +
-                                         std::to_string(id) + "_" + std::to_string(i) + ".bin";
-                const int fd = open(path.c_str(), O_RDWR | O_CREAT | O_EXCL, 0600);
+                const std::string path = rs ? std::string(dir) + "/" + rs->names[i]
+                                            : std::string(dir) + "/sv_tier_" + std::to_string((long)getpid()) + "_" +
+                                                  std::to_string(id) + "_" + std::to_string(i) + ".bin";
+                const int fd = rs ? open(path.c_str(), O_RDWR) : open(path.c_str(), O_RDWR | O_CREAT | O_EXCL, 0600);
                 if (fd < 0) {
                     release(h);
-                    return set_err(nullptr, SV_EIO, "cannot create tier file " + path);
+                    return set_err(nullptr, SV_EIO, (rs ? "cannot open tier file " : "cannot create tier file ") + path);
                 }
                 h->file_fds.push_back(fd);
                 h->file_paths.push_back(path);
                 void* p = MAP_FAILED;
-                if (ftruncate(fd, (off_t)fb) == 0)
+                struct stat sb_;
+                const bool sized = rs ? (fstat(fd, &sb_) == 0 && (size_t)sb_.st_size == fb)
+                                      : ftruncate(fd, (off_t)fb) == 0;
+                if (sized)
                     p = mmap(nullptr, fb, PROT_READ | PROT_WRITE, MAP_SHARED, fd, 0);
                 if (p == MAP_FAILED) {
                     release(h);
                     return set_err(nullptr, SV_EIO, "cannot size or map tier file " + path);
                 }
                 h->files[i] = p;
+                h->file_maps.push_back(p);
             }
         } else if (!h->pinned_tier) {
             for (auto& f : h->files) {
@@ -903,11 +928,19 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
                 f = p;
             }
         }
-        // |0...0>: amplitude 0 lives in file (t = 0, u = 0)
-        if (h->famp == 16) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
-        else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
-        h->slice_zero.assign(ns, 1);
-        h->slice_zero[0] = 0;
+        if (rs) {
+            // the checkpoint's state: its layout, its zero slices, its files as they are
+            h->order = rs->order;
+            for (int p = 0; p < n; ++p) h->pos[h->order[p]] = p;
+            h->slice_zero = rs->slice_zero;
+            h->keep_files = false;
+        } else {
+            // |0...0>: amplitude 0 lives in file (t = 0, u = 0)
+            if (h->famp == 16) { double one[2] = {1.0, 0.0}; std::memcpy(h->files[0], one, 16); }
+            else { float one[2] = {1.0f, 0.0f}; std::memcpy(h->files[0], one, 8); }
+            h->slice_zero.assign(ns, 1);
+            h->slice_zero[0] = 0;
+        }
         const size_t sb = ((size_t)1 << h->L) * h->amp;
         h->slots.assign(h->nslots, nullptr);
         for (auto& p : h->slots)
@@ -1359,6 +1392,124 @@ int reduce_slices(sv_handle h, const void* trailing_c128, int64_t count, const u
     return do_reduce(h, trailing_c128, count, bitstrings, out_c128, stats);
 }
 
+int sv_checkpoint(sv_handle h, int64_t tag)
+{
+    CHECK_HANDLE(h);
+    if (h->file_fds.empty() || h->tier_dir.empty())
+        return set_err(h, SV_EINVAL, "checkpoints need a host tier in files (create_state_files)");
+    int rc = sync_state(h);                 // every queued operation applied, every file written back
+    if (rc) return rc;
+    const size_t fb = file_amps(h) * h->famp;
+    for (size_t i = 0; i < h->files.size(); ++i)
+        if (msync(h->files[i], fb, MS_SYNC) != 0) return set_err(h, SV_EIO, "msync of a tier file failed");
+    std::string meta = "sv_checkpoint 1\n";
+    meta += "n " + std::to_string(h->n) + "\n";
+    // the qubits sliced now (those at the top positions), not at creation
+    uint64_t sliced = 0;
+    for (int p = h->L; p < h->n; ++p) sliced |= 1ull << h->order[p];
+    meta += "slice_mask " + std::to_string((unsigned long long)sliced) + "\n";
+    meta += "dtype " + std::to_string(h->dtype | (h->store32 ? SV_FLAG_STORE32 : 0)) + "\n";
+    meta += "tag " + std::to_string((long long)tag) + "\n";
+    meta += "order";
+    for (int p = 0; p < h->n; ++p) meta += " " + std::to_string(h->order[p]);
+    meta += "\nslice_zero";
+    for (uint8_t z : h->slice_zero) meta += z ? " 1" : " 0";
+    // logical file i is the file now mapped at files[i] (a change of the
+    // sliced set relabels files instead of moving them)
+    meta += "\nfiles " + std::to_string(h->files.size()) + "\n";
+    for (void* p : h->files) {
+        size_t j = 0;
+        while (j < h->file_maps.size() && h->file_maps[j] != p) ++j;
+        if (j == h->file_maps.size()) return set_err(h, SV_EIO, "internal: tier file without a path");
+        meta += h->file_paths[j].substr(h->file_paths[j].rfind('/') + 1) + "\n";
+    }
+    // write, flush and rename: a crash leaves the previous checkpoint or this one whole
+    const std::string final_path = h->tier_dir + "/" + kCheckpointName;
+    const std::string tmp = final_path + ".tmp";
+    const int fd = open(tmp.c_str(), O_WRONLY | O_CREAT | O_TRUNC, 0600);
+    if (fd < 0) return set_err(h, SV_EIO, "cannot write " + tmp);
+    const bool ok = write(fd, meta.data(), meta.size()) == (ssize_t)meta.size() && fsync(fd) == 0;
+    (void)close(fd);
+    if (!ok || rename(tmp.c_str(), final_path.c_str()) != 0) {
+        (void)unlink(tmp.c_str());
+        return set_err(h, SV_EIO, "cannot write " + final_path);
+    }
+    const int dfd = open(h->tier_dir.c_str(), O_RDONLY | O_DIRECTORY);
+    if (dfd >= 0) { (void)fsync(dfd); (void)close(dfd); }
+    return SV_OK;
+}
+
+int open_state_files(const char* dir, void* hip_stream, sv_handle* out, int64_t* tag)
+{
+    if (!dir || !*dir || !out) return set_err(nullptr, SV_EINVAL, "directory or out is NULL");
+    const std::string path = std::string(dir) + "/" + kCheckpointName;
+    FILE* f = std::fopen(path.c_str(), "r");
+    if (!f) return set_err(nullptr, SV_EIO, "no checkpoint in " + std::string(dir));
+    std::vector<char> buf(1 << 20);
+    const size_t got = std::fread(buf.data(), 1, buf.size() - 1, f);
+    std::fclose(f);
+    buf[got] = 0;
+    std::string text(buf.data());
+    size_t at = 0;
+    auto word = [&]() -> std::string {
+        while (at < text.size() && std::isspace((unsigned char)text[at])) ++at;
+        const size_t b = at;
+        while (at < text.size() && !std::isspace((unsigned char)text[at])) ++at;
+        return text.substr(b, at - b);
+    };
+    auto num = [&](long long lo, long long hi, long long* v) -> bool {
+        const std::string w = word();
+        if (w.empty()) return false;
+        char* end = nullptr;
+        errno = 0;
+        const long long x = std::strtoll(w.c_str(), &end, 10);
+        if (errno || *end || x < lo || x > hi) return false;
+        *v = x;
+        return true;
+    };
+    long long version = 0, n = 0, dtype = 0, t = 0, nfiles = 0;
+    unsigned long long mask = 0;
+    bool ok = word() == "sv_checkpoint" && num(1, 1, &version) && word() == "n" && num(1, 40, &n) &&
+              word() == "slice_mask";
+    if (ok) {
+        const std::string w = word();
+        char* end = nullptr;
+        mask = std::strtoull(w.c_str(), &end, 10);
+        ok = !w.empty() && !*end && (n >= 64 || (mask >> n) == 0);
+    }
+    ok = ok && word() == "dtype" && num(0, 0xfff, &dtype) && word() == "tag" &&
+         num(-(1ll << 62), 1ll << 62, &t) && word() == "order";
+    const int s = __builtin_popcountll(mask);
+    Restore rs;
+    if (ok) {
+        std::vector<int> seen(n, 0);
+        for (long long p = 0; p < n && ok; ++p) {
+            long long q = 0;
+            ok = num(0, n - 1, &q) && !seen[q];
+            if (ok) { seen[q] = 1; rs.order.push_back((int)q); }
+        }
+        // the top s positions must hold the sliced qubits
+        for (long long p = n - s; p < n && ok; ++p) ok = (mask >> rs.order[p]) & 1;
+    }
+    ok = ok && s >= 1 && s <= 12 && word() == "slice_zero";
+    for (int i = 0; ok && i < (1 << s); ++i) {
+        long long z = 0;
+        ok = num(0, 1, &z);
+        rs.slice_zero.push_back((uint8_t)z);
+    }
+    ok = ok && word() == "files" && num(1, 1 << 24, &nfiles) && nfiles == (1ll << (2 * s));
+    for (long long i = 0; ok && i < nfiles; ++i) {
+        const std::string w = word();
+        ok = !w.empty() && w.find('/') == std::string::npos && w != "." && w != "..";
+        rs.names.push_back(w);
+    }
+    if (!ok) return set_err(nullptr, SV_EINVAL, "malformed checkpoint " + path);
+    const int rc = create_common((int)n, mask, (int)dtype | SV_FLAG_TIER, hip_stream, nullptr, 0, out, dir, &rs);
+    if (rc) return rc;
+    if (tag) *tag = t;
+    return SV_OK;
+}
+
 int sync_state(sv_handle h)
 {
     CHECK_HANDLE(h);
@@ -1449,6 +1600,10 @@ int sv_set_option(sv_handle h, int option, int64_t value)
             return SV_OK;
         case SV_OPT_FAIL_IO: h->fail_io_at = value; return SV_OK;
         case SV_OPT_SPARSE_START: h->sparse_start = value != 0; return SV_OK;
+        case SV_OPT_KEEP_FILES:
+            if (h->file_fds.empty()) return set_err(h, SV_EINVAL, "SV_OPT_KEEP_FILES: the tier is not in files");
+            h->keep_files = value != 0;
+            return SV_OK;
     }
     return set_err(h, SV_EINVAL, "unknown option");
 }

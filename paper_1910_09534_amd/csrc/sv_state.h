@@ -81,6 +81,9 @@ struct sv_state {
     int famp = 8;                         // bytes per amplitude in the files
     std::vector<int> file_fds;            // file-backed tier: one open file per logical file
     std::vector<std::string> file_paths;  //   (removed when the handle is destroyed)
+    std::vector<void*> file_maps;         //   and where each is mapped (files[] gets relabelled)
+    std::string tier_dir;                 // their directory (checkpoint metadata lives there too)
+    bool keep_files = false;              // destroy keeps the files and the checkpoint
     std::vector<uint8_t> slice_zero;      // slice known to be all zero
     std::vector<void*> slots;             // device slice buffers
     void* pslot = nullptr;                // device buffer for local permutes

@@ -62,30 +62,52 @@ def grid_slice_sets(n: int):
 
 def simulate_sliced(circuit, bits: np.ndarray, set_a, set_b, dtype="c64", kmax: int = 5,
                     tier: bool = False, timing: bool = False, sched=None,
-                    pageable: bool = False, tier_dir: Optional[str] = None) -> Dict[str, object]:
+                    pageable: bool = False, tier_dir: Optional[str] = None,
+                    checkpoint: bool = False, resume: bool = False,
+                    stop_after: Optional[int] = None) -> Dict[str, object]:
     """Sliced evolution (Sec. 4): phases alternate the sliced set; each switch
     is one permute_qubits; the trailing gates on the last sliced set are
-    applied by the FP64 cross-slice reduction."""
+    applied by the FP64 cross-slice reduction.
+
+    With the tier in files (tier_dir): checkpoint makes the start of every
+    phase a restart point (sv_checkpoint, tagged with the phase index: all
+    earlier phases applied, the layout of this phase); resume continues
+    from the last checkpoint in tier_dir instead of starting from |0...0>.
+    stop_after=i ends the run right after phase i's checkpoint, leaving the
+    files and the checkpoint in place (as a run that dies there would);
+    the result then holds only "stopped"."""
     t0 = time.perf_counter()
     if sched is None:
         sched = planner.phase_schedule(circuit, set_a, set_b, kmax)
     t_plan = time.perf_counter() - t0
     n = circuit.n
     mask = sum(1 << q for q in sched.phases[0].sliced)
-    st = sv.State(n, mask, dtype, tier=tier, pageable=pageable, tier_dir=tier_dir)
+    if resume:
+        st = sv.State.open(tier_dir, n, mask, dtype)
+        start = int(st.tag)
+    else:
+        st = sv.State(n, mask, dtype, tier=tier, pageable=pageable, tier_dir=tier_dir)
+        start = 0
     if dtype == "c64":   # the phases were planned for this tile limit
         sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(n - len(sched.phases[0].sliced)))
     try:
         if timing:
             sv.set_option(st.h, sv.SV_OPT_TIMING, 1)
         t1 = time.perf_counter()
-        for ph in sched.phases:
+        for i, ph in enumerate(sched.phases):
+            if i < start:
+                continue
             sv.permute_qubits(st.h, ph.order)
+            if checkpoint:
+                sv.checkpoint(st.h, i)
+            if stop_after is not None and i >= stop_after:
+                sv.set_option(st.h, sv.SV_OPT_KEEP_FILES, 1)
+                return {"stopped": i}
             planner.enqueue(st.h, ph.ops, st.dtype)
         amps, stats = sv.reduce_slices(st.h, bits, sched.trailing)
         t_run = time.perf_counter() - t1
         out = {"amps": amps, "norm": stats[0], "xeb_sum": stats[1], "xeb_log_sum": stats[2],
-               "t_plan": t_plan, "t_run": t_run, "phases": len(sched.phases),
+               "t_plan": t_plan, "t_run": t_run, "phases": len(sched.phases), "resumed_at": start,
                "trailing_gates": len(sched.trailing_gate_ids),
                "sweeps": sum(len(p.ops) for p in sched.phases), "counters": sv.counters(st.h)}
         if timing:

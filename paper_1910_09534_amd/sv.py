@@ -20,6 +20,7 @@ SV_C64, SV_C128 = 0, 1
 SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE, SV_FLAG_STORE32 = 0x100, 0x200, 0x400, 0x800
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
 SV_OPT_SPARSE_START = 7
+SV_OPT_KEEP_FILES = 8
 SV_OP_FUSED, SV_OP_DIAG = 0, 1
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
@@ -29,7 +30,8 @@ EXPORTS = ("create_state", "create_state_ext", "create_state_files", "destroy_st
            "apply_ops", "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
            "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
-           "sv_batch_destroy", "sv_batch_error", "sv_contract", "reduce_slices_noalloc")
+           "sv_batch_destroy", "sv_batch_error", "sv_contract", "reduce_slices_noalloc", "sv_checkpoint",
+           "open_state_files")
 SV_BATCH_GRAPH = 1
 
 
@@ -56,6 +58,8 @@ def load():
     L.gather_amplitudes.argtypes = [P, I64, P, P]
     L.reduce_slices.argtypes = [P, P, I64, P, P, P]
     L.reduce_slices_noalloc.argtypes = [P, P, I64, P, P, P]
+    L.sv_checkpoint.argtypes = [P, I64]
+    L.open_state_files.argtypes = [ctypes.c_char_p, P, ctypes.POINTER(P), ctypes.POINTER(I64)]
     L.sync_state.argtypes = [P]
     L.sv_reset.argtypes = [P]
     L.last_error.argtypes = [P]
@@ -135,6 +139,19 @@ def create_state_files(n: int, slice_mask: int, dtype, stream, directory: str, s
     code = _dtype_code(dtype) | (SV_FLAG_STORE32 if store32 else 0)
     _check(lib().create_state_files(n, slice_mask, code, stream, directory.encode(), ctypes.byref(h)))
     return h.value
+
+
+def checkpoint(h, tag: int) -> None:
+    """Make a state whose tier is in files a restart point (sv_checkpoint)."""
+    _check(lib().sv_checkpoint(h, int(tag)), h)
+
+
+def open_state_files(directory: str, stream=None):
+    """(handle, tag) of the last checkpoint in `directory`."""
+    h = ctypes.c_void_p()
+    tag = ctypes.c_int64()
+    _check(lib().open_state_files(directory.encode(), stream, ctypes.byref(h), ctypes.byref(tag)))
+    return h.value, tag.value
 
 
 def destroy_state(h) -> None:
@@ -331,6 +348,17 @@ class State:
             self.h = create_state_files(n, slice_mask, dtype, stream, tier_dir, store32)
         else:
             self.h = create_state(n, slice_mask, dtype, stream, tier, pageable, store32)
+
+    @classmethod
+    def open(cls, directory: str, n: int, slice_mask: int, dtype="c64", stream=None) -> "State":
+        """The state of the last checkpoint in `directory` (open_state_files)
+        of an n-qubit state with this slice mask and dtype; the checkpoint's
+        tag is in .tag."""
+        h, tag = open_state_files(directory, stream)
+        st = cls.__new__(cls)
+        st.h, st.tag = h, tag
+        st.n, st.slice_mask, st.dtype = n, slice_mask, _dtype_code(dtype)
+        return st
 
     def fused(self, qubits, matrix):
         apply_fused(self.h, qubits, matrix, self.dtype)

@@ -244,3 +244,46 @@ def test_single_precision_storage(files, tmp_path):
         results[store32] = orc.rel_l2(got, psi)
     assert results[False] <= 1e-12
     assert 1e-10 < results[True] <= 2e-6
+
+
+@pytest.mark.parametrize("dtype,stop", [("c64", 0), ("c64", 2), ("c128", 1)])
+def test_checkpoint_restart_from_files(tmp_path, dtype, stop):
+    """Restart from the last complete phase (Sec. 4: every phase ends with the
+    logical files written whole): a run with its tier in files checkpoints
+    at the start of every phase and ends right after phase `stop`'s
+    checkpoint, leaving the files; a second run opens that checkpoint and
+    finishes.  Its amplitudes are bitwise those of an uninterrupted run and
+    match the oracle; the finished run removes the files."""
+    _gpu()
+    n = 16
+    c = W.sycamore_circuit(n, 14, seed=4100 + stop)
+    A, B = runner.grid_slice_sets(n)
+    bits = W.bitstrings(n, 2048, seed=41)
+    kmax = 5 if dtype == "c64" else 4
+    da, db = tmp_path / "a", tmp_path / "b"
+    da.mkdir()
+    db.mkdir()
+    full = runner.simulate_sliced(c, bits, A, B, dtype=dtype, kmax=kmax, tier_dir=str(da))
+    part = runner.simulate_sliced(c, bits, A, B, dtype=dtype, kmax=kmax, tier_dir=str(db), checkpoint=True,
+                                  stop_after=stop)
+    assert part == {"stopped": stop}
+    names = {p.name for p in db.iterdir()}
+    assert "sv_checkpoint.meta" in names and len(names) == 1 + (1 << len(A)) ** 2
+    res = runner.simulate_sliced(c, bits, A, B, dtype=dtype, kmax=kmax, tier_dir=str(db), checkpoint=True,
+                                 resume=True)
+    assert res["resumed_at"] == stop and full["phases"] > stop + 1
+    assert np.array_equal(res["amps"], full["amps"])
+    ref = orc.gather(orc.simulate(c), bits)
+    assert orc.rel_l2(res["amps"], ref) <= TOL[dtype]
+    assert list(db.iterdir()) == [] and list(da.iterdir()) == []
+
+
+def test_checkpoint_refused_outside_files():
+    _gpu()
+    st = sv.State(12, (1 << 3) | (1 << 9), "c64", tier=True)
+    try:
+        with pytest.raises(sv.SVError) as e:
+            sv.checkpoint(st.h, 0)
+        assert e.value.code == sv.SV_EINVAL
+    finally:
+        st.close()

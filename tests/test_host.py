@@ -316,3 +316,29 @@ def test_buddy_arena_blocks_disjoint_and_merge_back():
     assert a.free.get(a.top) == {i * a.top for i in range(7)}
     assert all(not v for b, v in a.free.items() if b != a.top)
     assert a.alloc((1 << 30) + 1) is None
+
+
+def test_open_state_files_rejects_missing_or_malformed_checkpoints(tmp_path):
+    """open_state_files reads the checkpoint's metadata before touching the
+    device: no checkpoint is SV_EIO, malformed metadata (bad counts, a
+    layout that is not a permutation, sliced qubits off the top positions,
+    file names with a path) is SV_EINVAL."""
+    from paper_1910_09534_amd import sv
+    with pytest.raises(sv.SVError) as e:
+        sv.open_state_files(str(tmp_path))
+    assert e.value.code == sv.SV_EIO
+    good = ["sv_checkpoint 1", "n 4", "slice_mask 8", "dtype 0", "tag 3", "order 0 1 2 3", "slice_zero 0 1",
+            "files 4", "f0", "f1", "f2", "f3"]
+    bad = [
+        [l.replace("order 0 1 2 3", "order 0 1 1 3") for l in good],      # not a permutation
+        [l.replace("order 0 1 2 3", "order 3 1 2 0") for l in good],      # sliced qubit 3 not on top
+        [l.replace("files 4", "files 3") for l in good][:-1],              # wrong file count
+        [l.replace("f2", "../f2") for l in good],                          # a path
+        [l.replace("n 4", "n 99") for l in good],                          # size out of range
+        good[:5],                                                           # truncated
+    ]
+    for lines in bad:
+        (tmp_path / "sv_checkpoint.meta").write_text("\n".join(lines) + "\n")
+        with pytest.raises(sv.SVError) as e:
+            sv.open_state_files(str(tmp_path))
+        assert e.value.code == sv.SV_EINVAL, lines
