@@ -17,14 +17,17 @@ are zero and are zero-filled if still unwritten when the state is read);
 amps_visited_frac gives the share of the full passes' amplitudes visited,
 and dense_start the same steps with every pass over the whole state.
 
-roofline: the kernel kind with the most time in the timed steps (staged
-passes: matrix-core bound, algorithmic flops = 8 2^k - 2 per amplitude per
-block, the complex dot product; the kernels issue 6 2^k of them as the
-three real products of the 3M form, reported as issued_frac; single
-sweeps: HBM bound, 16 bytes per amplitude per launch; a staged pass moves
-16 bytes per amplitude visited, 8 when it starts from |0...0> or takes an
-amplitude as zero), durations from HIP events on the kernels' stream;
-hbm_frac_run: the bytes those launches moved per step over the step time.
+roofline: the kernel kind with the most time in the timed steps.  Staged
+passes in the split-fp16 form (the default: complex64 products on the fp16
+matrix cores, 24 2^k issued flops per amplitude per block, a small share of
+the fp16 peak) are HBM bound: 16 bytes per amplitude visited, 8 when the
+pass starts from |0...0> or takes an amplitude as zero; the fp32 figures
+(algorithmic flops = 8 2^k - 2 per amplitude per block, the complex dot
+product, over the fp32 matrix peak) stay in the line for comparison with
+the fp32 form (3M, 6 2^k issued), which is matrix-core bound.  Single
+sweeps: HBM bound, 16 bytes per amplitude per launch.  Durations from HIP
+events on the kernels' stream; hbm_frac_run: the bytes those launches
+moved per step over the step time.
 
 value = 621 * 2^30 * steps / t  (each circuit gate counted once, the
 un-aggregated work over aggregated time).
@@ -70,6 +73,7 @@ import numpy as np  # noqa: E402
 METRIC = ("amp-updates/s & % HBM peak, 30q d14 complex64; served circuits/s + p99 latency")
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3
+FP16_PEAK_TFLOPS = 2500.0          # dense fp16 matrix cores
 
 
 KERNEL_SOURCES = ("paper_1910_09534_amd/csrc/sv_device.h", "paper_1910_09534_amd/csrc/sv_kernels.hip",
@@ -414,6 +418,8 @@ def main(argv=None) -> int:
     # per kernel kind, every launch of the timed steps bracketed by HIP events
     # on the stream the kernels run on; the dominant kind is the roofline's
     prof = sv.sweep_profile(h)
+    forms = sv.stage_forms(h)
+    split_form = forms["split"] > 0 and forms["fp32"] == 0
     sv.set_option(h, sv.SV_OPT_TIMING, 0)
     visited = (c1["amps_swept"] - c0["amps_swept"]) / args.steps
 
@@ -433,16 +439,25 @@ def main(argv=None) -> int:
         gbs = p["bytes"] / (p["ms"] * 1e-3) / 1e9
         tflops = p["flops"] / (p["ms"] * 1e-3) / 1e12          # algorithmic
         issued = p["issued"] / (p["ms"] * 1e-3) / 1e12         # as executed (3M on the matrix cores)
+        fp16 = kind == "staged" and split_form
+        ipeak = FP16_PEAK_TFLOPS if fp16 else FP32_PEAK_TFLOPS
         r = {"launches": p["count"], "avg_launch_ms": round(avg_ms, 4),
              "share_of_step": round(p["ms"] / (args.steps * ms_per_step), 4),
              "hbm": {"achieved_gbs": round(gbs, 1), "frac": round(gbs / HBM_PEAK_GBS, 4),
                      "bytes_per_launch": p["bytes"] / p["count"]},
              "fp32": {"achieved_tflops": round(tflops, 2), "frac": round(tflops / FP32_PEAK_TFLOPS, 4),
-                      "flops_per_launch": p["flops"] / p["count"],
-                      "issued_tflops": round(issued, 2), "issued_frac": round(issued / FP32_PEAK_TFLOPS, 4)},
+                      "flops_per_launch": p["flops"] / p["count"]},
+             "issued": {"dtype": "fp16" if fp16 else "fp32", "tflops": round(issued, 2), "peak": ipeak,
+                        "frac": round(issued / ipeak, 4)},
              "traffic": counter_traffic(kind)}
-        if kind == "staged":
-            r.update({"kernel": "k_stage (staged pass: 2-8 dense 4/5-qubit blocks per HBM pass, matrix cores)",
+        if kind == "staged" and fp16:
+            r.update({"kernel": "k_stage, split-fp16 form (staged pass: 2-8 dense 4/5-qubit blocks per HBM "
+                                "pass, fp16 matrix cores)",
+                      "bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                      "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)})
+        elif kind == "staged":
+            r.update({"kernel": "k_stage, fp32 form (staged pass: 2-8 dense 4/5-qubit blocks per HBM pass, "
+                                "fp32 matrix cores)",
                       "bound": "mfma", "achieved": round(tflops, 2), "peak": FP32_PEAK_TFLOPS,
                       "unit": "TFLOP/s", "frac": round(tflops / FP32_PEAK_TFLOPS, 4)})
         else:
@@ -455,7 +470,7 @@ def main(argv=None) -> int:
     dom = max((k for k in kinds if kinds[k]), key=lambda k: prof[k]["ms"])
     roof = dict(kinds[dom])
     roof = {key: roof[key] for key in ("bound", "achieved", "peak", "unit", "frac", "traffic", "kernel",
-                                       "avg_launch_ms", "launches", "share_of_step", "hbm", "fp32")}
+                                       "avg_launch_ms", "launches", "share_of_step", "hbm", "fp32", "issued")}
     other = [k for k in kinds if k != dom and kinds[k]]
     if other:
         roof["other_kernel"] = kinds[other[0]]

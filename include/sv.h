@@ -285,6 +285,16 @@ enum {
     SV_OPT_KEEP_FILES = 8,  /* states whose tier is in files: 1 = destroy_state keeps the
                               files and the checkpoint (so a later open_state_files
                               can resume); 0 (default) = they are removed */
+    SV_OPT_SPLIT = 9,       /* 1 (default): a staged pass runs its complex64 products on
+                              the fp16 matrix cores with single-precision accuracy
+                              (each fp32 operand split into two fp16 parts, fp32
+                              accumulation, the tile scaled by a power of two taken
+                              from the state's amplitude bound, see sv_stage_forms)
+                              when every block of the pass is unitary within 1e-3
+                              (largest entry of |M^H M - I|) and the bound is
+                              finite; otherwise, or with 0, on the fp32 matrix
+                              cores.  A batch takes the form at sv_batch_prepare, in
+                              its variant run from a reset only. */
     SV_OPT_SPARSE_START = 7 /* 1 (default): a resident state created as |0...0> or
                               reset with sv_reset is non-zero only on index bits some
                               operation has targeted since; staged passes visit only
@@ -306,6 +316,27 @@ int sv_set_option(sv_handle h, int option, int64_t value);
  * dense sweeps (HIP events on the handle's stream), reset by the call.
  */
 int sv_counters(sv_handle h, int64_t counters[8]);
+
+/*
+ * sv_stage_forms -- staged multi-block passes run since creation in the
+ * split-fp16 form (passes[0]) and in the fp32 form (passes[1]), and the
+ * state's amplitude bound: an upper bound on its norm, so on every
+ * |amplitude|, kept on the host.  It is 1 after creation and sv_reset, is
+ * multiplied by each queued op's growth (a bound on its largest singular
+ * value: the square root of the largest absolute row sum of M^H M; for a
+ * diagonal op its largest |entry|), and becomes infinite when
+ * sv_device_buffer hands out the amplitudes (the caller may write them) or
+ * when open_state_files restores a checkpoint that does not state it, or
+ * create_state_ext adopts the caller's amplitudes (SV_FLAG_KEEP).  A
+ * resident state with an unknown bound gets one from its norm, measured on
+ * the device when its next queue holds 4/5-qubit complex64 blocks (one read
+ * pass and a wait on the handle's stream).  The split form scales the tile
+ * by the largest power of two 2^e with 2^e * bound <= 2^15, so amplitudes
+ * stay in fp16 range (Sec. 5 computes in single precision; the split keeps
+ * that accuracy).  A batch counts its passes at sv_batch_prepare, in the
+ * form of its variant run from a reset.  Either pointer may be NULL.
+ */
+int sv_stage_forms(sv_handle h, int64_t passes[2], double* amp_bound);
 int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
 
 /* sv_sweep_profile -- with SV_OPT_TIMING: the timed launches split by kind,
@@ -313,7 +344,9 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count);
  * milliseconds, launch count, algorithmic flops (a k-qubit block is a
  * complex 2^k-term dot product per amplitude: 8 2^k - 2 flops), the flops
  * the kernels issued (6 2^k per amplitude per complex64 block on the
- * matrix cores, 3 real products; 8 2^k on the vector units) and the HBM
+ * fp32 matrix cores, 3 real products; 24 2^k on the fp16 matrix cores in
+ * the split form, 4 real products of 3 split terms; 8 2^k on the vector
+ * units) and the HBM
  * bytes the launches had to move (amplitudes read and written; after
  * sv_reset a staged pass visits only the amplitudes that can be non-zero,
  * reads none from |0...0> and none on positions no operation has reached).

@@ -35,6 +35,52 @@
 
 using namespace sv;
 
+double sv::op_growth(const void* m, int k, size_t amp, bool* unit)
+{
+    // G = M^H M (Hermitian: the upper triangle, in fp32, is enough for a
+    // tolerance of 1e-3); ||M||_2^2 = lambda_max(G) <= max_r sum_c |G_rc|
+    const int D = 1 << k;
+    std::vector<float> re((size_t)D * D), im((size_t)D * D);
+    for (size_t i = 0; i < (size_t)D * D; ++i) {
+        if (amp == 8) {
+            re[i] = ((const float*)m)[2 * i];
+            im[i] = ((const float*)m)[2 * i + 1];
+        } else {
+            re[i] = (float)((const double*)m)[2 * i];
+            im[i] = (float)((const double*)m)[2 * i + 1];
+        }
+    }
+    std::vector<float> gr((size_t)D * D, 0.f), gi((size_t)D * D, 0.f);
+    for (int x = 0; x < D; ++x) {
+        const float* ar = &re[(size_t)x * D];
+        const float* ai = &im[(size_t)x * D];
+        for (int r = 0; r < D; ++r) {
+            const float cr = ar[r], ci = -ai[r];
+            float* pr = &gr[(size_t)r * D];
+            float* pi = &gi[(size_t)r * D];
+            for (int c = r; c < D; ++c) {
+                pr[c] += cr * ar[c] - ci * ai[c];
+                pi[c] += cr * ai[c] + ci * ar[c];
+            }
+        }
+    }
+    std::vector<double> row(D, 0.0);
+    double dev = 0.0;
+    for (int r = 0; r < D; ++r)
+        for (int c = r; c < D; ++c) {
+            const double a = std::hypot((double)gr[(size_t)r * D + c], (double)gi[(size_t)r * D + c]);
+            row[r] += a;
+            if (c != r) row[c] += a;
+            const double d = c == r ? std::hypot((double)gr[(size_t)r * D + c] - 1.0, (double)gi[(size_t)r * D + c]) : a;
+            dev = std::max(dev, d);
+        }
+    double worst = 0.0;
+    for (int r = 0; r < D; ++r) worst = std::max(worst, row[r]);
+    if (unit) *unit = dev <= kUnitTol;
+    // not finite (NaN / inf entries): no bound
+    return std::isfinite(worst) ? std::sqrt(worst) : HUGE_VAL;
+}
+
 namespace {
 
 thread_local std::string g_create_error;
@@ -231,9 +277,20 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 const bool h_garbage_before = h->garbage;
                 const uint64_t support_before = h->support;
                 uint64_t pmask = 0, visited = 0;
+                // split-fp16 form: unitary blocks, the tile scaled from the
+                // state's amplitude bound through the run
+                bool unit = h->split;
+                double bmax = h->ops[i].bound_before;
+                for (int c = 0; c < cnt; ++c) {
+                    unit = unit && h->ops[i + c].unit;
+                    bmax *= std::max(1.0, h->ops[i + c].growth);
+                }
+                const int split_exp = unit ? split_exponent(bmax) : kNoSplit;
                 TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, stage_t, from_e0,
                                     last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused,
-                                    track ? h->support : ~0ull, track && h->garbage, &pmask, &visited));
+                                    track ? h->support : ~0ull, track && h->garbage, &pmask, &visited,
+                                    split_exp));
+                h->stage_forms[split_exp != kNoSplit ? 0 : 1] += 1;
                 h->e0_pending = false;
                 if (track) {
                     // the other tile positions were zero and stay zero
@@ -245,9 +302,11 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
                     double f = 0.0, fi = 0.0;
+                    // issued per amplitude: 3 real products (fp32 3M form), or
+                    // 4 real products x 3 split terms (fp16), 2 2^k flops each
                     for (int c = 0; c < cnt; ++c) {
                         f += block_flops_alg(ks[c]);
-                        fi += 6.0 * (double)(1 << ks[c]);
+                        fi += (split_exp != kNoSplit ? 24.0 : 6.0) * (double)(1 << ks[c]);
                     }
                     // from |0...0> nothing is read; amplitudes on positions
                     // not reached yet are taken as zero, not read
@@ -714,6 +773,44 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
     return tier_pass_pageable(h, write_back, std::forward<F>(visit));
 }
 
+// An amplitude bound for a resident state whose bound is unknown (its
+// buffer was written by the caller): its norm, an FP64 sum of |psi|^2 on the
+// device (one read pass and a host wait), and from it the bound before every
+// queued op.  Only when a staged pass of the queue could take the split form.
+int measure_bound(sv_state* h, const WorkBufs* wb)
+{
+    if (h->tier || !h->split || h->dtype != 0 || h->stage_t < 9 || h->mfma_min_k != 4 || h->ops.empty() ||
+        std::isfinite(h->ops[0].bound_before))
+        return SV_OK;
+    bool stageable = false;
+    for (const Op& op : h->ops) stageable = stageable || (op.kind == OP_DENSE && (op.k == 4 || op.k == 5));
+    if (!stageable) return SV_OK;
+    double* part;
+    double* small;
+    if (wb) {
+        part = (double*)wb->part;
+        small = (double*)wb->small;
+    } else {
+        const int rc = ensure_dev(h, &h->d_part, &h->d_part_cap, kPartDoubles * sizeof(double));
+        if (rc) return rc;
+        part = (double*)h->d_part;
+        small = (double*)h->d_small;
+    }
+    int nb = 0;
+    TRY(h, launch_norm_partials(h->stream, h->dev, h->dtype, h->n, part, &nb));
+    TRY(h, launch_finish_sum(h->stream, part, nb, 1, small));
+    double nrm2 = HUGE_VAL;
+    TRY(h, hipMemcpyAsync(&nrm2, small, sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    TRY(h, hipStreamSynchronize(h->stream));
+    double b = std::isfinite(nrm2) ? std::sqrt(nrm2) * (1.0 + 1e-6) : HUGE_VAL;
+    for (Op& op : h->ops) {
+        op.bound_before = b;
+        b *= op.growth;
+    }
+    h->amp_bound = b;
+    return SV_OK;
+}
+
 int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr, const WorkBufs* wb = nullptr)
 {
     if (norm_blocks) *norm_blocks = 0;
@@ -721,6 +818,8 @@ int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr, c
     int rc = upload_arena(h, wb);
     if (rc) return rc;
     if (!h->tier) {
+        rc = measure_bound(h, wb);
+        if (rc) return rc;
         void* cur = h->dev;
         rc = run_ops(h, h->stream, &cur, h->scratch, h->n, 0, norm_out, norm_blocks);
         if (rc) return rc;
@@ -972,6 +1071,8 @@ int create_common(int n, uint64_t slice_mask, int dtype, void* stream, void* ext
         e = launch_init(h->stream, h->dev, h->dtype, (uint64_t)1 << n, true);
         if (e != hipSuccess) { release(h); return fail_dev(nullptr, "init kernel", e); }
         h->support = 0;              // |0...0>, written in full: nothing stale
+    } else {
+        h->amp_bound = HUGE_VAL;     // the caller's amplitudes
     }
     h->d_small = pool_alloc(64, false, nullptr);
     if (!h->d_small) {
@@ -1158,6 +1259,9 @@ int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix)
     op.kind = OP_DENSE;
     op.k = k;
     for (int j = 0; j < k; ++j) op.pos[j] = h->pos[qubits[j]];
+    op.growth = op_growth(matrix, k, h->amp, &op.unit);
+    op.bound_before = h->amp_bound;
+    h->amp_bound *= op.growth;
     int minp = 64;
     for (int j = 0; j < k; ++j) minp = std::min(minp, op.pos[j]);
     if (h->dtype == 0 && h->mfma_min_k == 4 && k < 4 && minp < 4 && h->L >= 8) {
@@ -1201,6 +1305,20 @@ int apply_diag(sv_handle h, int m, const int* qubits, const void* phases)
     op.kind = OP_DIAG;
     op.k = m;
     for (int j = 0; j < m; ++j) op.pos[j] = h->pos[qubits[j]];
+    {
+        // a diagonal op scales amplitudes by its entries
+        double lo = HUGE_VAL, hi = 0.0;
+        for (size_t i = 0; i < ((size_t)1 << m); ++i) {
+            const double a = h->amp == 8 ? std::hypot((double)((const float*)phases)[2 * i], (double)((const float*)phases)[2 * i + 1])
+                                         : std::hypot(((const double*)phases)[2 * i], ((const double*)phases)[2 * i + 1]);
+            lo = std::min(lo, a);
+            hi = std::max(hi, a);
+        }
+        op.growth = std::isfinite(hi) ? hi : HUGE_VAL;
+        op.unit = hi - 1.0 <= kUnitTol && 1.0 - lo <= kUnitTol;
+    }
+    op.bound_before = h->amp_bound;
+    h->amp_bound *= op.growth;
     op.off = push_arena(h, phases, ((size_t)1 << m) * h->amp);
     h->ops.push_back(op);
     if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
@@ -1423,6 +1541,11 @@ int sv_checkpoint(sv_handle h, int64_t tag)
         if (j == h->file_maps.size()) return set_err(h, SV_EIO, "internal: tier file without a path");
         meta += h->file_paths[j].substr(h->file_paths[j].rfind('/') + 1) + "\n";
     }
+    {
+        char b[64];
+        std::snprintf(b, sizeof b, "bound %.17g\n", h->amp_bound);
+        meta += b;
+    }
     // write, flush and rename: a crash leaves the previous checkpoint or this one whole
     const std::string final_path = h->tier_dir + "/" + kCheckpointName;
     const std::string tmp = final_path + ".tmp";
@@ -1503,9 +1626,18 @@ int open_state_files(const char* dir, void* hip_stream, sv_handle* out, int64_t*
         ok = !w.empty() && w.find('/') == std::string::npos && w != "." && w != "..";
         rs.names.push_back(w);
     }
+    // the amplitude bound (infinite when absent or unreadable)
+    double bound = HUGE_VAL;
+    if (ok && word() == "bound") {
+        const std::string w = word();
+        char* end = nullptr;
+        const double v = std::strtod(w.c_str(), &end);
+        if (!w.empty() && !*end && v >= 0.0) bound = v;
+    }
     if (!ok) return set_err(nullptr, SV_EINVAL, "malformed checkpoint " + path);
     const int rc = create_common((int)n, mask, (int)dtype | SV_FLAG_TIER, hip_stream, nullptr, 0, out, dir, &rs);
     if (rc) return rc;
+    (*out)->amp_bound = bound;
     if (tag) *tag = t;
     return SV_OK;
 }
@@ -1524,6 +1656,7 @@ int sv_reset(sv_handle h)
     CHECK_HANDLE(h);
     h->ops.clear();
     h->arena.clear();
+    h->amp_bound = 1.0;
     if (!h->tier) {
         h->e0_pending = true;        // written by the first pass or on demand
         h->support = h->sparse_start ? 0 : ~0ull;
@@ -1577,6 +1710,7 @@ int sv_device_buffer(sv_handle h, void** dev, size_t* bytes)
         if (rc) return rc;
     }
     h->support = ~0ull;              // the caller may write it
+    if (!h->tier) h->amp_bound = HUGE_VAL;
     *dev = h->tier ? nullptr : h->dev;
     *bytes = h->tier ? 0 : ((size_t)1 << h->n) * h->amp;
     return SV_OK;
@@ -1600,6 +1734,7 @@ int sv_set_option(sv_handle h, int option, int64_t value)
             return SV_OK;
         case SV_OPT_FAIL_IO: h->fail_io_at = value; return SV_OK;
         case SV_OPT_SPARSE_START: h->sparse_start = value != 0; return SV_OK;
+        case SV_OPT_SPLIT: h->split = value != 0; return SV_OK;
         case SV_OPT_KEEP_FILES:
             if (h->file_fds.empty()) return set_err(h, SV_EINVAL, "SV_OPT_KEEP_FILES: the tier is not in files");
             h->keep_files = value != 0;
@@ -1612,6 +1747,17 @@ int sv_counters(sv_handle h, int64_t counters[8])
 {
     if (!h || !counters) return SV_EINVAL;
     for (int i = 0; i < 8; ++i) counters[i] = h->counters[i];
+    return SV_OK;
+}
+
+int sv_stage_forms(sv_handle h, int64_t passes[2], double* amp_bound)
+{
+    if (!h) return SV_EINVAL;
+    if (passes) {
+        passes[0] = h->stage_forms[0];
+        passes[1] = h->stage_forms[1];
+    }
+    if (amp_bound) *amp_bound = h->amp_bound;
     return SV_OK;
 }
 

@@ -44,6 +44,7 @@ struct Launch {
     // support's tiles; kind 5 clears outside `support`
     bool from_e0 = false, garbage = false;
     uint64_t support = ~0ull;
+    int split_exp = kNoSplit;                 // staged: split-fp16 tile scale exponent
 };
 
 }  // namespace
@@ -54,6 +55,9 @@ struct sv_batch_s {
     // recorded launches address both
     std::vector<void*> devs;
     std::vector<std::vector<int>> orders;
+    // per state: the product of its ops' growth factors (the amplitude
+    // bound advances by it at every launch)
+    std::vector<double> gprod;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* d_arena = nullptr;
@@ -120,7 +124,7 @@ hipError_t enqueue_all(sv_batch_s* b, const std::vector<Launch>& launches)
             for (int c = 0; c < L.cnt; ++c) pp[c] = L.spos[c];
             int t = 0;
             e = launch_stage(b->stream, L.psi, L.nloc, L.cnt, L.ks, pp, L.smat, L.t_max, L.from_e0, nullptr,
-                             nullptr, &t, L.support, L.garbage);
+                             nullptr, &t, L.support, L.garbage, nullptr, nullptr, L.split_exp);
         }
         if (e != hipSuccess) return e;
     }
@@ -150,8 +154,14 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
     if (!b) return berr(nullptr, SV_ENOMEM, "host allocation failed");
     b->states.assign(handles, handles + count);
     for (int i = 0; i < count; ++i) {
-        b->devs.push_back(handles[i]->dev);
-        b->orders.push_back(handles[i]->order);
+        sv_state* h = handles[i];
+        b->devs.push_back(h->dev);
+        b->orders.push_back(h->order);
+        double gp = 1.0;
+        for (const Op& op : h->ops) gp *= op.growth;
+        b->gprod.push_back(gp);
+        // the queued ops run at every launch, not now
+        if (!h->ops.empty()) h->amp_bound = h->ops[0].bound_before;
     }
     hipError_t e;
     if (hip_stream) {
@@ -219,6 +229,7 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
     // whether |0...0> is still unwritten and whether memory outside the
     // support still holds older values
     std::vector<uint64_t> rs_support(count, 0);
+    std::vector<double> rs_bound(count, 1.0);     // amplitude bound through the ops, from |0...0>
     std::vector<char> rs_e0(count, 1), rs_garbage(count, 1);
     auto rs_full = [&](int i) { return ((uint64_t)1 << handles[i]->n) - 1; };
     auto rs_materialize = [&](int i) {
@@ -258,13 +269,22 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
                 L.nloc = h->n;
                 L.cnt = w.cnt;
                 L.t_max = h->stage_t;
+                bool unit = h->split;
+                double bmax = rs_bound[i];
                 for (int c = 0; c < w.cnt; ++c) {
                     L.ks[c] = w.ks[c];
                     for (int u = 0; u < w.ks[c]; ++u) L.spos[c][u] = w.op[c].pos[u];
                     L.smat[c] = ab + w.op[c].off;
+                    unit = unit && w.op[c].unit;
+                    bmax *= std::max(1.0, w.op[c].growth);
+                    rs_bound[i] *= w.op[c].growth;
                 }
                 b->launches.push_back(L);
+                // from a reset the amplitude bound is known (1): that variant
+                // takes the split-fp16 form, the other the fp32 form
                 Launch R = L;
+                R.split_exp = unit ? split_exponent(bmax) : kNoSplit;
+                h->stage_forms[R.split_exp != kNoSplit ? 0 : 1] += 1;
                 R.from_e0 = rs_e0[i] != 0;
                 R.support = rs_support[i];
                 R.garbage = rs_garbage[i] != 0;
@@ -283,6 +303,7 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
                 h->counters[7] += w.cnt;
                 continue;
             }
+            rs_bound[i] *= w.op->growth * (w.fold ? w.fold->growth : 1.0);
             // a plain sweep needs every amplitude in memory
             rs_materialize(i);
             rs_support[i] = ~0ull;
@@ -418,6 +439,10 @@ int sv_batch_launch(sv_batch b)
     if (e != hipSuccess) {
         for (sv_state* h : b->states) { h->poisoned = true; h->err = "batch launch failed"; }
         return berr(b, SV_EDEVICE, std::string("batch launch failed: ") + hipGetErrorString(e));
+    }
+    for (size_t i = 0; i < b->states.size(); ++i) {
+        sv_state* h = b->states[i];
+        h->amp_bound = (reset ? 1.0 : h->amp_bound) * b->gprod[i];
     }
     if (hipEventRecord(b->ev_done, b->stream) != hipSuccess) return berr(b, SV_EDEVICE, "event record failed");
     for (sv_state* h : b->states)

@@ -122,10 +122,19 @@ hipError_t stage_prepare();
 // Widest tile the device runs: 14, or 13 where a workgroup cannot have the
 // whole LDS of a CU.
 int stage_max_t();
+// split_exp: kNoSplit = fp32 matrix-core form; otherwise the split-fp16
+// form with the tile scaled by 2^split_exp in LDS (-100..100).
+constexpr int kNoSplit = -1000;
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out, uint64_t support = ~0ull, bool garbage = false,
-                        uint64_t* tile_mask_out = nullptr, uint64_t* amps_out = nullptr);
+                        uint64_t* tile_mask_out = nullptr, uint64_t* amps_out = nullptr,
+                        int split_exp = kNoSplit);
+// Exponent e of the split-fp16 form's tile scale 2^e for a run whose
+// blocks are all unitary and whose state norm stays below bound: the
+// largest e with 2^e bound <= 2^15 (-100..100); kNoSplit when bound is not
+// finite (the run takes the fp32 form).
+int split_exponent(double bound);
 
 // Amplitudes a staged pass with these blocks visits (launch_stage's tile
 // choice for this support); 0 when the run does not fit a tile.

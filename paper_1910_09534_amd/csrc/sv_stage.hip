@@ -22,6 +22,7 @@
 // workgroup.  Every workgroup runs the same number of tile iterations, so
 // the barriers are reached uniformly.
 #include <atomic>
+#include <cmath>
 
 #include "sv_device.h"
 
@@ -56,6 +57,7 @@ struct StageK {
     int nops;
     int from_e0;                             // 1: input is |0...0>, not read
     double* norm_out;                        // non-null: per-workgroup FP64 sum of |psi|^2 of the result
+    float split_scale, split_unscale;        // split form: the tile's scale in LDS (a power of two) and its inverse
     int op_k[kStageMaxOps];
     int op_bits[kStageMaxOps][kMaxDense];    // tile-local bit of matrix bit j
     int op_lowmask_bits[kStageMaxOps][kMaxDense];  // the same bits, ascending
@@ -199,6 +201,286 @@ __device__ __forceinline__ void stage_block(const StageK& a, int o, const f4* __
     }
 }
 
+// ---- split-fp16 form -------------------------------------------------------
+// Every real product of the block runs on the fp16 matrix cores with single-
+// precision accuracy: each fp32 operand x is split into x_hi = f16(x) and
+// x_lo = f16(x - x_hi) (both rounded to nearest), so x_hi + x_lo carries 22
+// significant bits, and A x = A_hi x_hi + A_hi x_lo + A_lo x_hi up to a term
+// of relative size 2^-22; the fp16 products are exact and accumulate in fp32
+// (the split-precision scheme of Markidis et al. 2018 and Ootomo & Yokota
+// 2022, without their rescaling of the low parts: the tile is parked in LDS
+// scaled by a power of two chosen from a bound on the state's norm, so that
+// every amplitude stays below 2^15 and typical ones lie far above the fp16
+// subnormal range; the blocks are unitary, so their entries are at most 1).
+// Complex products use four real ones: Re y = Ar xr - Ai xi and
+// Im y = Ai xr + Ar xi.
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u2 __attribute__((ext_vector_type(2)));
+
+// f16(a), f16(b) packed (low half a), rounded to nearest even
+__device__ __forceinline__ uint32_t pk_hi(float a, float b)
+{
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 v = {(_Float16)a, (_Float16)b};
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+// f16(a - hi.lo), f16(b - hi.hi) packed: each residual is formed exactly in
+// fp32 inside the mixed-precision fma and rounded once to fp16
+__device__ __forceinline__ uint32_t pk_lo(float a, float b, uint32_t hi)
+{
+    uint32_t r;
+    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
+        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+        : "=&v"(r)
+        : "v"(hi), "v"(a), "v"(b));
+    return r;
+}
+
+__device__ __forceinline__ h8 neg8(h8 v)
+{
+    return __builtin_bit_cast(h8, __builtin_bit_cast(u4, v) ^ 0x80008000u);
+}
+
+__device__ __forceinline__ f4 mma(h8 a, h8 b, f4 c)
+{
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+}
+
+// Operand fragments of one block for the split form.  k = 5, per 16-row
+// block rb: Ar_hi, Ar_lo, Ai_hi, Ai_lo, -Ai_hi, -Ai_lo, element e of lane
+// (i, g) = matrix entry (16 rb + i, 4 e + g).  k = 4 (16 columns, so the
+// real and imaginary columns share one 32-deep product): [Ar | -Ai] and
+// [Ai | Ar], hi and lo, element e < 4 = entry (i, 4 e + g) of the first
+// part, e >= 4 of the second.
+template <int K>
+struct SplitA;
+template <>
+struct SplitA<5> {
+    h8 v[2][6];
+};
+template <>
+struct SplitA<4> {
+    h8 v[4];
+};
+
+// LDS image of a block's operands (what the kernel stages): k = 5: h8
+// [(rb * 4 + p) * 64 + lane], p = Ar_hi, Ar_lo, Ai_hi, Ai_lo; k = 4: h4
+// [p * 64 + lane].  Both take 8 bytes per matrix entry, as the fp32 form.
+__device__ __forceinline__ void split_load(SplitA<5>& A, const void* As, int lane)
+{
+    const h8* a8 = (const h8*)As;
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb) {
+#pragma unroll
+        for (int p = 0; p < 4; ++p) A.v[rb][p] = a8[(rb * 4 + p) * 64 + lane];
+        A.v[rb][4] = neg8(A.v[rb][2]);
+        A.v[rb][5] = neg8(A.v[rb][3]);
+    }
+}
+
+__device__ __forceinline__ void split_load(SplitA<4>& A, const void* As, int lane)
+{
+    const u2* a4 = (const u2*)As;
+    const u2 rh = a4[0 * 64 + lane], rl = a4[1 * 64 + lane], ih = a4[2 * 64 + lane], il = a4[3 * 64 + lane];
+    const uint32_t sg = 0x80008000u;
+    A.v[0] = __builtin_bit_cast(h8, u4{rh.x, rh.y, ih.x ^ sg, ih.y ^ sg});
+    A.v[1] = __builtin_bit_cast(h8, u4{rl.x, rl.y, il.x ^ sg, il.y ^ sg});
+    A.v[2] = __builtin_bit_cast(h8, u4{ih.x, ih.y, rh.x, rh.y});
+    A.v[3] = __builtin_bit_cast(h8, u4{il.x, il.y, rl.x, rl.y});
+}
+
+// NU units of a k = 5 block, split form (slots as in stage_units)
+template <int NU>
+__device__ __forceinline__ void split_units(const SplitA<5>& A, const int (&sx)[8], const int (&sy)[8], int cx,
+                                            int cy, const int (&su)[NU], float2* __restrict__ T)
+{
+    float2 x[NU][8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m)
+#pragma unroll
+        for (int q = 0; q < NU; ++q) x[q][m] = T[(su[q] + sx[m]) + cx];
+    h8 xrh[NU], xrl[NU], xih[NU], xil[NU];
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        u4 rh, rl, ih, il;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+            const float2 a = x[q][2 * w], b = x[q][2 * w + 1];
+            rh[w] = pk_hi(a.x, b.x);
+            ih[w] = pk_hi(a.y, b.y);
+            rl[w] = pk_lo(a.x, b.x, rh[w]);
+            il[w] = pk_lo(a.y, b.y, ih[w]);
+        }
+        xrh[q] = __builtin_bit_cast(h8, rh);
+        xrl[q] = __builtin_bit_cast(h8, rl);
+        xih[q] = __builtin_bit_cast(h8, ih);
+        xil[q] = __builtin_bit_cast(h8, il);
+    }
+    f4 re[NU][2], im[NU][2];
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+    // small terms first; 4 NU independent chains interleave
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][1], xrh[q], z);
+            im[q][rb] = mma(A.v[rb][3], xrh[q], z);
+        }
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][0], xrl[q], re[q][rb]);
+            im[q][rb] = mma(A.v[rb][2], xrl[q], im[q][rb]);
+        }
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][5], xih[q], re[q][rb]);
+            im[q][rb] = mma(A.v[rb][1], xih[q], im[q][rb]);
+        }
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][4], xil[q], re[q][rb]);
+            im[q][rb] = mma(A.v[rb][0], xil[q], im[q][rb]);
+        }
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][0], xrh[q], re[q][rb]);
+            im[q][rb] = mma(A.v[rb][2], xrh[q], im[q][rb]);
+        }
+#pragma unroll
+    for (int q = 0; q < NU; ++q)
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) {
+            re[q][rb] = mma(A.v[rb][4], xih[q], re[q][rb]);
+            im[q][rb] = mma(A.v[rb][0], xih[q], im[q][rb]);
+        }
+#pragma unroll
+    for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v)
+#pragma unroll
+            for (int q = 0; q < NU; ++q)
+                T[(su[q] + sy[4 * rb + v]) + cy] = float2{re[q][rb][v], im[q][rb][v]};
+}
+
+// NU units of a k = 4 block, split form: operand element e < 4 is Re x of
+// column 4 e + g, e >= 4 Im x of column 4 (e - 4) + g
+template <int NU>
+__device__ __forceinline__ void split_units(const SplitA<4>& A, const int (&sx)[4], const int (&sy)[4], int cx,
+                                            int cy, const int (&su)[NU], float2* __restrict__ T)
+{
+    float2 x[NU][4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m)
+#pragma unroll
+        for (int q = 0; q < NU; ++q) x[q][m] = T[(su[q] + sx[m]) + cx];
+    h8 xh[NU], xl[NU];
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        u4 hh, ll;
+        hh[0] = pk_hi(x[q][0].x, x[q][1].x);
+        hh[1] = pk_hi(x[q][2].x, x[q][3].x);
+        hh[2] = pk_hi(x[q][0].y, x[q][1].y);
+        hh[3] = pk_hi(x[q][2].y, x[q][3].y);
+        ll[0] = pk_lo(x[q][0].x, x[q][1].x, hh[0]);
+        ll[1] = pk_lo(x[q][2].x, x[q][3].x, hh[1]);
+        ll[2] = pk_lo(x[q][0].y, x[q][1].y, hh[2]);
+        ll[3] = pk_lo(x[q][2].y, x[q][3].y, hh[3]);
+        xh[q] = __builtin_bit_cast(h8, hh);
+        xl[q] = __builtin_bit_cast(h8, ll);
+    }
+    f4 re[NU], im[NU];
+    const f4 z = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        re[q] = mma(A.v[1], xh[q], z);
+        im[q] = mma(A.v[3], xh[q], z);
+    }
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        re[q] = mma(A.v[0], xl[q], re[q]);
+        im[q] = mma(A.v[2], xl[q], im[q]);
+    }
+#pragma unroll
+    for (int q = 0; q < NU; ++q) {
+        re[q] = mma(A.v[0], xh[q], re[q]);
+        im[q] = mma(A.v[2], xh[q], im[q]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+#pragma unroll
+        for (int q = 0; q < NU; ++q) T[(su[q] + sy[v]) + cy] = float2{re[q][v], im[q][v]};
+}
+
+// one block on the LDS tile, split form (slot offsets as in stage_block)
+template <int K, int NT>
+__device__ __forceinline__ void split_block(const StageK& a, int o, const void* As, float2* __restrict__ T, int wave)
+{
+    constexpr int NE = (1 << K) / 4;
+    const int lane = threadIdx.x & 63;
+    constexpr int nw = NT / 64;
+    const int j = lane & 15, h = lane >> 4;
+    int bit[K], low[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        bit[u] = 1 << a.op_bits[o][u];
+        low[u] = (1 << a.op_lowmask_bits[o][u]) - 1;
+    }
+    SplitA<K> A;
+    split_load(A, As, lane);
+    const int lj = lslot(spread<K>(j, low));
+    const int cx = lj + lslot(((h & 1) ? bit[0] : 0) | ((h & 2) ? bit[1] : 0));
+    const int cy = lj + lslot(((h & 1) ? bit[2] : 0) | ((h & 2) ? bit[3] : 0));
+    int sx[NE], sy[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        int off = 0;
+#pragma unroll
+        for (int u = 2; u < K; ++u)
+            if ((m >> (u - 2)) & 1) off |= bit[u];
+        sx[m] = lslot(off);
+    }
+#pragma unroll
+    for (int rb = 0; rb < NE / 4; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int off = (v & 1) ? bit[0] : 0;
+            off |= (v & 2) ? bit[1] : 0;
+#pragma unroll
+            for (int u = 4; u < K; ++u)
+                if ((rb >> (u - 4)) & 1) off |= bit[u];
+            sy[4 * rb + v] = lslot(off);
+        }
+    // units wave, wave + nw, ... in groups of NG (4 for k = 4, whose units
+    // are short, 2 for k = 5); units / nw is a power of two, so a wave runs
+    // whole groups or fewer than NG units one by one
+    constexpr int NG = K == 4 ? 4 : 2;
+    const int units = 1 << (a.t - K - 4);
+    if (units >= NG * nw) {
+        for (int unit = wave; unit < units; unit += NG * nw) {
+            int su[NG];
+#pragma unroll
+            for (int q = 0; q < NG; ++q) su[q] = lslot(spread<K>((unit + q * nw) * 16, low));
+            split_units<NG>(A, sx, sy, cx, cy, su, T);
+        }
+    } else {
+        for (int unit = wave; unit < units; unit += nw) {
+            const int su[1] = {lslot(spread<K>(unit * 16, low))};
+            split_units<1>(A, sx, sy, cx, cy, su, T);
+        }
+    }
+}
+
 // TW: tile width t (9..12), PER = 2^(t-8) elements per lane.  WIDE: the
 // lane part of an element's address needs more than 32 bits of byte offset
 // (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
@@ -216,7 +498,7 @@ __host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
     return r;
 }
 
-template <int TW, bool WIDE, bool ZERO>
+template <int TW, bool WIDE, bool ZERO, bool SPLIT>
 __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restrict__ psi, StageK a)
 {
     // lanes NT (2^LB), PER amplitudes per lane in PER / 2 adjacent pairs
@@ -226,8 +508,28 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
     float2* T = (float2*)smem;                                   // tile, padded
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     f4* Abase = smem + ((lslot(1 << TW) * 8 + 15) / 16);          // operand matrices
-    // stage every block's three real matrices in operand order
-    for (int o = 0; o < a.nops; ++o) {
+    // stage every block's operand matrices in operand order
+    for (int o = 0; o < a.nops && SPLIT; ++o) {
+        const int k = a.op_k[o];
+        const float2* mat = a.op_mat[o];
+        _Float16* dst = (_Float16*)((float*)Abase + a.op_aoff[o]);
+        const int D = 1 << k, NA = 4 * D * D;
+        for (int i = threadIdx.x; i < NA; i += NT) {
+            int e, l, p, R;
+            if (k == 5) {
+                e = i & 7, l = (i >> 3) & 63, p = (i >> 9) & 3;
+                R = 16 * (i >> 11) + (l & 15);
+            } else {
+                e = i & 3, l = (i >> 2) & 63, p = i >> 8;
+                R = l & 15;
+            }
+            const float2 m = mat[R * D + 4 * e + (l >> 4)];
+            const float v = p < 2 ? m.x : m.y;
+            const _Float16 hv = (_Float16)v;
+            dst[i] = (p & 1) ? (_Float16)(v - (float)hv) : hv;
+        }
+    }
+    for (int o = 0; o < a.nops && !SPLIT; ++o) {
         const int k = a.op_k[o];
         const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 2 * RB * KQ * 256;
         float* dst = (float*)(Abase) + a.op_aoff[o];
@@ -273,6 +575,10 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
     auto parked = [&](int m, float2& e0, float2& e1) {
         e0 = float2{xr[m].x, xr[m].y};
         e1 = float2{xr[m].z, xr[m].w};
+        if (SPLIT) {
+            e0.x *= a.split_scale, e0.y *= a.split_scale;
+            e1.x *= a.split_scale, e1.y *= a.split_scale;
+        }
         if (ZERO) {
             const uint32_t pi = (uint32_t)((threadIdx.x << 1) + 2 * NT * m);
             if (pi & a.newmask_t) e0 = float2{0.f, 0.f};
@@ -311,8 +617,13 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
         __builtin_amdgcn_s_setprio(0);
         for (int o = 0; o < a.nops; ++o) {
             const f4* As = (const f4*)((const float*)Abase + a.op_aoff[o]);
-            if (a.op_k[o] == 5) stage_block<5, NT>(a, o, As, T, wave);
-            else stage_block<4, NT>(a, o, As, T, wave);
+            if (SPLIT) {
+                if (a.op_k[o] == 5) split_block<5, NT>(a, o, As, T, wave);
+                else split_block<4, NT>(a, o, As, T, wave);
+            } else {
+                if (a.op_k[o] == 5) stage_block<5, NT>(a, o, As, T, wave);
+                else stage_block<4, NT>(a, o, As, T, wave);
+            }
             __syncthreads();
         }
         // Each lane parks the next tile's pairs in the very slots it has just
@@ -322,7 +633,11 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
         auto store_park = [&](auto park_next, auto sum_norm) {
 #pragma unroll
             for (int m = 0; m < PP; ++m) {
-                const float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
+                float2 v0 = T[ls + ES2 * m], v1 = T[ls + ES2 * m + 1];
+                if (SPLIT) {
+                    const float r = a.split_unscale;
+                    v0.x *= r, v0.y *= r, v1.x *= r, v1.y *= r;
+                }
                 if constexpr (decltype(park_next)::value) {
                     float2 e0, e1;
                     parked(m, e0, e1);
@@ -375,12 +690,14 @@ int stage_lds_bytes(int t, int nops, const int* ks)
 
 // the variant for a tile of t positions (9..14), 64-bit lane offsets, and
 // zeroing of stale elements
-static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
+static void (*stage_kernel(int t, bool wide, bool zero, bool split))(float2*, StageK)
 {
-#define SV_STAGE_CASE(T)                                                     \
-    case T:                                                                  \
-        return wide ? (zero ? k_stage<T, true, true> : k_stage<T, true, false>) \
-                    : (zero ? k_stage<T, false, true> : k_stage<T, false, false>);
+#define SV_STAGE_W(T, W)                                                                         \
+    (zero ? (split ? k_stage<T, W, true, true> : k_stage<T, W, true, false>)                     \
+          : (split ? k_stage<T, W, false, true> : k_stage<T, W, false, false>))
+#define SV_STAGE_CASE(T) \
+    case T:              \
+        return wide ? SV_STAGE_W(T, true) : SV_STAGE_W(T, false);
     switch (t) {
         SV_STAGE_CASE(9)
         SV_STAGE_CASE(10)
@@ -390,6 +707,7 @@ static void (*stage_kernel(int t, bool wide, bool zero))(float2*, StageK)
         SV_STAGE_CASE(14)
     }
 #undef SV_STAGE_CASE
+#undef SV_STAGE_W
     return nullptr;
 }
 
@@ -402,15 +720,15 @@ hipError_t stage_prepare()
     static std::atomic<bool> done{false};
     if (done) return hipSuccess;
     for (int t = 9; t <= 13; ++t)
-        for (int v = 0; v < 4; ++v) {
-            void (*k)(float2*, StageK) = stage_kernel(t, v & 1, v & 2);
+        for (int v = 0; v < 8; ++v) {
+            void (*k)(float2*, StageK) = stage_kernel(t, v & 1, v & 2, v & 4);
             const hipError_t e = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize,
                                                      kStageMaxLds);
             if (e != hipSuccess) return e;
         }
     bool ok14 = true;
-    for (int v = 0; v < 4 && ok14; ++v) {
-        void (*k)(float2*, StageK) = stage_kernel(14, v & 1, v & 2);
+    for (int v = 0; v < 8 && ok14; ++v) {
+        void (*k)(float2*, StageK) = stage_kernel(14, v & 1, v & 2, v & 4);
         ok14 = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds14) ==
                hipSuccess;
     }
@@ -418,6 +736,16 @@ hipError_t stage_prepare()
     g_stage14 = ok14;
     done = true;
     return hipSuccess;
+}
+
+int split_exponent(double bound)
+{
+    if (!(bound >= 0.0) || !std::isfinite(bound)) return kNoSplit;
+    if (bound < 0x1p-85) return 100;
+    int e = 15 - (int)std::ceil(std::log2(bound));
+    while (std::ldexp(bound, e) > 32768.0) --e;
+    while (e < 100 && std::ldexp(bound, e + 1) <= 32768.0) ++e;
+    return e < -100 ? kNoSplit : (e > 100 ? 100 : e);
 }
 
 int stage_max_t()
@@ -482,7 +810,7 @@ uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out, uint64_t support, bool garbage, uint64_t* tile_mask_out,
-                        uint64_t* amps_out)
+                        uint64_t* amps_out, int split_exp)
 {
     int P[64];
     const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P);
@@ -492,6 +820,10 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.nops = nops;
     a.from_e0 = from_e0 ? 1 : 0;
     a.norm_out = norm_out;
+    const bool split = split_exp != kNoSplit;
+    if (split && (split_exp < -100 || split_exp > 100)) return hipErrorInvalidValue;
+    a.split_scale = split ? std::ldexp(1.0f, split_exp) : 1.0f;
+    a.split_unscale = split ? std::ldexp(1.0f, -split_exp) : 1.0f;
     // tiles: only those whose id bits lie on positions that may be non-zero
     // (support); the other tiles hold zeros and stay zero
     uint64_t pmask = 0;
@@ -539,7 +871,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     uint64_t dl_max = 0;
     for (int b = 0; b < lb; ++b) dl_max |= a.dep_lane[b];
     const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
-    void (*kern)(float2*, StageK) = stage_kernel(t, wide, a.newmask_t != 0);
+    void (*kern)(float2*, StageK) = stage_kernel(t, wide, a.newmask_t != 0, split);
     if (!kern) return hipErrorInvalidValue;
     {
         const hipError_t e = stage_prepare();

@@ -21,7 +21,22 @@ struct Op {
     int pos[kMaxDiag] = {};    // physical positions at queue time
     size_t off = 0;            // arena offset of matrix / table
     BitRuns runs;              // OP_LPERM: destination -> source over local bits
+    // bound on the factor by which the op can raise the state's norm (its
+    // largest singular value), whether it is unitary within kUnitTol, and
+    // the state's amplitude bound before it (at queue time)
+    double growth = 1.0;
+    bool unit = true;
+    double bound_before = 1.0;
 };
+
+// Unitarity tolerance of an op (largest entry of |M^H M - I|): staged runs
+// of such blocks may take the split-fp16 form (entries at most ~1, largest
+// singular value ~1).
+constexpr double kUnitTol = 1e-3;
+
+// Largest-singular-value bound of a k-qubit matrix (row-major complex64 if
+// amp == 8, else complex128) and whether it is unitary within kUnitTol.
+double op_growth(const void* m, int k, size_t amp, bool* unit);
 
 // Writes |0...0> into a resident state whose reset was deferred (no-op
 // otherwise); on the handle's stream.
@@ -112,6 +127,7 @@ struct sv_state {
     bool timing = false, fold = true;
     int mfma_min_k = 4;
     int stage_t = 13;            // widest tile of staged multi-block passes (0: off)
+    bool split = true;           // staged passes in the split-fp16 form where the amplitude bound allows
     bool e0_pending = false;     // resident state is |0...0> but not yet written (sv_reset)
     // Resident states after sv_reset: every amplitude whose index has a bit
     // outside `support` is zero (the positions no operation has touched since
@@ -139,6 +155,12 @@ struct sv_state {
     double tk_issued[2] = {0.0, 0.0};
     double tk_bytes[2] = {0.0, 0.0};
     int64_t counters[8] = {};
+    // bound on the norm of the state (so on every |amplitude|): 1 after
+    // creation or sv_reset, times each applied op's growth; infinite once
+    // the device buffer has been handed out or when a restored tier does not
+    // state it
+    double amp_bound = 1.0;
+    int64_t stage_forms[2] = {};  // staged passes run in the split-fp16 / fp32 form
 
     bool poisoned = false;
     std::string err;

@@ -21,6 +21,7 @@ SV_FLAG_TIER, SV_FLAG_KEEP, SV_FLAG_PAGEABLE, SV_FLAG_STORE32 = 0x100, 0x200, 0x
 SV_OPT_TIMING, SV_OPT_MFMA, SV_OPT_FOLD_DIAG, SV_OPT_SLOTS, SV_OPT_STAGE, SV_OPT_FAIL_IO = 1, 2, 3, 4, 5, 6
 SV_OPT_SPARSE_START = 7
 SV_OPT_KEEP_FILES = 8
+SV_OPT_SPLIT = 9
 SV_OP_FUSED, SV_OP_DIAG = 0, 1
 
 ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_EDEVICE",
@@ -28,7 +29,7 @@ ERROR_NAMES = {SV_EINVAL: "SV_EINVAL", SV_ENOMEM: "SV_ENOMEM", SV_EDEVICE: "SV_E
 
 EXPORTS = ("create_state", "create_state_ext", "create_state_files", "destroy_state", "apply_fused", "apply_diag",
            "apply_ops", "permute_qubits", "gather_amplitudes", "reduce_slices", "sync_state", "sv_reset", "last_error",
-           "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_sweep_time",
+           "sv_get_order", "sv_device_buffer", "sv_set_option", "sv_counters", "sv_stage_forms", "sv_sweep_time",
            "sv_sweep_profile", "sv_batch_prepare", "sv_batch_launch", "sv_batch_sync", "sv_batch_info",
            "sv_batch_destroy", "sv_batch_error", "sv_contract", "reduce_slices_noalloc", "sv_checkpoint",
            "open_state_files")
@@ -68,6 +69,7 @@ def load():
     L.sv_device_buffer.argtypes = [P, ctypes.POINTER(P), ctypes.POINTER(SZ)]
     L.sv_set_option.argtypes = [P, I, I64]
     L.sv_counters.argtypes = [P, P]
+    L.sv_stage_forms.argtypes = [P, P, ctypes.POINTER(ctypes.c_double)]
     L.sv_sweep_time.argtypes = [P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(I64)]
     L.sv_sweep_profile.argtypes = [P, P, P, P, P, P]
     L.sv_batch_prepare.argtypes = [I, P, I, P, ctypes.POINTER(P)]
@@ -266,6 +268,15 @@ def device_buffer(h):
 
 def set_option(h, option: int, value: int) -> None:
     _check(lib().sv_set_option(h, option, value), h)
+
+
+def stage_forms(h) -> dict:
+    """Staged passes run in the split-fp16 and fp32 forms since creation,
+    and the state's amplitude bound (sv_stage_forms)."""
+    c = np.zeros(2, dtype=np.int64)
+    b = ctypes.c_double()
+    _check(lib().sv_stage_forms(h, _ptr(c), ctypes.byref(b)))
+    return {"split": int(c[0]), "fp32": int(c[1]), "amp_bound": b.value}
 
 
 def counters(h) -> dict:

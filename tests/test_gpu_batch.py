@@ -36,6 +36,7 @@ def test_batch_equals_alone_and_oracle(graph):
     for c, b, amps, p in zip(circs, bits, res["amps"], plans):
         st = sv.State(c.n, 0, "c64")
         try:
+            sv.set_option(st.h, sv.SV_OPT_STAGE, 0)          # as in the batch: no staged passes
             planner.enqueue(st.h, p, st.dtype)
             alone = st.gather(b)
         finally:

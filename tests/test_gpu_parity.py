@@ -342,7 +342,9 @@ def test_sweep_profile_splits_kinds():
         sv.sync_state(h)
         p = sv.sweep_profile(h)
         assert p["staged"]["count"] == 1 and p["sweep"]["count"] == 1
-        assert p["staged"]["issued"] == 6.0 * (32 + 16 + 32) * (1 << n)
+        # split-fp16 form (unitary blocks, measured bound): 24 2^k per amplitude
+        assert sv.stage_forms(h)["split"] == 1
+        assert p["staged"]["issued"] == 24.0 * (32 + 16 + 32) * (1 << n)
         assert p["staged"]["flops"] == (8.0 * 32 - 2 + 8.0 * 16 - 2 + 8.0 * 32 - 2) * (1 << n)
         assert p["sweep"]["issued"] == 8.0 * 8 * (1 << n)
         assert p["sweep"]["flops"] == (8.0 * 8 - 2) * (1 << n)
