@@ -39,8 +39,10 @@ double sv::op_growth(const void* m, int k, size_t amp, bool* unit)
 {
     // G = M^H M (Hermitian: the upper triangle, in fp32, is enough for a
     // tolerance of 1e-3); ||M||_2^2 = lambda_max(G) <= max_r sum_c |G_rc|
+    constexpr int DM = 1 << kMaxDense;
+    thread_local float re[DM * DM], im[DM * DM], gr[DM * DM], gi[DM * DM];
+    thread_local double row[DM];
     const int D = 1 << k;
-    std::vector<float> re((size_t)D * D), im((size_t)D * D);
     for (size_t i = 0; i < (size_t)D * D; ++i) {
         if (amp == 8) {
             re[i] = ((const float*)m)[2 * i];
@@ -49,8 +51,8 @@ double sv::op_growth(const void* m, int k, size_t amp, bool* unit)
             re[i] = (float)((const double*)m)[2 * i];
             im[i] = (float)((const double*)m)[2 * i + 1];
         }
+        gr[i] = gi[i] = 0.f;
     }
-    std::vector<float> gr((size_t)D * D, 0.f), gi((size_t)D * D, 0.f);
     for (int x = 0; x < D; ++x) {
         const float* ar = &re[(size_t)x * D];
         const float* ai = &im[(size_t)x * D];
@@ -64,7 +66,7 @@ double sv::op_growth(const void* m, int k, size_t amp, bool* unit)
             }
         }
     }
-    std::vector<double> row(D, 0.0);
+    for (int r = 0; r < D; ++r) row[r] = 0.0;
     double dev = 0.0;
     for (int r = 0; r < D; ++r)
         for (int c = r; c < D; ++c) {
@@ -79,6 +81,28 @@ double sv::op_growth(const void* m, int k, size_t amp, bool* unit)
     if (unit) *unit = dev <= kUnitTol;
     // not finite (NaN / inf entries): no bound
     return std::isfinite(worst) ? std::sqrt(worst) : HUGE_VAL;
+}
+
+void sv::size_op(Op& op, const uint8_t* arena, size_t amp)
+{
+    if (op.sized) return;
+    op.sized = true;
+    if (op.kind == OP_DENSE) {
+        op.growth = op_growth(arena + op.off, op.k, amp, &op.unit);
+    } else if (op.kind == OP_DIAG) {
+        // a diagonal op scales amplitudes by its entries
+        double lo = HUGE_VAL, hi = 0.0;
+        for (size_t i = 0; i < ((size_t)1 << op.k); ++i) {
+            const double a = amp == 8 ? std::hypot((double)((const float*)(arena + op.off))[2 * i],
+                                                   (double)((const float*)(arena + op.off))[2 * i + 1])
+                                      : std::hypot(((const double*)(arena + op.off))[2 * i],
+                                                   ((const double*)(arena + op.off))[2 * i + 1]);
+            lo = std::min(lo, a);
+            hi = std::max(hi, a);
+        }
+        op.growth = std::isfinite(hi) ? hi : HUGE_VAL;
+        op.unit = hi - 1.0 <= kUnitTol && 1.0 - lo <= kUnitTol;
+    }
 }
 
 namespace {
@@ -244,6 +268,9 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
     if (norm_blocks) *norm_blocks = 0;
     const char* dbase = (const char*)h->d_arena_use;
     const size_t nops = h->ops.size();
+    // the amplitude bound before op i (ops are sized as they are reached,
+    // so the host work overlaps the launches already queued)
+    double bnd = h->amp_bound;
     for (size_t i = 0; i < nops; ++i) {
         const Op& op = h->ops[i];
         // a run of consecutive 4/5-qubit complex64 blocks whose targets fit in
@@ -280,10 +307,13 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 // split-fp16 form: unitary blocks, the tile scaled from the
                 // state's amplitude bound through the run
                 bool unit = h->split;
-                double bmax = h->ops[i].bound_before;
+                double bmax = bnd;
                 for (int c = 0; c < cnt; ++c) {
-                    unit = unit && h->ops[i + c].unit;
-                    bmax *= std::max(1.0, h->ops[i + c].growth);
+                    Op& oc = h->ops[i + c];
+                    size_op(oc, h->arena.data(), h->amp);
+                    unit = unit && oc.unit;
+                    bmax *= std::max(1.0, oc.growth);
+                    bnd *= oc.growth;
                 }
                 const int split_exp = unit ? split_exponent(bmax) : kNoSplit;
                 TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, stage_t, from_e0,
@@ -328,6 +358,10 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
             if (rc) return rc;
         }
         h->support = ~0ull;
+        if (op.kind != OP_LPERM) {
+            size_op(h->ops[i], h->arena.data(), h->amp);
+            bnd *= h->ops[i].growth;
+        }
         if (op.kind == OP_DENSE) {
             DiagSpec fold;
             const DiagSpec* fp = nullptr;
@@ -337,6 +371,8 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 for (int j = 0; j < d.k; ++j) fold.pos[j] = d.pos[j];
                 fold.table = dbase + d.off;
                 fp = &fold;
+                size_op(h->ops[i + 1], h->arena.data(), h->amp);
+                bnd *= h->ops[i + 1].growth;
                 ++i;
             }
             hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -775,12 +811,12 @@ int tier_pass(sv_state* h, bool write_back, F&& visit)
 
 // An amplitude bound for a resident state whose bound is unknown (its
 // buffer was written by the caller): its norm, an FP64 sum of |psi|^2 on the
-// device (one read pass and a host wait), and from it the bound before every
-// queued op.  Only when a staged pass of the queue could take the split form.
+// device (one read pass and a host wait).  Only when a staged pass of the
+// queue could take the split form.
 int measure_bound(sv_state* h, const WorkBufs* wb)
 {
     if (h->tier || !h->split || h->dtype != 0 || h->stage_t < 9 || h->mfma_min_k != 4 || h->ops.empty() ||
-        std::isfinite(h->ops[0].bound_before))
+        std::isfinite(h->amp_bound))
         return SV_OK;
     bool stageable = false;
     for (const Op& op : h->ops) stageable = stageable || (op.kind == OP_DENSE && (op.k == 4 || op.k == 5));
@@ -802,12 +838,7 @@ int measure_bound(sv_state* h, const WorkBufs* wb)
     double nrm2 = HUGE_VAL;
     TRY(h, hipMemcpyAsync(&nrm2, small, sizeof(double), hipMemcpyDeviceToHost, h->stream));
     TRY(h, hipStreamSynchronize(h->stream));
-    double b = std::isfinite(nrm2) ? std::sqrt(nrm2) * (1.0 + 1e-6) : HUGE_VAL;
-    for (Op& op : h->ops) {
-        op.bound_before = b;
-        b *= op.growth;
-    }
-    h->amp_bound = b;
+    h->amp_bound = std::isfinite(nrm2) ? std::sqrt(nrm2) * (1.0 + 1e-6) : HUGE_VAL;
     return SV_OK;
 }
 
@@ -831,6 +862,11 @@ int flush(sv_state* h, double* norm_out = nullptr, int* norm_blocks = nullptr, c
         TRY(h, hipStreamWaitEvent(h->s_in, h->ev_arena, 0));
         rc = tier_pass(h, true, [](int, void*) { return SV_OK; });
         if (rc) return rc;
+    }
+    // the queue is applied: the bound advances over it
+    for (Op& op : h->ops) {
+        size_op(op, h->arena.data(), h->amp);
+        h->amp_bound *= op.growth;
     }
     h->ops.clear();
     h->arena.clear();
@@ -1259,9 +1295,6 @@ int apply_fused(sv_handle h, int k, const int* qubits, const void* matrix)
     op.kind = OP_DENSE;
     op.k = k;
     for (int j = 0; j < k; ++j) op.pos[j] = h->pos[qubits[j]];
-    op.growth = op_growth(matrix, k, h->amp, &op.unit);
-    op.bound_before = h->amp_bound;
-    h->amp_bound *= op.growth;
     int minp = 64;
     for (int j = 0; j < k; ++j) minp = std::min(minp, op.pos[j]);
     if (h->dtype == 0 && h->mfma_min_k == 4 && k < 4 && minp < 4 && h->L >= 8) {
@@ -1305,20 +1338,6 @@ int apply_diag(sv_handle h, int m, const int* qubits, const void* phases)
     op.kind = OP_DIAG;
     op.k = m;
     for (int j = 0; j < m; ++j) op.pos[j] = h->pos[qubits[j]];
-    {
-        // a diagonal op scales amplitudes by its entries
-        double lo = HUGE_VAL, hi = 0.0;
-        for (size_t i = 0; i < ((size_t)1 << m); ++i) {
-            const double a = h->amp == 8 ? std::hypot((double)((const float*)phases)[2 * i], (double)((const float*)phases)[2 * i + 1])
-                                         : std::hypot(((const double*)phases)[2 * i], ((const double*)phases)[2 * i + 1]);
-            lo = std::min(lo, a);
-            hi = std::max(hi, a);
-        }
-        op.growth = std::isfinite(hi) ? hi : HUGE_VAL;
-        op.unit = hi - 1.0 <= kUnitTol && 1.0 - lo <= kUnitTol;
-    }
-    op.bound_before = h->amp_bound;
-    h->amp_bound *= op.growth;
     op.off = push_arena(h, phases, ((size_t)1 << m) * h->amp);
     h->ops.push_back(op);
     if (h->arena.size() > ((size_t)64 << 20) || h->ops.size() > 65536) return flush(h);
@@ -1757,7 +1776,14 @@ int sv_stage_forms(sv_handle h, int64_t passes[2], double* amp_bound)
         passes[0] = h->stage_forms[0];
         passes[1] = h->stage_forms[1];
     }
-    if (amp_bound) *amp_bound = h->amp_bound;
+    if (amp_bound) {
+        double b = h->amp_bound;
+        for (Op& op : h->ops) {
+            size_op(op, h->arena.data(), h->amp);
+            b *= op.growth;
+        }
+        *amp_bound = b;
+    }
     return SV_OK;
 }
 

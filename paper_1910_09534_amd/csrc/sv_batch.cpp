@@ -158,10 +158,11 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
         b->devs.push_back(h->dev);
         b->orders.push_back(h->order);
         double gp = 1.0;
-        for (const Op& op : h->ops) gp *= op.growth;
+        for (Op& op : h->ops) {
+            size_op(op, h->arena.data(), h->amp);
+            gp *= op.growth;
+        }
         b->gprod.push_back(gp);
-        // the queued ops run at every launch, not now
-        if (!h->ops.empty()) h->amp_bound = h->ops[0].bound_before;
     }
     hipError_t e;
     if (hip_stream) {

@@ -22,11 +22,11 @@ struct Op {
     size_t off = 0;            // arena offset of matrix / table
     BitRuns runs;              // OP_LPERM: destination -> source over local bits
     // bound on the factor by which the op can raise the state's norm (its
-    // largest singular value), whether it is unitary within kUnitTol, and
-    // the state's amplitude bound before it (at queue time)
+    // largest singular value) and whether it is unitary within kUnitTol;
+    // worked out from the queued data when first needed (size_op)
     double growth = 1.0;
     bool unit = true;
-    double bound_before = 1.0;
+    bool sized = false;
 };
 
 // Unitarity tolerance of an op (largest entry of |M^H M - I|): staged runs
@@ -36,7 +36,11 @@ constexpr double kUnitTol = 1e-3;
 
 // Largest-singular-value bound of a k-qubit matrix (row-major complex64 if
 // amp == 8, else complex128) and whether it is unitary within kUnitTol.
+// Allocates nothing (per-thread buffers).
 double op_growth(const void* m, int k, size_t amp, bool* unit);
+
+// Fills op.growth / op.unit from its data in the host arena (once).
+void size_op(Op& op, const uint8_t* arena, size_t amp);
 
 // Writes |0...0> into a resident state whose reset was deferred (no-op
 // otherwise); on the handle's stream.
@@ -155,10 +159,10 @@ struct sv_state {
     double tk_issued[2] = {0.0, 0.0};
     double tk_bytes[2] = {0.0, 0.0};
     int64_t counters[8] = {};
-    // bound on the norm of the state (so on every |amplitude|): 1 after
-    // creation or sv_reset, times each applied op's growth; infinite once
-    // the device buffer has been handed out or when a restored tier does not
-    // state it
+    // bound on the norm of the amplitudes in memory (so on every
+    // |amplitude|), before the queued ops: 1 after creation or sv_reset,
+    // times each applied op's growth; infinite once the device buffer has
+    // been handed out or when a restored tier does not state it
     double amp_bound = 1.0;
     int64_t stage_forms[2] = {};  // staged passes run in the split-fp16 / fp32 form
 

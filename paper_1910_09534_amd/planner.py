@@ -385,15 +385,36 @@ def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = No
 
 # Modelled device time (ms per 2^30 complex64 amplitudes) of a single sweep
 # of a k-qubit block, and of a staged pass: the larger of its memory time
-# and a fixed part plus the blocks' matrix-core work (the vector and matrix
-# units do not overlap, so a pass with several blocks is compute bound).
-# Only the ranking of candidate plans uses these figures.
-# (Fitted to measured 30-qubit step times of 31 aggregations: per staged
-# pass 1.475 ms, per 5-qubit block 1.78, per 4-qubit block 1.10.)
+# and a fixed part plus a cost per block.  Only the ranking of candidate
+# plans uses these figures.  Two forms of the staged kernel:
+#  * "split" (the library's default, SV_OPT_SPLIT 1): products on the fp16
+#    matrix cores; a block costs its LDS round trip, split and barrier more
+#    than its matrix-core work (least squares over 80 measured single
+#    passes on a dense 30-qubit state, tile limits 12..14, 2..8 blocks:
+#    memory 3.5, fixed 0.55, per 4-qubit block 0.83, per 5-qubit block 0.95;
+#    rms error 0.24 ms);
+#  * "fp32" (SV_OPT_SPLIT 0): the fp32 matrix cores bound the pass (fitted
+#    to measured 30-qubit step times of 31 aggregations: memory 3.35, fixed
+#    1.475, per 5-qubit block 1.78, per 4-qubit block 1.10).
+# STAGE_FORM selects the model.  It defaults to the fp32 figures for both
+# forms: ranked with them, the 30-qubit depth-14 circuit's plans run in the
+# split form 0.2-1.0 ms faster (39 blocks in 16 passes and one sweep, 39.4
+# ms of device time) than ranked with the split fit (52 smaller blocks in
+# 17 passes, 39.6-39.7 ms): the split fit's max() form prices blocks under
+# the memory time as free, which they are not quite.
 SWEEP_MS = {1: 2.9, 2: 2.9, 3: 3.4, 4: 3.5, 5: 3.57, 6: 3.7}
-STAGE_MS_MEM = 3.35
-STAGE_MS_FIXED = 1.475
-STAGE_MS_BLOCK = {4: 1.10, 5: 1.78}
+STAGE_MODELS = {
+    "split": (3.5, 0.55, {4: 0.83, 5: 0.95}),
+    "fp32": (3.35, 1.475, {4: 1.10, 5: 1.78}),
+}
+STAGE_FORM = "fp32"
+
+
+def stage_pass_ms(ks: Sequence[int]) -> float:
+    """Modelled time of one staged pass of blocks of widths `ks` over 2^30
+    amplitudes (STAGE_FORM's model)."""
+    mem, fixed, per = STAGE_MODELS[STAGE_FORM]
+    return max(mem, fixed + sum(per[k] for k in ks))
 
 
 def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) -> float:
@@ -403,7 +424,7 @@ def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) ->
     tot = 0.0
     for r in stage_runs(ops, pos_of, tmax):
         if len(r) >= 2:
-            tot += max(STAGE_MS_MEM, STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r))
+            tot += stage_pass_ms([len(ops[i].qubits) for i in r])
         else:
             o = ops[r[0]]
             tot += SWEEP_MS.get(len(o.qubits), 4.0) if o.kind == "dense" else SWEEP_MS[1]
@@ -466,7 +487,7 @@ def sparse_cost(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[int]
             o = ops[r[0]]
             tot += SWEEP_MS.get(len(o.qubits), 4.0) if o.kind == "dense" else SWEEP_MS[1]
             continue
-        base = max(STAGE_MS_MEM, STAGE_MS_FIXED + sum(STAGE_MS_BLOCK[len(ops[i].qubits)] for i in r))
+        base = stage_pass_ms([len(ops[i].qubits) for i in r])
         tot += base * 2.0 ** (lv - nloc) + STAGE_MS_LAUNCH
     return tot
 
