@@ -960,7 +960,7 @@ def serve_summary(pool, kmax, count):
             "p50_latency_s": s["p50_latency_s"], "p99_latency_s": s["p99_latency_s"],
             "makespan_s": s["makespan_s"],
             "mean_wait_admit_s": s["mean_wait_admit_s"], "mean_wait_plan_s": s["mean_wait_plan_s"],
-            "mean_queue_s": s["mean_queue_s"], "mean_run_s": s["mean_run_s"], "device_busy": s["device_busy"],
+            "mean_queue_s": s["mean_queue_s"], "mean_run_s": s["mean_run_s"], "launch_time_over_makespan": s["launch_time_over_makespan"],
             # measured: arrival rate over the completion rate the server sustained
             "offered_load_rho_measured": 50.0 / mu, "max_inflight": inflight,
             "max_norm_error": float(max(abs(r.norm - 1) for r in res)),
@@ -992,7 +992,7 @@ def bench_serve(args) -> int:
         "p50_latency_s": s50["p50_latency_s"], "p99_latency_s": s50["p99_latency_s"],
         "mean_latency_s": s50["mean_latency_s"], "makespan_s": s50["makespan_s"],
         "mean_wait_admit_s": s50["mean_wait_admit_s"], "mean_wait_plan_s": s50["mean_wait_plan_s"],
-        "mean_queue_s": s50["mean_queue_s"], "mean_run_s": s50["mean_run_s"], "device_busy": s50["device_busy"],
+        "mean_queue_s": s50["mean_queue_s"], "mean_run_s": s50["mean_run_s"], "launch_time_over_makespan": s50["launch_time_over_makespan"],
         # measured: arrival rate over the completion rate the server sustained
         "offered_load_rho_measured": 50.0 / mu, "max_inflight": srv.max_inflight,
         "max_norm_error": float(np.abs(norms - 1).max()), "t_run_s": round(t_run, 1),
