@@ -287,9 +287,18 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 mm[c] = dbase + h->ops[i + c].off;
             }
             const size_t j = i + cnt;
-            // a single block goes through a staged pass only when it is the
-            // queue's last op and the pass also sums the norm (saving a read)
-            if (cnt >= 2 || (cnt == 1 && j == nops && norm_out != nullptr)) {
+            // a single block goes through a staged pass when it takes the
+            // split-fp16 form (the pass reads and writes its tiles in long
+            // runs, where a single sweep reads 16-group tiles scattered over
+            // the block's target bits), or when it is the queue's last op and
+            // the pass also sums the norm (saving a read)
+            bool lone_split = false;
+            if (cnt == 1 && h->split) {
+                size_op(h->ops[i], h->arena.data(), h->amp);
+                lone_split = h->ops[i].unit &&
+                             split_exponent(bnd * std::max(1.0, h->ops[i].growth)) != kNoSplit;
+            }
+            if (cnt >= 2 || (cnt == 1 && (lone_split || (j == nops && norm_out != nullptr)))) {
                 const bool from_e0 = h->e0_pending && i == 0 && !h->tier;
                 hipEvent_t e0 = nullptr, e1 = nullptr;
                 if (h->timing) {

@@ -208,7 +208,9 @@ int sv_batch_prepare(int count, sv_handle* handles, int flags, void* hip_stream,
             if (can_stage && ops[j].kind == OP_DENSE && (ops[j].k == 4 || ops[j].k == 5)) {
                 Sw w{3, &ops[j], nullptr, 0, {}};
                 w.cnt = form_stage_run(ops.data(), ops.size(), j, h->stage_t, h->n, h->fold, w.ks);
-                if (w.cnt >= 2) {
+                // a lone unitary block also takes a staged pass, as run_ops
+                // gives it (split-fp16 form in the reset variant)
+                if (w.cnt >= 2 || (w.cnt == 1 && h->split && ops[j].unit)) {
                     sweeps[i].push_back(w);
                     j += w.cnt - 1;
                     any_staged = true;
