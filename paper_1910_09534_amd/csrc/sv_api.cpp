@@ -275,13 +275,15 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
         const Op& op = h->ops[i];
         // a run of consecutive 4/5-qubit complex64 blocks whose targets fit in
         // one LDS tile goes through a single staged HBM pass
+        // (complex64 with the matrix-core sweeps on from k = 4; complex128
+        // always: its single sweeps run on the vector units)
         const int stage_t = h->stage_t;
-        if (op.kind == OP_DENSE && h->dtype == 0 && stage_t >= 9 && h->mfma_min_k == 4 &&
+        if (op.kind == OP_DENSE && stage_t >= 9 && (h->dtype != 0 || h->mfma_min_k == 4) &&
             (op.k == 4 || op.k == 5)) {
             int ks[kStageRunMax];
             const int* pp[kStageRunMax];
             const void* mm[kStageRunMax];
-            const int cnt = form_stage_run(h->ops.data(), nops, i, stage_t, nloc, h->fold, ks);
+            const int cnt = form_stage_run(h->ops.data(), nops, i, stage_t, nloc, h->fold, ks, h->dtype);
             for (int c = 0; c < cnt; ++c) {
                 pp[c] = h->ops[i + c].pos;
                 mm[c] = dbase + h->ops[i + c].off;
@@ -293,7 +295,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
             // the block's target bits), or when it is the queue's last op and
             // the pass also sums the norm (saving a read)
             bool lone_split = false;
-            if (cnt == 1 && h->split) {
+            if (cnt == 1 && h->split && h->dtype == 0) {
                 size_op(h->ops[i], h->arena.data(), h->amp);
                 lone_split = h->ops[i].unit &&
                              split_exponent(bnd * std::max(1.0, h->ops[i].growth)) != kNoSplit;
@@ -315,7 +317,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 uint64_t pmask = 0, visited = 0;
                 // split-fp16 form: unitary blocks, the tile scaled from the
                 // state's amplitude bound through the run
-                bool unit = h->split;
+                bool unit = h->split && h->dtype == 0;
                 double bmax = bnd;
                 for (int c = 0; c < cnt; ++c) {
                     Op& oc = h->ops[i + c];
@@ -328,7 +330,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 TRY(h, launch_stage(st, *psi, nloc, cnt, ks, pp, mm, stage_t, from_e0,
                                     last ? norm_out : nullptr, last ? norm_blocks : nullptr, &tused,
                                     track ? h->support : ~0ull, track && h->garbage, &pmask, &visited,
-                                    split_exp));
+                                    split_exp, h->dtype));
                 h->stage_forms[split_exp != kNoSplit ? 0 : 1] += 1;
                 h->e0_pending = false;
                 if (track) {
@@ -341,8 +343,9 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                 if (h->timing) {
                     TRY(h, hipEventRecord(e1, st));
                     double f = 0.0, fi = 0.0;
-                    // issued per amplitude: 3 real products (fp32 3M form), or
-                    // 4 real products x 3 split terms (fp16), 2 2^k flops each
+                    // issued per amplitude: 3 real products (3M form, fp32 or
+                    // FP64), or 4 real products x 3 split terms (fp16), 2 2^k
+                    // flops each
                     for (int c = 0; c < cnt; ++c) {
                         f += block_flops_alg(ks[c]);
                         fi += (split_exp != kNoSplit ? 24.0 : 6.0) * (double)(1 << ks[c]);
@@ -353,7 +356,7 @@ int run_ops(sv_state* h, hipStream_t st, void** psi, void* alt, int nloc, uint64
                     double rd = from_e0 ? 0.0 : amps;
                     if (!from_e0 && track && h_garbage_before)
                         rd = std::ldexp(amps, -__builtin_popcountll(pmask & ~support_before));
-                    h->tev_info.push_back({1, f * amps, fi * amps, 8.0 * (amps + rd)});
+                    h->tev_info.push_back({1, f * amps, fi * amps, (double)h->amp * (amps + rd)});
                 }
                 h->counters[0] += 1;
                 h->counters[3] += (int64_t)visited;
@@ -1865,7 +1868,7 @@ int sv::materialize_e0(sv_state* h)
 }
 
 // ---- staged-run formation (shared with the batch executor) -----------------
-int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks)
+int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks, int dtype)
 {
     bool in[64] = {};
     for (int p = 0; p < 4; ++p) in[p] = true;
@@ -1881,7 +1884,8 @@ int sv::form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nl
         for (int p = 0; p < 64; ++p) t += in2[p];
         if (t < 9) t = 9;
         ks[cnt] = q.k;
-        if (t > stage_t || t > stage_max_t() || t > nloc || stage_lds_bytes(t, cnt + 1, ks) > stage_lds_limit(t))
+        if (t > stage_t || t > stage_max_t(dtype) || t > nloc ||
+            stage_lds_bytes(t, cnt + 1, ks, dtype) > stage_lds_limit(t, dtype))
             break;
         for (int p = 0; p < 64; ++p) in[p] = in2[p];
         ++cnt;

@@ -112,16 +112,19 @@ inline bool dense_uses_mfma(int k, int nloc, int mfma_min_k)
 // so tile amplitudes with a bit on a tile position outside the support are
 // taken as zero instead of read.  *tile_mask_out: the tile's positions;
 // *amps_out: amplitudes visited.
-int stage_lds_bytes(int t, int nops, const int* ks);
-// LDS budget of a tile of t positions (80 KiB up to 13: two workgroups per
-// CU; 160 KiB at 14: one 512-lane workgroup per CU).
-int stage_lds_limit(int t);
+// dtype 0: complex64 (fp32 or split-fp16 form); 1: complex128 (FP64 form,
+// one 512-lane workgroup per CU, tiles of 9..13 positions).
+int stage_lds_bytes(int t, int nops, const int* ks, int dtype = 0);
+// LDS budget of a tile of t positions (complex64: 80 KiB up to 13, two
+// workgroups per CU; 160 KiB at 14, one 512-lane workgroup per CU;
+// complex128: 160 KiB).
+int stage_lds_limit(int t, int dtype = 0);
 // Sets the staged kernels' LDS attribute for every tile width (idempotent;
 // launch_stage does it on first use, graph capture needs it beforehand).
 hipError_t stage_prepare();
-// Widest tile the device runs: 14, or 13 where a workgroup cannot have the
-// whole LDS of a CU.
-int stage_max_t();
+// Widest tile the device runs: complex64 14, or 13 where a workgroup cannot
+// have the whole LDS of a CU; complex128 13, or 0 (no staged passes) there.
+int stage_max_t(int dtype = 0);
 // split_exp: kNoSplit = fp32 matrix-core form; otherwise the split-fp16
 // form with the tile scaled by 2^split_exp in LDS (-100..100).
 constexpr int kNoSplit = -1000;
@@ -129,7 +132,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out, uint64_t support = ~0ull, bool garbage = false,
                         uint64_t* tile_mask_out = nullptr, uint64_t* amps_out = nullptr,
-                        int split_exp = kNoSplit);
+                        int split_exp = kNoSplit, int dtype = 0);
 // Exponent e of the split-fp16 form's tile scale 2^e for a run whose
 // blocks are all unitary and whose state norm stays below bound: the
 // largest e with 2^e bound <= 2^15 (-100..100); kNoSplit when bound is not
@@ -138,7 +141,7 @@ int split_exponent(double bound);
 
 // Amplitudes a staged pass with these blocks visits (launch_stage's tile
 // choice for this support); 0 when the run does not fit a tile.
-uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support);
+uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support, int dtype = 0);
 
 // Contraction over entanglement indices: out[x2 2^n1 + x1] =
 // sum_e t1[e 2^n1 + x1] t2[e 2^n2 + x2] (complex64 or complex128).

@@ -680,13 +680,218 @@ __global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restri
 }
 
 
-int stage_lds_bytes(int t, int nops, const int* ks)
+// ---- complex128 staged pass ---------------------------------------------------
+// The FP64 form for complex128 states (Sec. 5 computes in double): the same
+// tile scheme, with a tile of 2^t double-complex amplitudes taking twice the
+// LDS of a complex64 one, so one 512-lane workgroup per CU holds the whole
+// 160 KiB (a 13-position complex128 tile plus its blocks' matrices is the
+// double of a 13-position complex64 tile plus its own).  Each lane moves one
+// amplitude per 16-byte access (tile bits 0..8 are the lane, bits 9.. the
+// element index), and every block's three real products (3M, as in the
+// fp32 form) run on v_mfma_f64_16x16x4f64, whose operand layouts are those
+// of v_mfma_f32_16x16x4f32 (its result rows are not: see stage64_block),
+// one 16-group unit per wave at a time.
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double dd2 __attribute__((ext_vector_type(2)));
+
+template <int K>
+__device__ __forceinline__ void stage64_block(const StageK& a, int o, const d4* __restrict__ As,
+                                              double2* __restrict__ T, int wave)
 {
-    int floats = 0;
-    for (int o = 0; o < nops; ++o) floats += 2 * (1 << (2 * ks[o]));
-    const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16 + 1;
-    return tile_f4 * 16 + floats * 4;
+    using S = MfmaShape<K>;
+    constexpr int RB = S::RB, KQ = S::KQ, NE = S::D / 4;
+    constexpr int nw = 8;
+    const int lane = threadIdx.x & 63;
+    const int j = lane & 15, h = lane >> 4;
+    int bit[K], low[K];
+#pragma unroll
+    for (int u = 0; u < K; ++u) {
+        bit[u] = 1 << a.op_bits[o][u];
+        low[u] = (1 << a.op_lowmask_bits[o][u]) - 1;
+    }
+    // operands as in the fp32 form; results: v_mfma_f64_16x16x4f64 gives
+    // item v of lane (j, h) row h + 4 v (the fp32 instruction 4 h + v), so
+    // h selects result bits 0, 1 and v bits 2, 3
+    const int lj = lslot(spread<K>(j, low));
+    const int cx = lj + lslot(((h & 1) ? bit[0] : 0) | ((h & 2) ? bit[1] : 0));
+    const int cy = cx;
+    int sx[NE], sy[NE];
+#pragma unroll
+    for (int m = 0; m < NE; ++m) {
+        int off = 0;
+#pragma unroll
+        for (int u = 2; u < K; ++u)
+            if ((m >> (u - 2)) & 1) off |= bit[u];
+        sx[m] = lslot(off);
+    }
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            int off = (v & 1) ? bit[2] : 0;
+            off |= (v & 2) ? bit[3] : 0;
+#pragma unroll
+            for (int u = 4; u < K; ++u)
+                if ((rb >> (u - 4)) & 1) off |= bit[u];
+            sy[4 * rb + v] = lslot(off);
+        }
+    const int units = 1 << (a.t - K - 4);
+    for (int unit = wave; unit < units; unit += nw) {
+        const int su = lslot(spread<K>(unit * 16, low));
+        double2 x[NE];
+#pragma unroll
+        for (int m = 0; m < NE; ++m) x[m] = T[(su + sx[m]) + cx];
+        d4 acc[3][RB];
+#pragma unroll
+        for (int p = 0; p < 3; ++p)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) acc[p][rb] = d4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int sq = 0; sq < KQ; ++sq) {
+            d4 av[3][RB];
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) {
+                av[0][rb] = As[((0 * RB + rb) * KQ + sq) * 64 + lane];
+                av[1][rb] = As[((1 * RB + rb) * KQ + sq) * 64 + lane];
+                av[2][rb] = av[0][rb] + av[1][rb];
+            }
+#pragma unroll
+            for (int s4 = 0; s4 < 4; ++s4) {
+                const double2 xv = x[4 * sq + s4];
+                const double bs = xv.x + xv.y;
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    acc[0][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[0][rb][s4], xv.x, acc[0][rb], 0, 0, 0);
+                    acc[1][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[1][rb][s4], xv.y, acc[1][rb], 0, 0, 0);
+                    acc[2][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[2][rb][s4], bs, acc[2][rb], 0, 0, 0);
+                }
+            }
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const double p1 = acc[0][rb][v], p2 = acc[1][rb][v], p3 = acc[2][rb][v];
+                T[(su + sy[4 * rb + v]) + cy] = double2{p1 - p2, p3 - p1 - p2};
+            }
+    }
 }
+
+// TW: tile width t (9..13), PER = 2^(t-9) amplitudes per lane.  WIDE and
+// ZERO as for k_stage.
+template <int TW, bool WIDE, bool ZERO>
+__global__ __launch_bounds__(512) void k_stage64(double2* __restrict__ psi, StageK a)
+{
+    constexpr int NT = 512, LB = 9, PER = 1 << (TW - LB);
+    extern __shared__ d4 smem64[];
+    double2* T = (double2*)smem64;                               // tile, padded
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    d4* Abase = smem64 + ((lslot(1 << TW) * 16 + 31) / 32);      // operand matrices
+    for (int o = 0; o < a.nops; ++o) {
+        const int k = a.op_k[o];
+        const int D = 1 << k, RB = D / 16, KQ = D / 16, NA = 2 * RB * KQ * 256;
+        double* dst = (double*)Abase + a.op_aoff[o];
+        const double2* mat = (const double2*)a.op_mat[o];
+        for (int i = threadIdx.x; i < NA; i += NT) {
+            const int s4 = i & 3, l = (i >> 2) & 63, blk = i >> 8;
+            const int sq = blk % KQ, rb = (blk / KQ) % RB, p = blk / (KQ * RB);
+            const int R = 16 * rb + (l & 15);
+            const int C = 4 * (4 * sq + s4) + (l >> 4);
+            const double2 m = mat[R * D + C];
+            dst[i] = p == 0 ? m.x : m.y;
+        }
+    }
+    // element m of lane l: tile-local index l + NT m, LDS slot lslot(l) + ES m
+    constexpr int ES = NT + NT / 16;
+    uint64_t dl = 0;
+    for (int b = 0; b < LB; ++b)
+        if ((threadIdx.x >> b) & 1) dl |= a.dep_lane[b];
+    const uint32_t dlb = (uint32_t)(dl * sizeof(double2));      // used when !WIDE
+    auto elem = [&](uint64_t tb, int m) -> dd2* {
+        if (WIDE) return (dd2*)(psi + (tb + dl + a.dep_i[m]));
+        return (dd2*)((char*)(psi + (tb + a.dep_i[m])) + dlb);
+    };
+    const int ls = lslot(threadIdx.x);
+    dd2 xr[PER];
+    auto load_tile = [&](uint64_t tile, uint64_t tb) {
+        if (a.from_e0) {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) xr[m] = dd2{0.0, 0.0};
+            if (tile == 0 && threadIdx.x == 0) xr[0].x = 1.0;
+        } else {
+#pragma unroll
+            for (int m = 0; m < PER; ++m) xr[m] = __builtin_nontemporal_load(elem(tb, m));
+        }
+    };
+    auto parked = [&](int m) -> double2 {
+        double2 e = double2{xr[m].x, xr[m].y};
+        if (ZERO && (((uint32_t)threadIdx.x + (uint32_t)(NT * m)) & a.newmask_t)) e = double2{0.0, 0.0};
+        return e;
+    };
+    double nacc = 0.0;
+    uint64_t tile = blockIdx.x;
+    uint64_t tb = spread_bits(tile, a.tmask);
+    if (tile < a.tiles) {
+        load_tile(tile, tb);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) T[ls + ES * m] = parked(m);
+    }
+    __syncthreads();
+    for (; tile < a.tiles; tile += gridDim.x) {
+        const uint64_t nt = tile + gridDim.x;
+        const uint64_t nb = ((tb | ~a.tmask) + a.tstep) & a.tmask;
+        const bool next = nt < a.tiles;
+        __builtin_amdgcn_s_setprio(1);
+        if (next) load_tile(nt, nb);
+        __builtin_amdgcn_s_setprio(0);
+        for (int o = 0; o < a.nops; ++o) {
+            const d4* As = (const d4*)((const double*)Abase + a.op_aoff[o]);
+            if (a.op_k[o] == 5) stage64_block<5>(a, o, As, T, wave);
+            else stage64_block<4>(a, o, As, T, wave);
+            __syncthreads();
+        }
+        // each lane parks the next tile's elements in the slots it has just
+        // read for its stores
+        __builtin_amdgcn_s_setprio(1);
+#pragma unroll
+        for (int m = 0; m < PER; ++m) {
+            const double2 v = T[ls + ES * m];
+            if (next) T[ls + ES * m] = parked(m);
+            __builtin_nontemporal_store(dd2{v.x, v.y}, elem(tb, m));
+            if (a.norm_out) nacc = fma(v.x, v.x, fma(v.y, v.y, nacc));
+        }
+        __builtin_amdgcn_s_setprio(0);
+        __syncthreads();
+        tb = nb;
+    }
+    if (a.norm_out) {
+        double* sh = (double*)smem64;
+        sh[threadIdx.x] = nacc;
+        __syncthreads();
+        for (int hh = NT / 2; hh > 0; hh >>= 1) {
+            if ((int)threadIdx.x < hh) sh[threadIdx.x] += sh[threadIdx.x + hh];
+            __syncthreads();
+        }
+        if (threadIdx.x == 0) a.norm_out[blockIdx.x] = sh[0];
+    }
+}
+
+int stage_lds_bytes(int t, int nops, const int* ks, int dtype)
+{
+    int scalars = 0;
+    for (int o = 0; o < nops; ++o) scalars += 2 * (1 << (2 * ks[o]));
+    if (dtype) {
+        // complex128: tile in 32-byte units, then the matrices in double
+        const int tile_d4 = (((1 << t) + ((1 << t) >> 4)) * 16 + 31) / 32;
+        return tile_d4 * 32 + scalars * 8;
+    }
+    const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16 + 1;
+    return tile_f4 * 16 + scalars * 4;
+}
+
+// LDS a tile of t positions may use: complex64 as above; complex128 always
+// the whole CU (one 512-lane workgroup)
+static inline int stage_lds_limit_dt(int t, int dtype) { return dtype ? kStageMaxLds14 : stage_lds_limit_t(t); }
 
 // the variant for a tile of t positions (9..14), 64-bit lane offsets, and
 // zeroing of stale elements
@@ -711,9 +916,28 @@ static void (*stage_kernel(int t, bool wide, bool zero, bool split))(float2*, St
     return nullptr;
 }
 
+static void (*stage64_kernel(int t, bool wide, bool zero))(double2*, StageK)
+{
+#define SV_STAGE64_CASE(T) \
+    case T:                \
+        return wide ? (zero ? k_stage64<T, true, true> : k_stage64<T, true, false>) \
+                    : (zero ? k_stage64<T, false, true> : k_stage64<T, false, false>);
+    switch (t) {
+        SV_STAGE64_CASE(9)
+        SV_STAGE64_CASE(10)
+        SV_STAGE64_CASE(11)
+        SV_STAGE64_CASE(12)
+        SV_STAGE64_CASE(13)
+    }
+#undef SV_STAGE64_CASE
+    return nullptr;
+}
+
 // 14-position tiles need the whole LDS of a CU for one workgroup; where the
-// device refuses that, tiles stop at 13 positions
+// device refuses that, tiles stop at 13 positions (and complex128 states
+// take no staged passes)
 static std::atomic<bool> g_stage14{false};
+static std::atomic<bool> g_stage64{false};
 
 hipError_t stage_prepare()
 {
@@ -734,6 +958,15 @@ hipError_t stage_prepare()
     }
     if (!ok14) (void)hipGetLastError();
     g_stage14 = ok14;
+    bool ok64 = true;
+    for (int t = 9; t <= 13 && ok64; ++t)
+        for (int v = 0; v < 4 && ok64; ++v) {
+            void (*k)(double2*, StageK) = stage64_kernel(t, v & 1, v & 2);
+            ok64 = hipFuncSetAttribute((const void*)k, hipFuncAttributeMaxDynamicSharedMemorySize, kStageMaxLds14) ==
+                   hipSuccess;
+        }
+    if (!ok64) (void)hipGetLastError();
+    g_stage64 = ok64;
     done = true;
     return hipSuccess;
 }
@@ -748,15 +981,16 @@ int split_exponent(double bound)
     return e < -100 ? kNoSplit : (e > 100 ? 100 : e);
 }
 
-int stage_max_t()
+int stage_max_t(int dtype)
 {
-    if (stage_prepare() != hipSuccess) return 13;
+    if (stage_prepare() != hipSuccess) return dtype ? 0 : 13;
+    if (dtype) return g_stage64 ? 13 : 0;
     return g_stage14 ? kStageMaxT : 13;
 }
 
-int stage_lds_limit(int t)
+int stage_lds_limit(int t, int dtype)
 {
-    return stage_lds_limit_t(t);
+    return stage_lds_limit_dt(t, dtype);
 }
 
 // Tile positions of a staged pass, ascending, into P (returns t, or -1 when
@@ -769,9 +1003,9 @@ int stage_lds_limit(int t)
 // 14-position tile (one workgroup per CU) is used only when the targets
 // need it.
 static int stage_positions(int nloc, int nops, const int* ks, const int* const* pos, int t_max,
-                           uint64_t support, int* P)
+                           uint64_t support, int* P, int dtype)
 {
-    if (t_max > stage_max_t()) t_max = stage_max_t();
+    if (t_max > stage_max_t(dtype)) t_max = stage_max_t(dtype);
     if (nops < 1 || nops > kStageMaxOps) return -1;
     bool in[64] = {};
     for (int p = 0; p < 4; ++p) in[p] = true;
@@ -785,21 +1019,23 @@ static int stage_positions(int nloc, int nops, const int* ks, const int* const* 
     for (int round = 0; round < 2; ++round)
         for (int p = 0; p < nloc && cnt < (round ? 9 : widen_to); ++p) {
             if (in[p] || (round == 0 && !((support >> p) & 1))) continue;
-            if (stage_lds_bytes(cnt + 1, nops, ks) > stage_lds_limit_t(cnt + 1)) break;
+            if (stage_lds_bytes(cnt + 1, nops, ks, dtype) > stage_lds_limit_dt(cnt + 1, dtype)) break;
             in[p] = true;
             ++cnt;
         }
     int t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;
-    if (t > t_max || t < 9 || nloc < t || stage_lds_bytes(t, nops, ks) > stage_lds_limit_t(t)) return -1;
+    if (t > t_max || t < 9 || nloc < t || stage_lds_bytes(t, nops, ks, dtype) > stage_lds_limit_dt(t, dtype))
+        return -1;
     return t;
 }
 
-uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support)
+uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, int t_max, uint64_t support,
+                      int dtype)
 {
     int P[64];
-    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P);
+    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P, dtype);
     if (t < 0) return 0;
     uint64_t pmask = 0;
     for (int b = 0; b < t; ++b) pmask |= 1ull << P[b];
@@ -810,11 +1046,12 @@ uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, 
 hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int* ks, const int* const* pos,
                         const void* const* mats, int t_max, bool from_e0, double* norm_out, int* norm_blocks,
                         int* t_out, uint64_t support, bool garbage, uint64_t* tile_mask_out,
-                        uint64_t* amps_out, int split_exp)
+                        uint64_t* amps_out, int split_exp, int dtype)
 {
     int P[64];
-    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P);
+    const int t = stage_positions(nloc, nops, ks, pos, t_max, support, P, dtype);
     if (t < 0) return hipErrorInvalidValue;
+    if (dtype && split_exp != kNoSplit) return hipErrorInvalidValue;
     StageK a{};
     a.t = t;
     a.nops = nops;
@@ -836,14 +1073,17 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.newmask_t = 0;
     for (int b = 0; b < t; ++b)
         if ((newmask >> P[b]) & 1) a.newmask_t |= 1u << b;
-    const int lb = t >= 14 ? 9 : 8;                             // lane bits of the tile index
-    // tile bit 0 (position 0) pairs adjacent amplitudes; lane bit b is tile
-    // bit b + 1; pair index bit c is tile bit lb + 1 + c
-    for (int b = 0; b < lb; ++b) a.dep_lane[b] = 1ull << P[b + 1];
-    for (int i = 0; i < (1 << (t - lb - 1)); ++i) {
+    const int lb = (t >= 14 || dtype) ? 9 : 8;                  // lane bits of the tile index
+    // complex64: tile bit 0 (position 0) pairs adjacent amplitudes; lane bit
+    // b is tile bit b + 1; pair index bit c is tile bit lb + 1 + c.
+    // complex128: lane bit b is tile bit b; element index bit c is tile bit
+    // lb + c
+    const int pb = dtype ? 0 : 1;
+    for (int b = 0; b < lb; ++b) a.dep_lane[b] = 1ull << P[b + pb];
+    for (int i = 0; i < (1 << (t - lb - pb)); ++i) {
         uint64_t d = 0;
-        for (int b = lb + 1; b < t; ++b)
-            if ((i >> (b - lb - 1)) & 1) d |= 1ull << P[b];
+        for (int b = lb + pb; b < t; ++b)
+            if ((i >> (b - lb - pb)) & 1) d |= 1ull << P[b];
         a.dep_i[i] = d;
     }
     int aoff = 0;
@@ -865,27 +1105,32 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
             }
         for (int j = 0; j < ks[o]; ++j) a.op_lowmask_bits[o][j] = tbit[j];
     }
-    const int lds = stage_lds_bytes(t, nops, ks);
-    if (lds > stage_lds_limit_t(t)) return hipErrorInvalidValue;
+    const int lds = stage_lds_bytes(t, nops, ks, dtype);
+    if (lds > stage_lds_limit_dt(t, dtype)) return hipErrorInvalidValue;
     // byte offset of the lane part of an element address
     uint64_t dl_max = 0;
     for (int b = 0; b < lb; ++b) dl_max |= a.dep_lane[b];
-    const bool wide = dl_max * sizeof(float2) >= (1ull << 32);
-    void (*kern)(float2*, StageK) = stage_kernel(t, wide, a.newmask_t != 0, split);
-    if (!kern) return hipErrorInvalidValue;
+    const bool wide = dl_max * (dtype ? sizeof(double2) : sizeof(float2)) >= (1ull << 32);
+    void (*kern)(float2*, StageK) = dtype ? nullptr : stage_kernel(t, wide, a.newmask_t != 0, split);
+    void (*kern64)(double2*, StageK) = dtype ? stage64_kernel(t, wide, a.newmask_t != 0) : nullptr;
+    if (!kern && !kern64) return hipErrorInvalidValue;
     {
         const hipError_t e = stage_prepare();
         if (e != hipSuccess) return e;
     }
-    // persistent: as many workgroups as are resident (LDS-limited, at most 4 per CU)
+    // persistent: as many workgroups as are resident (LDS-limited, at most 4
+    // per CU; complex128: one 512-lane workgroup per CU)
     int per_cu = (160 * 1024) / lds;
     if (per_cu > 4) per_cu = 4;
-    if (per_cu < 1) per_cu = 1;
+    if (per_cu < 1 || dtype) per_cu = 1;
     uint64_t grid = a.tiles;
     const uint64_t cap = 256ull * per_cu;
     if (grid > cap) grid = cap;
     a.tstep = spread_bits(grid, a.tmask);
-    hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(stage_threads(t)), lds, st, (float2*)psi, a);
+    if (dtype)
+        hipLaunchKernelGGL(kern64, dim3((unsigned)grid), dim3(512), lds, st, (double2*)psi, a);
+    else
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(stage_threads(t)), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     if (norm_blocks) *norm_blocks = norm_out ? (int)grid : 0;
     if (tile_mask_out) *tile_mask_out = pmask;

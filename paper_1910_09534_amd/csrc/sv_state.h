@@ -72,7 +72,8 @@ int reduce_with(sv_state* h, const void* trailing, int64_t count, const uint64_t
 // widest) positions within the LDS budget, at most kStageRunMax ops.  Returns the op count (0 when
 // ops[i] cannot start one) and their widths in ks.
 constexpr int kStageRunMax = 8;
-int form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks);
+int form_stage_run(const Op* ops, size_t nops, size_t i, int stage_t, int nloc, bool fold, int* ks,
+                   int dtype = 0);
 
 }  // namespace sv
 

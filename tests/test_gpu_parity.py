@@ -255,10 +255,12 @@ def test_dense_on_sliced_qubit_rejected():
         sv.destroy_state(h)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n", [12, 14, 18])
-def test_staged_multiblock_pass(n):
+def test_staged_multiblock_pass(n, dtype):
     """Runs of 4/5-qubit blocks sharing an LDS tile go through one staged HBM
-    pass; the result equals one pass per block and the oracle."""
+    pass (complex64: split-fp16 form; complex128: FP64 form); the result
+    equals one pass per block and the oracle."""
     rng = np.random.default_rng(n)
     psi = W.random_state(n, rng)
     ops = []
@@ -269,11 +271,11 @@ def test_staged_multiblock_pass(n):
         ops.append((qs, W.random_unitary(1 << k, rng)))
     outs = {}
     for stage in (12, 0):
-        h, t = state_from_numpy(psi, "c64")
+        h, t = state_from_numpy(psi, dtype)
         try:
             sv.set_option(h, sv.SV_OPT_STAGE, stage)
             for qs, u in ops:
-                sv.apply_fused(h, qs, u, "c64")
+                sv.apply_fused(h, qs, u, dtype)
             outs[stage] = read_all(h, n)
             cnt = sv.counters(h)
         finally:
@@ -283,14 +285,16 @@ def test_staged_multiblock_pass(n):
     ref = psi.copy()
     for qs, u in ops:
         orc.apply_dense(ref, qs, u)
-    assert orc.rel_l2(outs[12], ref) <= 1e-5
-    assert orc.rel_l2(outs[0], ref) <= 1e-5
-    assert orc.rel_l2(outs[12], outs[0]) <= 1e-6
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    assert orc.rel_l2(outs[12], ref) <= tol
+    assert orc.rel_l2(outs[0], ref) <= tol
+    assert orc.rel_l2(outs[12], outs[0]) <= (1e-6 if dtype == "c64" else 1e-13)
 
 
+@pytest.mark.parametrize("dtype", ["c64", "c128"])
 @pytest.mark.parametrize("n,tmax", [(12, 12), (14, 9), (15, 10), (17, 11), (18, 12), (13, 13), (19, 13),
                                     (14, 14), (21, 14)])
-def test_staged_pass_any_positions(n, tmax):
+def test_staged_pass_any_positions(n, tmax, dtype):
     """Staged passes over blocks whose targets lie anywhere (no position
     limit), with tiles widened to the largest width allowed: equal to one
     pass per block and to the oracle; the widened tile still holds every
@@ -307,11 +311,11 @@ def test_staged_pass_any_positions(n, tmax):
         ops.append((qs, W.random_unitary(1 << k, rng)))
     outs = {}
     for stage in (tmax, 0):
-        h, t = state_from_numpy(psi, "c64")
+        h, t = state_from_numpy(psi, dtype)
         try:
             sv.set_option(h, sv.SV_OPT_STAGE, stage)
             for qs, u in ops:
-                sv.apply_fused(h, qs, u, "c64")
+                sv.apply_fused(h, qs, u, dtype)
             outs[stage] = read_all(h, n)
             cnt = sv.counters(h)
         finally:
@@ -321,9 +325,10 @@ def test_staged_pass_any_positions(n, tmax):
     ref = psi.copy()
     for qs, u in ops:
         orc.apply_dense(ref, qs, u)
-    assert orc.rel_l2(outs[tmax], ref) <= 1e-5
-    assert orc.rel_l2(outs[0], ref) <= 1e-5
-    assert orc.rel_l2(outs[tmax], outs[0]) <= 1e-6
+    tol = 1e-5 if dtype == "c64" else 1e-12
+    assert orc.rel_l2(outs[tmax], ref) <= tol
+    assert orc.rel_l2(outs[0], ref) <= tol
+    assert orc.rel_l2(outs[tmax], outs[0]) <= (1e-6 if dtype == "c64" else 1e-13)
 
 
 def test_sweep_profile_splits_kinds():
@@ -616,3 +621,31 @@ def test_headline_configuration_full_size():
     finally:
         sv.destroy_state(h)
         del buf
+
+
+@pytest.mark.parametrize("n", [18, 21])
+def test_c128_staged_circuit_from_reset(n):
+    """A planned circuit on a complex128 state through FP64 staged passes
+    from a reset (the first pass builds its tiles from |0...0>, later ones
+    take stale memory on newly reached positions as zero, the last one sums
+    the norm), run twice so the second run starts over the first one's
+    amplitudes: both equal the oracle to 1e-12, norm included."""
+    _torch()
+    circ = W.sycamore_circuit(n, 10, seed=900 + n)
+    ops = planner.plan(circ.gates, 5, sparse_start=True)
+    bits = W.bitstrings(n, 512, seed=n)
+    ref = orc.simulate(circ)
+    st = sv.State(n, 0, "c128")
+    try:
+        sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
+        packed = planner.pack(ops, sv.SV_C128)
+        for _ in range(2):
+            sv.reset(st.h)
+            planner.enqueue(st.h, packed, sv.SV_C128)
+            amps, stats = sv.reduce_slices(st.h, bits)
+            assert orc.rel_l2(amps, orc.gather(ref, bits)) <= 1e-12
+            assert abs(stats[0] - 1.0) <= 1e-12
+        cnt = sv.counters(st.h)
+    finally:
+        st.close()
+    assert cnt["staged_blocks"] >= 4, cnt
