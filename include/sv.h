@@ -274,11 +274,12 @@ enum {
     SV_OPT_FOLD_DIAG = 3,  /* 1 (default): fold a diagonal op into the preceding dense sweep */
     SV_OPT_SLOTS = 4,      /* tier: number of device slice slots (>= 2) */
     SV_OPT_STAGE = 5,      /* widest LDS tile (9..14 positions, default 13) for running a
-                              run of consecutive 4/5-qubit complex64 blocks in one pass
-                              over HBM (14: one 512-lane workgroup per CU holding the
+                              run of consecutive 4/5-qubit blocks in one pass over HBM
+                              (complex64: 14 = one 512-lane workgroup per CU holding the
                               whole LDS, used only when a run's targets need 14
-                              positions); 0: one pass per block; other values:
-                              SV_EINVAL */
+                              positions; complex128: one 512-lane workgroup per CU, tiles
+                              of at most 13 positions, products on the FP64 matrix
+                              cores); 0: one pass per block; other values: SV_EINVAL */
     SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer
                               from now on (n >= 1) is not issued and reports SV_EIO,
                               poisoning the handle; 0 (default): off */
