@@ -743,19 +743,25 @@ def bench_contract(args) -> int:
     p2, _ = sv.device_buffer(states[1].h)
     out = torch.empty(1 << (n1 + n2), dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream()
-    for _ in range(args.warmup):
-        sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream)
-    torch.cuda.synchronize()
-    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-           for _ in range(args.steps)]
-    t0 = time.perf_counter()
-    for a, b in evs:
-        a.record(stream)
-        sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream)
-        b.record(stream)
-    torch.cuda.synchronize()
-    t = (time.perf_counter() - t0) / args.steps
-    kms = sum(a.elapsed_time(b) for a, b in evs) / args.steps
+
+    def timed(fp32):
+        for _ in range(args.warmup):
+            sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream, fp32=fp32)
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        t0 = time.perf_counter()
+        for a, b in evs:
+            a.record(stream)
+            sv.contract(p1, p2, out.data_ptr(), n1, n2, e, "c64", stream.cuda_stream, fp32=fp32)
+            b.record(stream)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps, sum(a.elapsed_time(b) for a, b in evs) / args.steps
+
+    # the fp32 3M form for comparison, then the split-fp16 form (the default,
+    # whose output the sampled check below reads)
+    t32, kms32 = timed(True)
+    t, kms = timed(False)
     flops = 8.0 * float(1 << (n1 + n2)) * float(1 << e)        # complex multiply-add per term
     hbm = 8.0 * ((1 << nt1) + (1 << nt2) + (1 << (n1 + n2)))     # read both tensors, write the joint state
     # sampled outputs against the oracle's own tensors (never the GPU's)
@@ -813,10 +819,13 @@ def bench_contract(args) -> int:
         res = runner.simulate_deferred(circ, W.bitstrings(n, 1 << 16, seed=2006), sp.part1,
                                        args.defer_cycles, kmax=args.kmax)
     tf = flops / (kms * 1e-3) / 1e12
-    # the kernel's own arithmetic: three real products (3M form), 6 flops
-    # per complex multiply-add; the roofline is priced on those
+    # the kernel's own arithmetic: four real products of three split terms
+    # on the fp16 matrix cores, 24 flops per complex multiply-add; the
+    # roofline is priced on those (the fp32 form: three real products, 3M)
+    flops_split = 3.0 * flops
+    tf16 = flops_split / (kms * 1e-3) / 1e12
     flops_3m = 0.75 * flops
-    tf3 = flops_3m / (kms * 1e-3) / 1e12
+    tf3 = flops_3m / (kms32 * 1e-3) / 1e12
     line = {
         "metric": "contraction deferral: tensor 1 x tensor 2 contraction TFLOP/s "
                   "(complex-equivalent, 8 flops per complex multiply-add)",
@@ -828,24 +837,25 @@ def bench_contract(args) -> int:
                                f"two tensors of {nt1} and {nt2} qubits ({e} entanglement indices), "
                                f"contracted into the 2^{n1 + n2} joint state",
                    "n": n, "n1": n1, "n2": n2, "e": e, "bridging_gates": sp.n_bridging},
-        "roofline": {"bound": "mfma", "achieved": round(tf3, 2), "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tf3 / FP32_PEAK_TFLOPS, 4), "traffic": contract_traffic(),
-                     "kernel": "k_contract_mfma (3M form on FP32 matrix cores)",
-                     "avg_launch_ms": round(kms, 4), "flops_per_launch": flops_3m,
-                     "flops": "6 M N K: the 3M form's three real M x N x K products",
+        "roofline": {"bound": "mfma", "achieved": round(tf16, 2), "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(tf16 / FP16_PEAK_TFLOPS, 4), "traffic": None,
+                     "kernel": "k_contract_split (split-fp16 form: complex64 products at single-precision "
+                               "accuracy on the fp16 matrix cores)",
+                     "avg_launch_ms": round(kms, 4), "flops_per_launch": flops_split,
+                     "flops": "24 M N K: four real M x N x K products of three split terms each",
                      "complex_equivalent_tflops": round(tf, 2),
-                     # the complex-equivalent rate (8 M N K) exceeds the FP32
-                     # peak only because the 3M form does 3/4 of that arithmetic
-                     "complex_equivalent_frac": round(tf / FP32_PEAK_TFLOPS, 4),
-                     "note": "frac counts the flops the kernel issues (3M form); complex_equivalent_frac "
-                             "counts 8 flops per complex multiply-add and can exceed 1 only because the "
-                             "3M form does three quarters of that arithmetic",
-                     "hbm": {"bytes_per_launch": hbm, "achieved_gbs": round(hbm / (kms * 1e-3) / 1e9, 1),
-                             # counter traffic (L2 refills, mostly from the last-level
-                             # cache) as a rate: far below HBM bandwidth, so the
-                             # refills cost the matrix-core-bound kernel no time
-                             "traffic_gbs": None if contract_traffic() is None else
-                             round(contract_traffic() / (kms * 1e-3) / 1e9, 1)}},
+                     "complex_equivalent_frac_of_fp32_peak": round(tf / FP32_PEAK_TFLOPS, 4),
+                     "hbm": {"bytes_per_launch": hbm, "achieved_gbs": round(hbm / (kms * 1e-3) / 1e9, 1)},
+                     "fp32_form": {"kernel": "k_contract_mfma (3M form on FP32 matrix cores)",
+                                   "avg_launch_ms": round(kms32, 4), "achieved": round(tf3, 2),
+                                   "peak": FP32_PEAK_TFLOPS, "frac": round(tf3 / FP32_PEAK_TFLOPS, 4),
+                                   "flops": "6 M N K: the 3M form's three real M x N x K products",
+                                   "traffic": contract_traffic(),
+                                   # counter traffic (L2 refills, mostly from the last-level
+                                   # cache) as a rate: far below HBM bandwidth, so the refills
+                                   # cost the matrix-core-bound kernel no time
+                                   "traffic_gbs": None if contract_traffic() is None else
+                                   round(contract_traffic() / (kms32 * 1e-3) / 1e9, 1)}},
         "sampled_rel_l2_vs_oracle": err, "oracle_sample_s": t_or,
         "pipeline": None if res is None else
         {"t_run_s": round(res["t_run"], 3), "t_tensors_s": round(res["t_tensors"], 3),

@@ -410,10 +410,16 @@ const char* sv_batch_error(sv_batch b);
  *   indices in the same order; out: device buffer of 2^(n1+n2) amplitudes
  *   (caller-owned, overwritten, not overlapping the inputs).  dtype SV_C64
  *   (FP32 sums, on the matrix cores when 2^n2 >= 128, 2^n1 >= 64 and
- *   2^e >= 16) or SV_C128 (FP64 sums).  All buffers 16-byte aligned.
+ *   2^e >= 16: by default on the fp16 matrix cores at single-precision
+ *   accuracy, each tensor scaled by a power of two from its largest
+ *   |component| and every value split into two fp16 parts, with two 8-byte
+ *   words of stream-ordered device memory for the scales; | SV_CONTRACT_FP32
+ *   for the 3M form on the fp32 matrix cores) or SV_C128 (FP64 sums).  All
+ *   buffers 16-byte aligned.
  *   hip_stream: stream to run on (NULL: the null stream); asynchronous.
  *   Errors: SV_EINVAL (NULL or misaligned buffer, e above 30, n1 + n2, n1 + e
  *   or n2 + e above 40, overlap), SV_EDEVICE; the text is last_error(NULL). */
+enum { SV_CONTRACT_FP32 = 0x1000 };
 int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e, int dtype, void* hip_stream);
 
 #ifdef __cplusplus

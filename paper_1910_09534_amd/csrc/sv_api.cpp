@@ -1825,6 +1825,8 @@ int sv_sweep_time(sv_handle h, double* total_ms, int64_t* count)
 
 int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e, int dtype, void* hip_stream)
 {
+    const bool split = !(dtype & SV_CONTRACT_FP32);
+    dtype &= ~SV_CONTRACT_FP32;
     if (!t1 || !t2 || !out) return set_err(nullptr, SV_EINVAL, "sv_contract: NULL buffer");
     if (dtype != SV_C64 && dtype != SV_C128) return set_err(nullptr, SV_EINVAL, "sv_contract: bad dtype");
     if (n1 < 0 || n2 < 0 || e < 0 || e > 30 || n1 + n2 > 40 || n1 + e > 40 || n2 + e > 40)
@@ -1838,7 +1840,7 @@ int sv_contract(const void* t1, const void* t2, void* out, int n1, int n2, int e
         const uintptr_t p0 = (uintptr_t)p, p1 = p0 + (amp << (np + e));
         if (p0 < o1 && o0 < p1) return set_err(nullptr, SV_EINVAL, "sv_contract: output overlaps an input");
     }
-    const hipError_t err = launch_contract((hipStream_t)hip_stream, t1, t2, out, n1, n2, e, dtype);
+    const hipError_t err = launch_contract((hipStream_t)hip_stream, t1, t2, out, n1, n2, e, dtype, split);
     if (err != hipSuccess) return fail_dev(nullptr, "sv_contract launch", err);
     return SV_OK;
 }

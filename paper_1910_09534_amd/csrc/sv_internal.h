@@ -147,7 +147,7 @@ uint64_t stage_visits(int nloc, int nops, const int* ks, const int* const* pos, 
 // sum_e t1[e 2^n1 + x1] t2[e 2^n2 + x2] (complex64 or complex128).
 bool contract_uses_mfma(int dtype, int n1, int n2, int e);
 hipError_t launch_contract(hipStream_t st, const void* t1, const void* t2, void* out, int n1, int n2, int e,
-                           int dtype);
+                           int dtype, bool split = true);
 
 // Zeroes every amplitude whose index has a bit outside `support`.
 hipError_t launch_zero_outside(hipStream_t st, void* psi, int dtype, int nloc, uint64_t support);

@@ -309,10 +309,17 @@ def sweep_profile(h) -> dict:
             for i, kind in enumerate(("sweep", "staged"))}
 
 
-def contract(t1_ptr: int, t2_ptr: int, out_ptr: int, n1: int, n2: int, e: int, dtype, stream=None) -> None:
+SV_CONTRACT_FP32 = 0x1000
+
+
+def contract(t1_ptr: int, t2_ptr: int, out_ptr: int, n1: int, n2: int, e: int, dtype, stream=None,
+             fp32: bool = False) -> None:
     """out[x2 2^n1 + x1] = sum_c t1[c 2^n1 + x1] t2[c 2^n2 + x2] on device
-    buffers (see sv_contract in include/sv.h).  Asynchronous on `stream`."""
-    _check(lib().sv_contract(t1_ptr, t2_ptr, out_ptr, n1, n2, e, _dtype_code(dtype), stream))
+    buffers (see sv_contract in include/sv.h).  Asynchronous on `stream`.
+    fp32: complex64 products in the 3M form on the fp32 matrix cores instead
+    of the split-fp16 form."""
+    code = _dtype_code(dtype) | (SV_CONTRACT_FP32 if fp32 else 0)
+    _check(lib().sv_contract(t1_ptr, t2_ptr, out_ptr, n1, n2, e, code, stream))
 
 
 def _bcheck(rc: int, b=None):
