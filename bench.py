@@ -838,7 +838,7 @@ def bench_contract(args) -> int:
                                f"contracted into the 2^{n1 + n2} joint state",
                    "n": n, "n1": n1, "n2": n2, "e": e, "bridging_gates": sp.n_bridging},
         "roofline": {"bound": "mfma", "achieved": round(tf16, 2), "peak": FP16_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(tf16 / FP16_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(tf16 / FP16_PEAK_TFLOPS, 4), "traffic": contract_traffic(),
                      "kernel": "k_contract_split (split-fp16 form: complex64 products at single-precision "
                                "accuracy on the fp16 matrix cores)",
                      "avg_launch_ms": round(kms, 4), "flops_per_launch": flops_split,
@@ -850,12 +850,12 @@ def bench_contract(args) -> int:
                                    "avg_launch_ms": round(kms32, 4), "achieved": round(tf3, 2),
                                    "peak": FP32_PEAK_TFLOPS, "frac": round(tf3 / FP32_PEAK_TFLOPS, 4),
                                    "flops": "6 M N K: the 3M form's three real M x N x K products",
-                                   "traffic": contract_traffic(),
+                                   "traffic": contract_traffic("k_contract_mfma"),
                                    # counter traffic (L2 refills, mostly from the last-level
                                    # cache) as a rate: far below HBM bandwidth, so the refills
                                    # cost the matrix-core-bound kernel no time
-                                   "traffic_gbs": None if contract_traffic() is None else
-                                   round(contract_traffic() / (kms32 * 1e-3) / 1e9, 1)}},
+                                   "traffic_gbs": None if contract_traffic("k_contract_mfma") is None else
+                                   round(contract_traffic("k_contract_mfma") / (kms32 * 1e-3) / 1e9, 1)}},
         "sampled_rel_l2_vs_oracle": err, "oracle_sample_s": t_or,
         "pipeline": None if res is None else
         {"t_run_s": round(res["t_run"], 3), "t_tensors_s": round(res["t_tensors"], 3),
@@ -923,9 +923,9 @@ def bench_permute(args) -> int:
     return 0
 
 
-def contract_traffic():
-    """HBM bytes per k_contract_mfma launch from the committed counter runs,
-    or None when the kernel source changed since."""
+def contract_traffic(kernel: str = "k_contract_split"):
+    """HBM bytes per launch of a contraction kernel from the committed
+    counter runs, or None when the kernel source changed since."""
     path = os.path.join(ROOT, "profiles", "contract_30q_traffic.json")
     if not os.path.exists(path):
         return None
@@ -933,7 +933,7 @@ def contract_traffic():
         d = json.load(f)
     if d.get("source_hash") != source_hash("paper_1910_09534_amd/csrc/sv_contract.hip"):
         return None
-    return d.get("traffic_bytes_per_launch")
+    return d.get("per_kernel", {}).get(kernel, {}).get("traffic_bytes_per_launch")
 
 
 def profile_traffic(name: str, source: str):
