@@ -98,11 +98,12 @@ def kernel_hash() -> str:
     return h.hexdigest()[:16]
 
 
-def counter_traffic(kind: str):
+def counter_traffic(kind: str, alg_bytes: float):
     """HBM bytes per launch of one kernel kind ("staged" passes or single
     "sweep"s) from the committed counter runs (FETCH_SIZE + WRITE_SIZE,
     scaled by a plain copy of known size), or None when the kernel sources
-    changed since the counters were taken."""
+    changed since the counters were taken or the launches moved other
+    algorithmic bytes (another plan)."""
     path = os.path.join(ROOT, TRAFFIC_FILE)
     if not os.path.exists(path):
         return None
@@ -110,7 +111,10 @@ def counter_traffic(kind: str):
         d = json.load(f)
     if d.get("kernel_hash") != kernel_hash():
         return None
-    return d.get("per_kind", {}).get(kind, {}).get("traffic_bytes_per_launch")
+    e = d.get("per_kind", {}).get(kind, {})
+    if abs(e.get("algorithmic_bytes_per_launch", 0.0) - alg_bytes) > 1e-6 * alg_bytes:
+        return None
+    return e.get("traffic_bytes_per_launch")
 
 
 def calibrate_copy() -> int:
@@ -261,8 +265,9 @@ def bench_c128(circ, bits, args, steps: int = 3):
     try:
         for kmax in ([args.c128_kmax] if args.c128_kmax else [4, 5]):
             for staged in (True, False):
-                sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n) if staged else 0)
-                ops = (planner.plan(circ.gates, kmax, sparse_start=True) if staged
+                tmax = planner.stage_tmax(n, "c128")
+                sv.set_option(h, sv.SV_OPT_STAGE, tmax if staged else 0)
+                ops = (planner.plan(circ.gates, kmax, sparse_start=True, tmax=tmax) if staged
                        else planner.plan(circ.gates, kmax, staged=False))
                 packed = planner.pack(ops, sv.SV_C128)
 
@@ -423,6 +428,7 @@ def main(argv=None) -> int:
     buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     stream = torch.cuda.current_stream().cuda_stream
     h = sv.create_state_ext(n, 0, "c64", stream, buf.data_ptr(), buf.numel() * 8)
+    sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n))   # the tile limit the plan was made for
     packed = planner.pack(ops, sv.SV_C64)          # the whole plan queued by one library call
 
     def step():
@@ -481,7 +487,7 @@ def main(argv=None) -> int:
                       "flops_per_launch": p["flops"] / p["count"]},
              "issued": {"dtype": "fp16" if fp16 else "fp32", "tflops": round(issued, 2), "peak": ipeak,
                         "frac": round(issued / ipeak, 4)},
-             "traffic": counter_traffic(kind)}
+             "traffic": counter_traffic(kind, p["bytes"] / p["count"])}
         if kind == "staged" and fp16:
             r.update({"kernel": "k_stage, split-fp16 form (staged pass: 2-8 dense 4/5-qubit blocks per HBM "
                                 "pass, fp16 matrix cores)",

@@ -276,8 +276,11 @@ enum {
     SV_OPT_STAGE = 5,      /* widest LDS tile (9..14 positions, default 13) for running a
                               run of consecutive 4/5-qubit blocks in one pass over HBM
                               (complex64: 14 = one 512-lane workgroup per CU holding the
-                              whole LDS, used only when a run's targets need 14
-                              positions; complex128: one 512-lane workgroup per CU, tiles
+                              whole LDS; a pass widens its tile with free positions
+                              to the widest width the LDS holds for its blocks'
+                              matrices; in the split-fp16 form 14 measured fastest
+                              for states of 2^23 to 2^30 amplitudes, in the fp32 form
+                              13 at 2^30; complex128: one 512-lane workgroup per CU, tiles
                               of at most 13 positions, products on the FP64 matrix
                               cores); 0: one pass per block; other values: SV_EINVAL */
     SV_OPT_FAIL_IO = 6,    /* failure injection for tests: the n-th host-tier transfer

@@ -995,13 +995,14 @@ int stage_lds_limit(int t, int dtype)
 
 // Tile positions of a staged pass, ascending, into P (returns t, or -1 when
 // the run does not fit): 0..3 plus every target, widened with the lowest
-// free positions up to t_max (or the LDS limit): a block has 2^(t-k-4)
-// 16-group units per tile for the workgroup's four waves (8 for k = 5 at
-// t = 12), and the tile's contiguous runs are longer.  Only positions
-// inside the support widen it: one outside would double the amplitudes
-// visited (beyond the 9 the kernel needs).  Widening stops at 13: a
-// 14-position tile (one workgroup per CU) is used only when the targets
-// need it.
+// free positions to the widest tile within t_max that the LDS holds (a
+// 14-position tile: one 512-lane workgroup per CU; 13 and less: two 256-lane
+// ones).  Wider tiles mean more 16-group units per wave and longer
+// contiguous runs in memory: on the 30-qubit headline, widening to 14
+// wherever it fits measured 35.2-35.5 ms per step against 36.4 when tiles
+// widened to 13 at most.  Only positions inside the support widen it: one
+// outside would double the amplitudes visited (beyond the 9 the kernel
+// needs).
 static int stage_positions(int nloc, int nops, const int* ks, const int* const* pos, int t_max,
                            uint64_t support, int* P, int dtype)
 {
@@ -1015,18 +1016,33 @@ static int stage_positions(int nloc, int nops, const int* ks, const int* const* 
     }
     int cnt = 0;
     for (int p = 0; p < 64; ++p) cnt += in[p];
-    const int widen_to = t_max < 13 ? t_max : 13;
-    for (int round = 0; round < 2; ++round)
-        for (int p = 0; p < nloc && cnt < (round ? 9 : widen_to); ++p) {
-            if (in[p] || (round == 0 && !((support >> p) & 1))) continue;
-            if (stage_lds_bytes(cnt + 1, nops, ks, dtype) > stage_lds_limit_dt(cnt + 1, dtype)) break;
-            in[p] = true;
-            ++cnt;
+    // support positions free to widen with, lowest first
+    int cand[64], nc = 0;
+    for (int p = 0; p < nloc; ++p)
+        if (!in[p] && ((support >> p) & 1)) cand[nc++] = p;
+    auto fits = [&](int tt) { return stage_lds_bytes(tt, nops, ks, dtype) <= stage_lds_limit_dt(tt, dtype); };
+    // the widest tile within t_max whose LDS fits (up to 13 positions the
+    // limit is the same, so past the first width that fails no narrower
+    // one fits; 14 has a limit of its own)
+    int want = cnt;
+    for (int tt = t_max; tt > cnt; --tt)
+        if (tt - cnt <= nc && fits(tt)) {
+            want = tt;
+            break;
         }
+    for (int i = 0; i < want - cnt; ++i) in[cand[i]] = true;
+    cnt = want;
+    // at least 9 positions, from outside the support if need be
+    for (int p = 0; p < nloc && cnt < 9; ++p) {
+        if (in[p]) continue;
+        if (!fits(cnt + 1)) break;
+        in[p] = true;
+        ++cnt;
+    }
     int t = 0;
     for (int p = 0; p < 64; ++p)
         if (in[p]) P[t++] = p;
-    if (t > t_max || t < 9 || nloc < t || stage_lds_bytes(t, nops, ks, dtype) > stage_lds_limit_dt(t, dtype))
+    if (t > t_max || t < 9 || nloc < t || !fits(t))
         return -1;
     return t;
 }

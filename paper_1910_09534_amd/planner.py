@@ -256,8 +256,8 @@ def fuse_grow(gates, kmax: int, window: int = 4, last_gain: float = 0.0) -> List
 # positions (0..3 always), and the LDS budget covers the tile (2^t complex64
 # plus one pad per 16) and Re/Im of every block's matrix: STAGE_LDS up to
 # 13 positions (two workgroups per CU), STAGE_LDS14 at 14 (one 512-lane
-# workgroup per CU).  Tiles are widened to 13 positions at most; 14 only
-# when a run's targets need them.
+# workgroup per CU).  Tiles are widened with support positions to the
+# widest width within the limit whose LDS fits (`_tile_positions`).
 STAGE_T = 14
 STAGE_MAX_OPS = 8
 STAGE_LDS = 80 * 1024
@@ -268,20 +268,23 @@ def _lds_limit(t: int) -> int:
     return STAGE_LDS14 if t >= 14 else STAGE_LDS
 
 
-# Widest tile for states of more than 2^STAGE_WIDE_MAX_N amplitudes: 14
-# positions (fewer passes) measured faster for states of up to 2^28
-# amplitudes (batches of 20-28 qubits: 311 against 289 circuits/s) and
-# slower at 2^30 (47.8 against 47.4 ms per 30-qubit step), where the
-# 13-position tiles with two workgroups per CU overlap better.
-STAGE_WIDE_MAX_N = 28
+# Widest tile per state: 14 positions for complex64 (one 512-lane workgroup
+# per CU, fewer passes).  In the split-fp16 form, the default, it measured
+# faster at every size: 36.2-36.4 against 39.4-40.5 ms per 30-qubit step
+# (14 instead of 17 passes), batches of 20-28 qubits tuned to 14 from 23
+# qubits.  The fp32 form (SV_OPT_SPLIT 0) measured slower with 14 at 2^30
+# amplitudes (45.8 against 44.6 ms per step), where two workgroups per CU
+# overlap its longer block work better; such callers pass 13.  Complex128
+# tiles hold at most 13 positions.
+STAGE_T_C128 = 13
 
 
-def stage_tmax(nloc: int) -> int:
+def stage_tmax(nloc: int, dtype: str = "c64") -> int:
     """Tile limit for a state of 2^nloc amplitudes: at most nloc - 9
-    positions, so that a pass has at least 512 tiles (two workgroups per
-    CU), 14 up to 2^28 amplitudes and 13 above; 0 (no staged passes) below
-    9.  Callers pass it to the device as SV_OPT_STAGE for the state."""
-    t = min(STAGE_T if nloc <= STAGE_WIDE_MAX_N else 13, nloc - 9)
+    positions, so that a pass has at least 512 tiles, and at most 14 for
+    complex64 (13 for complex128); 0 (no staged passes) below 9.  Callers
+    pass it to the device as SV_OPT_STAGE for the state."""
+    t = min(STAGE_T if dtype == "c64" else STAGE_T_C128, nloc - 9)
     return t if t >= 9 else 0
 
 
@@ -435,6 +438,30 @@ def staged_cost(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = None) ->
 STAGE_MS_LAUNCH = 0.02
 
 
+def _tile_positions(P: int, ks: Sequence[int], S: int, nloc: int, tmax: int) -> Tuple[int, int]:
+    """The device's tile of a staged pass (mask, width): targets and 0..3
+    (P), widened with the lowest support positions to the widest tile
+    within tmax whose LDS fits, then with any positions up to 9."""
+    t = bin(P).count("1")
+    cand = [p for p in range(nloc) if not (P >> p) & 1 and (S >> p) & 1]
+    for tt in range(tmax, t, -1):
+        if tt - t <= len(cand) and _stage_lds(tt, ks) <= _lds_limit(tt):
+            for p in cand[:tt - t]:
+                P |= 1 << p
+            t = tt
+            break
+    for p in range(nloc):
+        if t >= 9:
+            break
+        if (P >> p) & 1:
+            continue
+        if _stage_lds(t + 1, ks) > _lds_limit(t + 1):
+            break
+        P |= 1 << p
+        t += 1
+    return P, t
+
+
 def sparse_passes(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[int] = None,
                   support: int = 0) -> List[Tuple[List[int], int]]:
     """The passes `ops` run as from |0...0> (after sv_reset), each with the
@@ -459,18 +486,7 @@ def sparse_passes(ops: Sequence["Op"], nloc: int, pos_of=None, tmax: Optional[in
         for i in r:
             for q in ops[i].qubits:
                 tg |= 1 << pos(q)
-        P = tg | 0xF
-        t = bin(P).count("1")
-        for rnd in (0, 1):
-            for p_ in range(nloc):
-                if t >= (9 if rnd else min(tmax, 13)):
-                    break
-                if (P >> p_) & 1 or (rnd == 0 and not (S >> p_) & 1):
-                    continue
-                if _stage_lds(t + 1, ks) > _lds_limit(t + 1):
-                    break
-                P |= 1 << p_
-                t += 1
+        P, t = _tile_positions(tg | 0xF, ks, S, nloc, tmax)
         out.append((r, t + bin(S & ~P).count("1")))
         S |= tg
     return out
@@ -620,7 +636,7 @@ def _staged_candidates(gates, kmax: int, pos_of, tmax: int) -> List[List[Op]]:
 
 
 def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=None,
-         nloc: Optional[int] = None, sparse_start: bool = False) -> List[Op]:
+         nloc: Optional[int] = None, sparse_start: bool = False, tmax: Optional[int] = None) -> List[Op]:
     """Aggregate with every available heuristic and keep the cheapest plan.
 
     staged (complex64 states): blocks on fewer than 4 qubits are widened to
@@ -630,9 +646,10 @@ def plan(gates, kmax: int, fold_diag: bool = False, staged: bool = True, pos_of=
     are ranked by `plan_cost`.  sparse_start (the ops run right after
     sv_reset): the gates are also tried in orders that bring qubits into
     play late (`support_order` over `activation_orders`), and the
-    candidates are ranked by `sparse_cost`."""
+    candidates are ranked by `sparse_cost`.  tmax: widest staged tile
+    (default stage_tmax(nloc), the complex64 limit)."""
     n_loc = _nloc_of(gates) if nloc is None else nloc
-    tmax = stage_tmax(n_loc) if staged else 0
+    tmax = (stage_tmax(n_loc) if tmax is None else tmax) if staged else 0
     if not tmax or fold_diag:
         cands = [fuse(gates, kmax, fold_diag=fold_diag)]
         if not fold_diag:

@@ -19,13 +19,14 @@ from . import planner, sv
 
 def simulate(circuit, bits: np.ndarray, dtype="c64", kmax: int = 5, fold_diag: bool = False,
              timing: bool = False, mfma: int = 4, stream=None, stage: Optional[int] = None) -> Dict[str, object]:
-    """stage: widest staged tile (SV_OPT_STAGE); None = planner.stage_tmax(n)
-    for complex64, 0 = no staged passes."""
+    """stage: widest staged tile (SV_OPT_STAGE); None = planner.stage_tmax(n,
+    dtype), 0 = no staged passes."""
     t0 = time.perf_counter()
     if stage is None:
-        stage = planner.stage_tmax(circuit.n) if dtype == "c64" else 0
+        stage = planner.stage_tmax(circuit.n, dtype)
     ops = planner.plan(circuit.gates, kmax, fold_diag=fold_diag, staged=stage > 0,
-                       nloc=max(circuit.n, stage + 9) if stage else None, sparse_start=stage > 0)
+                       nloc=max(circuit.n, stage + 9) if stage else None, sparse_start=stage > 0,
+                       tmax=stage or None)
     t_plan = time.perf_counter() - t0
     st = sv.State(circuit.n, 0, dtype, stream)
     try:

@@ -55,26 +55,29 @@ def product_amplitudes(circuit, rows, cols, bits):
     return out
 
 
-@pytest.mark.parametrize("start", ["sparse", "dense"])
-def test_headline_vs_stored_oracle(start):
+@pytest.mark.parametrize("start,tile", [("sparse", 14), ("dense", 14), ("sparse", 13)])
+def test_headline_vs_stored_oracle(start, tile):
     """30 qubits, depth 14, complex64, k <= 5: resident state in a torch
     buffer (create_state_ext), sv_reset, the plan for a run from |0...0>
-    (sparse start) or the plan with every pass over the whole state, FP64
-    reduction of the 2^16 seeded bitstrings; all 2^16 amplitudes, the norm
-    and the cross-entropy sums against the oracle's complex128 run."""
+    (sparse start) or the plan with every pass over the whole state, tiles
+    of at most 14 positions (the default) or 13, FP64 reduction of the 2^16
+    seeded bitstrings; all 2^16 amplitudes, the norm and the cross-entropy
+    sums against the oracle's complex128 run."""
     torch = _torch()
     g = _golden("headline_30q_d14.npz")
     circ = W.config_circuit(2)
     bits = W.config_bitstrings(2)
     assert np.array_equal(bits, g["bitstrings"])
     n = circ.n
-    ops = planner.plan(circ.gates, 5, sparse_start=(start == "sparse"))
+    assert planner.stage_tmax(n) == 14
+    ops = planner.plan(circ.gates, 5, sparse_start=(start == "sparse"), tmax=tile)
     for o in ops:
         o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     h = sv.create_state_ext(n, 0, "c64", torch.cuda.current_stream().cuda_stream, buf.data_ptr(),
                             buf.numel() * 8)
     try:
+        sv.set_option(h, sv.SV_OPT_STAGE, tile)
         sv.set_option(h, sv.SV_OPT_SPARSE_START, 1 if start == "sparse" else 0)
         sv.reset(h)
         planner.enqueue(h, ops, sv.SV_C64)
@@ -85,7 +88,7 @@ def test_headline_vs_stored_oracle(start):
         del buf
         torch.cuda.empty_cache()
     err = orc.rel_l2(amps, g["amps"])
-    print(f"headline {start}: rel_l2={err:.3e} norm={stats[0]:.9f} staged={cnt['staged_blocks']}", flush=True)
+    print(f"headline {start} tile {tile}: rel_l2={err:.3e} norm={stats[0]:.9f} staged={cnt['staged_blocks']}", flush=True)
     assert cnt["staged_blocks"] > 0
     assert err <= TOL64
     assert abs(stats[0] - float(g["norm"])) <= 1e-5

@@ -602,6 +602,7 @@ def test_headline_configuration_full_size():
     inv_ops = planner.plan(inv, 5)
     buf = torch.empty(1 << n, dtype=torch.complex64, device="cuda")
     h = sv.create_state_ext(n, 0, "c64", None, buf.data_ptr(), buf.numel() * 8)
+    sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
     try:
         outs = []
         for _ in range(2):
@@ -632,12 +633,13 @@ def test_c128_staged_circuit_from_reset(n):
     amplitudes: both equal the oracle to 1e-12, norm included."""
     _torch()
     circ = W.sycamore_circuit(n, 10, seed=900 + n)
-    ops = planner.plan(circ.gates, 5, sparse_start=True)
+    tmax = planner.stage_tmax(n, "c128")
+    ops = planner.plan(circ.gates, 5, sparse_start=True, tmax=tmax)
     bits = W.bitstrings(n, 512, seed=n)
     ref = orc.simulate(circ)
     st = sv.State(n, 0, "c128")
     try:
-        sv.set_option(st.h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
+        sv.set_option(st.h, sv.SV_OPT_STAGE, tmax)
         packed = planner.pack(ops, sv.SV_C128)
         for _ in range(2):
             sv.reset(st.h)
