@@ -335,6 +335,38 @@ def bench_c128(circ, bits, args, steps: int = 3):
 GOLDEN_HEADLINE = os.path.join(ROOT, "tests", "golden", "headline_30q_d14.npz")
 
 
+def time_single_blocks(h, n: int, reps: int = 4) -> dict:
+    """One lone unitary 5-qubit block on the dense resident state (after the
+    headline steps), at three target sets: as a one-block staged pass (the
+    route a lone unitary block takes; tile of 14 positions) and as a plain
+    fused sweep (`k_dense_mfma`).  Best of `reps` launches, HIP events on
+    the state's stream; HBM fraction of the 16 B moved per amplitude."""
+    from paper_1910_09534_amd import planner, sv
+    from paper_1910_09534_amd import workload as W
+    u = W.random_unitary(32, np.random.default_rng(55)).astype(np.complex64)
+    out = {}
+    sv.set_option(h, sv.SV_OPT_TIMING, 1)
+    for qs in ([0, 1, 2, 3, 4], [10, 11, 12, 13, 14], [20, 21, 22, 23, 24]):
+        row = {}
+        for form, t in (("staged", planner.stage_tmax(n)), ("sweep", 0)):
+            sv.set_option(h, sv.SV_OPT_STAGE, t)
+            best = None
+            for _ in range(reps + 1):
+                sv.sweep_profile(h)
+                sv.apply_fused(h, qs, u, "c64")
+                sv.sync_state(h)
+                p = sv.sweep_profile(h)
+                ms = p["staged"]["ms"] + p["sweep"]["ms"]
+                by = p["staged"]["bytes"] + p["sweep"]["bytes"]
+                if best is None or ms < best[0]:
+                    best = (ms, by)
+            row[form] = {"ms": round(best[0], 4), "hbm_frac": round(best[1] / (best[0] * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)}
+        out["-".join(str(q) for q in (qs[0], qs[-1]))] = row
+    sv.set_option(h, sv.SV_OPT_TIMING, 0)
+    sv.set_option(h, sv.SV_OPT_STAGE, planner.stage_tmax(n))
+    return out
+
+
 def accuracy_vs_stored(amps, stats, bits):
     """Relative L2 error of the step's amplitudes against the complex128
     amplitudes the CPU oracle stored for the same circuit and bitstrings
@@ -381,6 +413,8 @@ def main(argv=None) -> int:
                     help="skip the serving summary in the default line")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests of the serving summary in the default line")
+    ap.add_argument("--no-single-block", action="store_true",
+                    help="leave out the lone 5-qubit block timings after the headline steps")
     ap.add_argument("--no-c128", action="store_true",
                     help="skip the complex128 form of the default workload")
     ap.add_argument("--c128-kmax", type=int, default=0,
@@ -468,6 +502,7 @@ def main(argv=None) -> int:
     if not args.no_dense_start:
         dense_ms, damps, dstats = time_dense_start(h, circ, bits, args)
         dense_acc = accuracy_vs_stored(damps, dstats, bits)
+    single = None if args.no_single_block else time_single_blocks(h, n)
 
     def kind_roof(kind):
         p = prof[kind]
@@ -546,6 +581,7 @@ def main(argv=None) -> int:
         "dense_start": None if dense_ms is None else
         {"ms_per_step": round(dense_ms, 3), "value": gates * float(1 << n) / (dense_ms * 1e-3),
          "rel_l2_vs_oracle": dense_acc and dense_acc["rel_l2_vs_oracle"]},
+        "single_block_30q": single,
         "block_amp_updates_per_s": ndense * float(1 << n) * args.steps / t,
         "norm": stats[0],
         "roofline": roof,

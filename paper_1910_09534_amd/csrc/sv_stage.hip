@@ -885,7 +885,9 @@ int stage_lds_bytes(int t, int nops, const int* ks, int dtype)
         const int tile_d4 = (((1 << t) + ((1 << t) >> 4)) * 16 + 31) / 32;
         return tile_d4 * 32 + scalars * 8;
     }
-    const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16 + 1;
+    // complex64: the padded tile (slots lslot(0 .. 2^t - 1), where the
+    // operand matrices start: see k_stage), then the matrices in float
+    const int tile_f4 = ((1 << t) + ((1 << t) >> 4)) * 8 / 16;
     return tile_f4 * 16 + scalars * 4;
 }
 

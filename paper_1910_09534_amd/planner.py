@@ -289,7 +289,7 @@ def stage_tmax(nloc: int, dtype: str = "c64") -> int:
 
 
 def _stage_lds(t: int, ks: Sequence[int]) -> int:
-    tile = (((1 << t) + ((1 << t) >> 4)) * 8 // 16 + 1) * 16
+    tile = ((1 << t) + ((1 << t) >> 4)) * 8
     return tile + sum(2 * (1 << (2 * k)) for k in ks) * 4
 
 
