@@ -331,6 +331,41 @@ def test_staged_pass_any_positions(n, tmax, dtype):
     assert orc.rel_l2(outs[tmax], outs[0]) <= (1e-6 if dtype == "c64" else 1e-13)
 
 
+@pytest.mark.parametrize("n,stage,blocks", [
+    # three 5-qubit blocks on 14 positions: the tile and matrices fill the 160 KiB exactly
+    (18, 14, [[4, 6, 7, 9, 10], [12, 13, 15, 16, 17], [0, 6, 12, 17, 2]]),
+    # eight 4-qubit blocks on 14 positions (the most blocks a pass takes)
+    (18, 14, [[4, 6, 7, 9], [10, 12, 13, 15], [16, 17, 0, 4], [6, 10, 16, 1], [7, 12, 17, 2],
+              [9, 13, 3, 4], [15, 16, 6, 7], [0, 1, 12, 17]]),
+    # [5, 4, 4] on 13 positions: two workgroups' 80 KiB exactly
+    (17, 13, [[4, 5, 7, 8, 10], [11, 12, 14, 15], [4, 11, 1, 2]]),
+])
+def test_staged_pass_full_lds(n, stage, blocks):
+    """Runs whose tile and matrices fill the LDS budget exactly run as one
+    staged pass and equal one sweep per block and the oracle."""
+    rng = np.random.default_rng(7000 + n + len(blocks))
+    psi = W.random_state(n, rng)
+    ops = [(qs, W.random_unitary(1 << len(qs), rng)) for qs in blocks]
+    outs = {}
+    for st in (stage, 0):
+        h, t = state_from_numpy(psi, "c64")
+        try:
+            sv.set_option(h, sv.SV_OPT_STAGE, st)
+            for qs, u in ops:
+                sv.apply_fused(h, qs, u, "c64")
+            outs[st] = read_all(h, n)
+            cnt = sv.counters(h)
+        finally:
+            sv.destroy_state(h)
+        if st:
+            assert cnt["staged_blocks"] == len(blocks) and cnt["dense_sweeps"] == 1, cnt
+    ref = psi.copy()
+    for qs, u in ops:
+        orc.apply_dense(ref, qs, u)
+    assert orc.rel_l2(outs[stage], ref) <= 1e-5
+    assert orc.rel_l2(outs[stage], outs[0]) <= 1e-6
+
+
 def test_sweep_profile_splits_kinds():
     """With timing on, staged passes and single sweeps are reported apart,
     with their launch counts and the arithmetic of their blocks."""

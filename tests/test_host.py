@@ -92,17 +92,51 @@ def test_cfg2_plan_counts():
 
 def test_cfg2_sparse_plan_shape():
     """Regression pin on the 30-qubit depth-14 plan that the benchmark runs
-    from |0...0>: every gate once, at most 17 HBM passes, and the passes
-    visit at most 63 % of what as many full passes would (the device's
-    visit counter is checked against this model in a GPU test)."""
+    from |0...0> on 14-position tiles: every gate once, at most 13 HBM
+    passes, and the passes visit at most 58 % of what as many full passes
+    would (the device's visit counter is checked against this model in a
+    GPU test)."""
     c = W.config_circuit(2)
     tmax = planner.stage_tmax(c.n)
+    assert tmax == 14
     ops = planner.plan(c.gates, 5, sparse_start=True)
     assert sum(o.ngates for o in ops) == 621
     passes = planner.sparse_passes(ops, c.n, None, tmax)
-    assert len(passes) <= 17
+    assert len(passes) <= 13
     visited = sum(1 << lv for _, lv in passes) / (len(passes) * (1 << c.n))
-    assert visited <= 0.63
+    assert visited <= 0.58
+
+
+def test_stage_lds_budget_and_widening():
+    """The LDS a staged pass needs: the padded tile (each group of 16
+    elements takes 17 slots of 8 bytes: one pad per 16), then Re / Im of
+    every block's matrix in float.  Three 5-qubit blocks fill a
+    14-position tile's 160 KiB exactly, a fourth does not fit; [5, 4, 4]
+    fills a 13-position tile's 80 KiB (two workgroups per CU).  Widening
+    takes the widest tile within the limit whose LDS fits, from support
+    positions only (others only up to 9)."""
+    for t in range(9, 15):
+        slots = (1 << t) // 16 * 17
+        assert max(i + (i >> 4) for i in range(1 << t)) < slots          # every element's slot inside
+        assert planner._stage_lds(t, []) == slots * 8
+    assert planner._stage_lds(14, [5, 5, 5]) == planner.STAGE_LDS14 == 160 * 1024
+    assert planner._stage_lds(14, [5, 5, 5, 4]) > planner.STAGE_LDS14
+    assert planner._stage_lds(14, [4] * 8) <= planner.STAGE_LDS14
+    assert planner._stage_lds(13, [5, 4, 4]) == planner.STAGE_LDS == 80 * 1024
+    assert planner._stage_lds(13, [5, 5, 4]) > planner.STAGE_LDS
+    full = (1 << 30) - 1
+    tg = 0xF | sum(1 << p for p in (8, 9, 12, 13, 17, 20, 21, 25))     # 12 positions
+    mask = lambda ps: sum(1 << p for p in ps)                             # noqa: E731
+    # two 5-qubit blocks: widened to 14 with the two lowest free positions
+    assert planner._tile_positions(tg, [5, 5], full, 30, 14) == (tg | mask([4, 5]), 14)
+    # three fill 160 KiB at 14; 13 would need two workgroups' 80 KiB and fails
+    assert planner._tile_positions(tg, [5, 5, 5], full, 30, 14) == (tg | mask([4, 5]), 14)
+    assert planner._tile_positions(tg, [5, 5, 5], full, 30, 13) == (tg, 12)
+    # four do not fit 13 or 14 positions: the tile stays at its 12
+    assert planner._tile_positions(tg, [5, 5, 5, 5], full, 30, 14) == (tg, 12)
+    # only support positions widen it
+    assert planner._tile_positions(tg, [5, 5], mask([6, 29]) | tg, 30, 14) == (tg | mask([6, 29]), 14)
+    assert planner._tile_positions(0xF | mask([20, 21]), [4], 0, 30, 14) == (0xF | mask([4, 5, 6, 20, 21]), 9)
 
 
 def _declared_functions():
