@@ -80,9 +80,11 @@ def test_headline_vs_stored_oracle(start, tile):
         sv.set_option(h, sv.SV_OPT_STAGE, tile)
         sv.set_option(h, sv.SV_OPT_SPARSE_START, 1 if start == "sparse" else 0)
         sv.reset(h)
+        c0 = sv.counters(h)["amps_swept"]
         planner.enqueue(h, ops, sv.SV_C64)
         amps, stats = sv.reduce_slices(h, bits)
         cnt = sv.counters(h)
+        swept = cnt["amps_swept"] - c0
     finally:
         sv.destroy_state(h)
         del buf
@@ -90,6 +92,13 @@ def test_headline_vs_stored_oracle(start, tile):
     err = orc.rel_l2(amps, g["amps"])
     print(f"headline {start} tile {tile}: rel_l2={err:.3e} norm={stats[0]:.9f} staged={cnt['staged_blocks']}", flush=True)
     assert cnt["staged_blocks"] > 0
+    # the passes visit what the planner's model of the device says (tile
+    # widening, support growth); every pass visits the whole state otherwise
+    if start == "sparse":
+        model = sum(1 << lv for _, lv in planner.sparse_passes(ops, n, None, tile))
+    else:
+        model = len(planner.stage_runs(ops, None, tile)) * (1 << n)
+    assert swept == model, (swept, model)
     assert err <= TOL64
     assert abs(stats[0] - float(g["norm"])) <= 1e-5
     ref1, ref2 = (float(x) for x in g["xeb"])
