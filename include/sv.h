@@ -275,7 +275,8 @@ enum {
     SV_OPT_SLOTS = 4,      /* tier: number of device slice slots (>= 2) */
     SV_OPT_STAGE = 5,      /* widest LDS tile (9..14 positions, default 13) for running a
                               run of consecutive 4/5-qubit blocks in one pass over HBM
-                              (complex64: 14 = one 512-lane workgroup per CU holding the
+                              (complex64: 14 = one workgroup per CU, 1024 lanes in the split
+                              form and 512 in the fp32 form, holding the
                               whole LDS; a pass widens its tile with free positions
                               to the widest width the LDS holds for its blocks'
                               matrices; in the split-fp16 form 14 measured fastest

@@ -37,7 +37,13 @@ constexpr int kStageMaxLds14 = 160 * 1024;  // 14 positions: one 512-lane workgr
 
 // LDS a tile of t positions may use, and its workgroup size
 static inline int stage_lds_limit_t(int t) { return t >= 14 ? kStageMaxLds14 : kStageMaxLds; }
-static inline int stage_threads(int t) { return t >= 14 ? 512 : 256; }
+// lanes of a complex64 staged-pass workgroup: 256 for tiles of up to 13
+// positions; 14 positions take the whole LDS, one workgroup per CU, of 1024
+// lanes in the split form (four waves per SIMD to hide each tile's LDS and
+// barrier latency; the kernel fits 128 VGPRs with one 5-qubit or two
+// 4-qubit units per wave at a time) and 512 in the fp32 form (its 3M units
+// need more registers)
+static inline int stage_threads(int t, bool split) { return t >= 14 ? (split ? 1024 : 512) : 256; }
 
 struct StageK {
     uint64_t tiles;                          // 2^(nloc - t)
@@ -51,8 +57,8 @@ struct StageK {
     // zero but their memory may hold older values: tile-local index bits
     // (bit b = position P[b]) of such elements, parked in LDS as zeros
     uint32_t newmask_t;
-    uint64_t dep_lane[9];                    // global offset of element bit b (lane bits: 8, or 9 at t = 14)
-    uint64_t dep_i[32];                      // global offset of element bits 8.. (i = e >> 8)
+    uint64_t dep_lane[10];                   // global offset of lane bit b (8 lane bits; 9 or 10 at t = 14)
+    uint64_t dep_i[32];                      // global offset of the pair (element) index bits above the lane bits
     int t;
     int nops;
     int from_e0;                             // 1: input is |0...0>, not read
@@ -462,9 +468,10 @@ __device__ __forceinline__ void split_block(const StageK& a, int o, const void* 
             sy[4 * rb + v] = lslot(off);
         }
     // units wave, wave + nw, ... in groups of NG (4 for k = 4, whose units
-    // are short, 2 for k = 5); units / nw is a power of two, so a wave runs
-    // whole groups or fewer than NG units one by one
-    constexpr int NG = K == 4 ? 4 : 2;
+    // are short, 2 for k = 5; half that with 1024 lanes, which must fit 128
+    // VGPRs); units / nw is a power of two, so a wave runs whole groups or
+    // fewer than NG units one by one
+    constexpr int NG = NT >= 1024 ? (K == 4 ? 2 : 1) : (K == 4 ? 4 : 2);
     const int units = 1 << (a.t - K - 4);
     if (units >= NG * nw) {
         for (int unit = wave; unit < units; unit += NG * nw) {
@@ -481,7 +488,7 @@ __device__ __forceinline__ void split_block(const StageK& a, int o, const void* 
     }
 }
 
-// TW: tile width t (9..12), PER = 2^(t-8) elements per lane.  WIDE: the
+// TW: tile width t (9..14), PER = 2^t / lanes elements per lane.  WIDE: the
 // lane part of an element's address needs more than 32 bits of byte offset
 // (otherwise element addresses are a wave-uniform 64-bit base plus a 32-bit
 // per-lane offset, so loads and stores take the scalar-base form).
@@ -499,10 +506,10 @@ __host__ __device__ inline uint64_t spread_bits(uint64_t x, uint64_t m)
 }
 
 template <int TW, bool WIDE, bool ZERO, bool SPLIT>
-__global__ __launch_bounds__(TW >= 14 ? 512 : 256) void k_stage(float2* __restrict__ psi, StageK a)
+__global__ __launch_bounds__(TW >= 14 ? (SPLIT ? 1024 : 512) : 256) void k_stage(float2* __restrict__ psi, StageK a)
 {
     // lanes NT (2^LB), PER amplitudes per lane in PER / 2 adjacent pairs
-    constexpr int NT = TW >= 14 ? 512 : 256, LB = TW >= 14 ? 9 : 8;
+    constexpr int NT = TW >= 14 ? (SPLIT ? 1024 : 512) : 256, LB = TW >= 14 ? (SPLIT ? 10 : 9) : 8;
     constexpr int PER = 1 << (TW - LB);
     extern __shared__ f4 smem[];
     float2* T = (float2*)smem;                                   // tile, padded
@@ -1091,7 +1098,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     a.newmask_t = 0;
     for (int b = 0; b < t; ++b)
         if ((newmask >> P[b]) & 1) a.newmask_t |= 1u << b;
-    const int lb = (t >= 14 || dtype) ? 9 : 8;                  // lane bits of the tile index
+    const int lb = dtype ? 9 : (t >= 14 ? (split ? 10 : 9) : 8);  // lane bits of the tile index
     // complex64: tile bit 0 (position 0) pairs adjacent amplitudes; lane bit
     // b is tile bit b + 1; pair index bit c is tile bit lb + 1 + c.
     // complex128: lane bit b is tile bit b; element index bit c is tile bit
@@ -1148,7 +1155,7 @@ hipError_t launch_stage(hipStream_t st, void* psi, int nloc, int nops, const int
     if (dtype)
         hipLaunchKernelGGL(kern64, dim3((unsigned)grid), dim3(512), lds, st, (double2*)psi, a);
     else
-        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(stage_threads(t)), lds, st, (float2*)psi, a);
+        hipLaunchKernelGGL(kern, dim3((unsigned)grid), dim3(stage_threads(t, split)), lds, st, (float2*)psi, a);
     if (t_out) *t_out = t;
     if (norm_blocks) *norm_blocks = norm_out ? (int)grid : 0;
     if (tile_mask_out) *tile_mask_out = pmask;

@@ -255,7 +255,7 @@ def fuse_grow(gates, kmax: int, window: int = 4, last_gain: float = 0.0) -> List
 # holds at most STAGE_MAX_OPS 4/5-qubit blocks, the tile at most STAGE_T
 # positions (0..3 always), and the LDS budget covers the tile (2^t complex64
 # plus one pad per 16) and Re/Im of every block's matrix: STAGE_LDS up to
-# 13 positions (two workgroups per CU), STAGE_LDS14 at 14 (one 512-lane
+# 13 positions (two workgroups per CU), STAGE_LDS14 at 14 (one
 # workgroup per CU).  Tiles are widened with support positions to the
 # widest width within the limit whose LDS fits (`_tile_positions`).
 STAGE_T = 14
@@ -268,7 +268,7 @@ def _lds_limit(t: int) -> int:
     return STAGE_LDS14 if t >= 14 else STAGE_LDS
 
 
-# Widest tile per state: 14 positions for complex64 (one 512-lane workgroup
+# Widest tile per state: 14 positions for complex64 (one workgroup
 # per CU, fewer passes).  In the split-fp16 form, the default, it measured
 # faster at every size: 36.2-36.4 against 39.4-40.5 ms per 30-qubit step
 # (14 instead of 17 passes), batches of 20-28 qubits tuned to 14 from 23
