@@ -33,7 +33,7 @@ namespace sv {
 constexpr int kStageMaxOps = 8;
 constexpr int kStageMaxT = 14;
 constexpr int kStageMaxLds = 80 * 1024;     // tiles of up to 13 positions: two 256-lane workgroups per CU
-constexpr int kStageMaxLds14 = 160 * 1024;  // 14 positions: one 512-lane workgroup per CU
+constexpr int kStageMaxLds14 = 160 * 1024;  // 14 positions: one workgroup per CU
 
 // LDS a tile of t positions may use, and its workgroup size
 static inline int stage_lds_limit_t(int t) { return t >= 14 ? kStageMaxLds14 : kStageMaxLds; }
@@ -1005,7 +1005,7 @@ int stage_lds_limit(int t, int dtype)
 // Tile positions of a staged pass, ascending, into P (returns t, or -1 when
 // the run does not fit): 0..3 plus every target, widened with the lowest
 // free positions to the widest tile within t_max that the LDS holds (a
-// 14-position tile: one 512-lane workgroup per CU; 13 and less: two 256-lane
+// 14-position tile: one workgroup per CU; 13 and less: two or more 256-lane
 // ones).  Wider tiles mean more 16-group units per wave and longer
 // contiguous runs in memory: on the 30-qubit headline, widening to 14
 // wherever it fits measured 35.2-35.5 ms per step against 36.4 when tiles
