@@ -399,18 +399,21 @@ def order_for_staging(ops: Sequence["Op"], pos_of=None, tmax: Optional[int] = No
 #  * "fp32" (SV_OPT_SPLIT 0): the fp32 matrix cores bound the pass (fitted
 #    to measured 30-qubit step times of 31 aggregations: memory 3.35, fixed
 #    1.475, per 5-qubit block 1.78, per 4-qubit block 1.10).
-# STAGE_FORM selects the model.  It defaults to the fp32 figures for both
-# forms: ranked with them, the 30-qubit depth-14 circuit's plans run in the
-# split form 0.2-1.0 ms faster (39 blocks in 16 passes and one sweep, 39.4
-# ms of device time) than ranked with the split fit (52 smaller blocks in
-# 17 passes, 39.6-39.7 ms): the split fit's max() form prices blocks under
-# the memory time as free, which they are not quite.
+# STAGE_FORM selects the model.  It defaults to the split fit, the form
+# the device takes for unitary blocks: with 14-position tiles the 30-qubit
+# depth-14 circuit planned from |0...0> gets the same plan either way (41
+# blocks in 13 passes), and planned for passes over the whole state the
+# split fit's plan (33 blocks, 29 of them 5-qubit, in 13 passes) runs
+# 48.0-48.9 ms per step against 50.5-51.4 for the fp32 figures' (37
+# blocks, 11 of them 5-qubit).  With 13-position tiles the fp32 figures
+# had ranked better (0.2-1.0 ms on that circuit): the split fit's max()
+# prices blocks under the memory time as free, which they are not quite.
 SWEEP_MS = {1: 2.9, 2: 2.9, 3: 3.4, 4: 3.5, 5: 3.57, 6: 3.7}
 STAGE_MODELS = {
     "split": (3.5, 0.55, {4: 0.83, 5: 0.95}),
     "fp32": (3.35, 1.475, {4: 1.10, 5: 1.78}),
 }
-STAGE_FORM = "fp32"
+STAGE_FORM = "split"
 
 
 def stage_pass_ms(ks: Sequence[int]) -> float:
