@@ -376,3 +376,22 @@ def test_open_state_files_rejects_missing_or_malformed_checkpoints(tmp_path):
         with pytest.raises(sv.SVError) as e:
             sv.open_state_files(str(tmp_path))
         assert e.value.code == sv.SV_EINVAL, lines
+
+
+def test_counter_traffic_only_for_the_kernels_and_plan_it_was_taken_on(tmp_path, monkeypatch):
+    """The benchmark reports counter traffic for the staged passes only when
+    the kernel sources are those the counters were taken on and the
+    launches move the same algorithmic bytes (the same plan); otherwise
+    null."""
+    import json
+    import bench
+    path = tmp_path / "traffic.json"
+    alg = 9.0e9
+    path.write_text(json.dumps({"kernel_hash": bench.kernel_hash(), "per_kind": {"staged": {
+        "traffic_bytes_per_launch": 9.6e9, "algorithmic_bytes_per_launch": alg}}}))
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(path))
+    assert bench.counter_traffic("staged", alg) == 9.6e9
+    assert bench.counter_traffic("staged", alg * 1.01) is None      # another plan
+    assert bench.counter_traffic("sweep", alg) is None              # no such kind profiled
+    monkeypatch.setattr(bench, "kernel_hash", lambda: "0" * 16)     # other kernel sources
+    assert bench.counter_traffic("staged", alg) is None
