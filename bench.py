@@ -81,6 +81,7 @@ KERNEL_SOURCES = ("paper_1910_09534_amd/csrc/sv_device.h", "paper_1910_09534_amd
                   "paper_1910_09534_amd/csrc/sv_mfma.hip", "paper_1910_09534_amd/csrc/sv_stage.hip",
                   "paper_1910_09534_amd/csrc/sv_internal.h")
 TRAFFIC_FILE = "profiles/staged_pass_30q_d14_traffic.json"
+BATCH_TUNED = "profiles/batch_256_circuits_tuned.json"
 
 
 def kernel_hash() -> str:
@@ -415,6 +416,8 @@ def main(argv=None) -> int:
                     help="requests of the serving summary in the default line")
     ap.add_argument("--no-single-block", action="store_true",
                     help="leave out the lone 5-qubit block timings after the headline steps")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="leave out the 256-circuit batch summary of the default line")
     ap.add_argument("--no-c128", action="store_true",
                     help="skip the complex128 form of the default workload")
     ap.add_argument("--c128-kmax", type=int, default=0,
@@ -555,6 +558,18 @@ def main(argv=None) -> int:
     torch.cuda.empty_cache()
 
     c128 = None if args.no_c128 else bench_c128(circ, bits, args)
+    batch = None
+    if not args.no_batch:
+        # the batch workload with the committed tuned table (autotuned on an
+        # MI355X by bench.py --config 4 --tune-cache ...), replays timed on
+        # the host; its parity with the oracle is a GPU test
+        b = batch_summary(args, 256, 3, 1, os.path.join(ROOT, BATCH_TUNED), compare_c128=False)
+        batch = {k: b[k] for k in ("value", "unit", "ms_per_step", "steps", "amp_updates_per_s", "kmax_by_n",
+                                   "stage_t_by_n", "t_tune_s", "t_plan_s")}
+        batch["ms_per_batch"] = batch.pop("ms_per_step")
+        batch["launches_per_batch"] = b["config"]["launches_per_batch"]
+        batch["workload"] = b["config"]["workload"]
+        torch.cuda.empty_cache()
     serving = None
     if pool is not None:
         serving = serve_summary(pool, args.kmax, count=args.serve_requests)
@@ -586,6 +601,7 @@ def main(argv=None) -> int:
         "norm": stats[0],
         "roofline": roof,
         "c128": c128,
+        "batch": batch,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -679,12 +695,21 @@ def bench_sliced(args) -> int:
 
 def bench_batch(args) -> int:
     """256 independent circuits, one graph-captured batch per step."""
+    print(json.dumps(batch_summary(args, args.n or 256, args.steps, args.warmup, args.tune_cache,
+                                   compare_c128=not args.no_c128)), flush=True)
+    return 0
+
+
+def batch_summary(args, count: int, steps: int, warmup: int, tune_cache, compare_c128: bool) -> dict:
+    """The batch workload's line: `count` circuits of 20-28 qubits, fusion
+    width and tile limit per qubit count from `tune_cache` (or tuned on
+    this GPU first), `warmup` + `steps` graph replays timed on the host;
+    with compare_c128 also the same circuits as a complex128 batch."""
     import torch
     from paper_1910_09534_amd import autotune, planner, runner, sv
     from paper_1910_09534_amd import workload as W
 
     torch.cuda.set_device(0)
-    count = args.n or 256
     specs = W.batch_specs(count)
     circs = [W.sycamore_circuit(s["n"], s["depth"], s["seed"]) for s in specs]
     bits = [W.bitstrings(s["n"], 1024, s["bit_seed"]) for s in specs]
@@ -693,14 +718,14 @@ def bench_batch(args) -> int:
     if args.batch_unstaged:
         tuned = autotune.tune(ns)
         tuned["stage_t"] = {n: 0 for n in ns}
-    elif args.tune_cache and os.path.exists(args.tune_cache):
-        tuned = autotune.load(args.tune_cache)
+    elif tune_cache and os.path.exists(tune_cache):
+        tuned = autotune.load(tune_cache)
     else:
         # fusion width k in {3..6} and staged tile limit in {12, 13, 14} per
         # qubit count, timed on this GPU
         tuned = autotune.tune_staged(ns)
-        if args.tune_cache:
-            autotune.save(tuned, args.tune_cache)
+        if tune_cache:
+            autotune.save(tuned, tune_cache)
     tuned.setdefault("mfma_min_k", {n: 4 for n in ns})
     t_tune = time.perf_counter() - t0
     t0 = time.perf_counter()
@@ -715,9 +740,9 @@ def bench_batch(args) -> int:
             o.matrix = np.ascontiguousarray(o.matrix, dtype=np.complex64)
     t_plan = time.perf_counter() - t0
     res = runner.run_batch(circs, bits, "c64", kmax=tuned["kmax"], mfma_min_k=tuned["mfma_min_k"],
-                           graph=True, repeats=args.warmup + args.steps, plans=plans, staged=staged,
+                           graph=True, repeats=warmup + steps, plans=plans, staged=staged,
                            stage_t=tuned["stage_t"] if staged else None)
-    times = res["times"][args.warmup:]
+    times = res["times"][warmup:]
     t = sum(times) / len(times)
     gate_amps = sum(len(c.gates) * float(1 << c.n) for c in circs)
     swept = res["info"]["amps_swept"]
@@ -725,7 +750,7 @@ def bench_batch(args) -> int:
     err = []
     half = (count + 1) // 2
     t128 = 0.0
-    for lo in ((0, half) if not args.no_c128 else ()):
+    for lo in ((0, half) if compare_c128 else ()):
         sub = slice(lo, min(lo + half, count))
         r = runner.run_batch(circs[sub], bits[sub], "c128", kmax=4, graph=True)
         t128 += r["times"][-1]
@@ -733,8 +758,8 @@ def bench_batch(args) -> int:
             err.append(float(np.linalg.norm(a64 - a128) / np.linalg.norm(a128)))
     line = {
         "metric": "batch: circuits/s and amp-updates/s, one graph-captured batch",
-        "value": count / t, "unit": "circuits/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": round(1e3 * t, 2), "higher_is_better": True,
+        "value": count / t, "unit": "circuits/s", "n_gpus": 1, "steps": steps,
+        "warmup": warmup, "ms_per_step": round(1e3 * t, 2), "higher_is_better": True,
         "dtype": "c64", "data": "synthetic",
         "config": {"workload": f"{count} ABCDCDAB circuits, n ~ U{{20..28}}, depth ~ U{{10..20}}, "
                                "complex64, 1024 bitstrings each",
@@ -749,8 +774,7 @@ def bench_batch(args) -> int:
         "c128_batch_s": round(t128, 3) if err else None,
         "rel_l2_vs_c128_max": max(err) if err else None,
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 def bench_contract(args) -> int:
