@@ -416,6 +416,8 @@ def main(argv=None) -> int:
                     help="requests of the serving summary in the default line")
     ap.add_argument("--no-single-block", action="store_true",
                     help="leave out the lone 5-qubit block timings after the headline steps")
+    ap.add_argument("--no-contraction", action="store_true",
+                    help="leave out the contraction-deferral timings of the default line")
     ap.add_argument("--no-batch", action="store_true",
                     help="leave out the 256-circuit batch summary of the default line")
     ap.add_argument("--no-c128", action="store_true",
@@ -570,6 +572,19 @@ def main(argv=None) -> int:
         batch["launches_per_batch"] = b["config"]["launches_per_batch"]
         batch["workload"] = b["config"]["workload"]
         torch.cuda.empty_cache()
+    contraction = None
+    if not args.no_contraction:
+        # the contraction-deferral leg (--config 6) without its oracle
+        # sample and deferred pipeline: both kernels timed with HIP events
+        ca = argparse.Namespace(**vars(args))
+        ca.n, ca.steps, ca.warmup, ca.no_cpu_baseline, ca.no_pipeline = 0, 3, 1, True, True
+        c = contract_summary(ca)
+        r = c["roofline"]
+        contraction = {"workload": c["config"]["workload"], "kernel": "k_contract_split",
+                       "avg_launch_ms": r["avg_launch_ms"], "issued_tflops": r["achieved"],
+                       "frac_of_fp16_peak": r["frac"], "complex_equivalent_tflops": r["complex_equivalent_tflops"],
+                       "traffic": r["traffic"], "fp32_form_avg_launch_ms": r["fp32_form"]["avg_launch_ms"]}
+        torch.cuda.empty_cache()
     serving = None
     if pool is not None:
         serving = serve_summary(pool, args.kmax, count=args.serve_requests)
@@ -602,6 +617,7 @@ def main(argv=None) -> int:
         "roofline": roof,
         "c128": c128,
         "batch": batch,
+        "contraction": contraction,
         "serving": serving,
         "cpu_baseline": cpu,
     }
@@ -778,6 +794,12 @@ def batch_summary(args, count: int, steps: int, warmup: int, tune_cache, compare
 
 
 def bench_contract(args) -> int:
+    """Contraction deferral line (`contract_summary`)."""
+    print(json.dumps(contract_summary(args)), flush=True)
+    return 0
+
+
+def contract_summary(args) -> dict:
     """Contraction deferral: the bridging gates of the first cycles of an
     ABCDCDAB circuit as EI / E2Q on two tensors (left and right grid halves),
     then the tensor 1 x tensor 2 contraction over the entanglement indices;
@@ -928,8 +950,7 @@ def bench_contract(args) -> int:
          "contract_ms": round(res["contract_ms"], 3), "norm": res["norm"]},
         "cpu_baseline": cpu,
     }
-    print(json.dumps(line), flush=True)
-    return 0
+    return line
 
 
 def bench_permute(args) -> int:
