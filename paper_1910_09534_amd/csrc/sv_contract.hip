@@ -171,8 +171,9 @@ __global__ __launch_bounds__(kCThreads) void k_contract_mfma(const float2* t1, c
 // stays below 2^14) and split into hi = f16(x) and lo = f16(x - hi); the
 // three products A_hi B_hi + A_hi B_lo + A_lo B_hi accumulate in fp32 on
 // v_mfma_f32_16x16x32_f16.  A K chunk of 16 complex values is one 32-deep
-// real product: Re = [Br | -Bi] [Ar ; Ai] and Im = [Br | Bi] [Ai ; Ar]
-// (B = t2^T, A = t1): six products per 16 x 16 block per chunk.  The chunk
+// real product: Re = [Br | Bi] [Ar ; -Ai] and Im = [Br | Bi] [Ai ; Ar]
+// (B = t2^T, A = t1): six products per 16 x 16 block per chunk, both
+// sharing the B operand.  The chunk
 // is parked in LDS already split, each row's 16 values contiguous (hi and
 // lo of the real and imaginary parts), so a lane reads its 8 operand
 // values with one 16-byte access.
@@ -184,21 +185,27 @@ typedef uint32_t cu2 __attribute__((ext_vector_type(2)));
 constexpr int kSRow = 16;                  // f16 per LDS row: the chunk's 16 k values
 
 // f16 pair (a, b), round to nearest
-__device__ __forceinline__ uint32_t cpk_hi(float a, float b)
-{
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const h2 v = {(_Float16)a, (_Float16)b};
-    return __builtin_bit_cast(uint32_t, v);
-}
-
-// f16(a - hi.lo), f16(b - hi.hi): residuals formed exactly, rounded once
-__device__ __forceinline__ uint32_t cpk_lo(float a, float b, uint32_t hi)
+// f16(a s), f16(b s), each rounded once (s is a power of two, so a s is
+// exact): the scale and the conversion in one mixed-precision fma
+__device__ __forceinline__ uint32_t cpk_hi(float a, float b, float s)
 {
     uint32_t r;
-    asm("v_fma_mixlo_f16 %0, %1, -1.0, %2 op_sel_hi:[1,0,0]\n\t"
-        "v_fma_mixhi_f16 %0, %1, -1.0, %3 op_sel:[1,0,0] op_sel_hi:[1,0,0]"
+    asm("v_fma_mixlo_f16 %0, %1, %3, 0\n\t"
+        "v_fma_mixhi_f16 %0, %2, %3, 0"
         : "=&v"(r)
-        : "v"(hi), "v"(a), "v"(b));
+        : "v"(a), "v"(b), "v"(s));
+    return r;
+}
+
+// f16(a s - hi.lo), f16(b s - hi.hi): residuals formed exactly in the fma,
+// rounded once
+__device__ __forceinline__ uint32_t cpk_lo(float a, float b, float s, uint32_t hi)
+{
+    uint32_t r;
+    asm("v_fma_mixlo_f16 %0, %1, %3, -%4 op_sel_hi:[0,0,1]\n\t"
+        "v_fma_mixhi_f16 %0, %2, %3, -%4 op_sel:[0,0,1] op_sel_hi:[0,0,1]"
+        : "=&v"(r)
+        : "v"(a), "v"(b), "v"(s), "v"(hi));
     return r;
 }
 
@@ -283,12 +290,12 @@ __global__ __launch_bounds__(kCThreads) void k_contract_split(const float2* t1, 
         cu4 rh, rl, ih, il;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-            const float x0 = gb[2 * w].x * sb, x1 = gb[2 * w + 1].x * sb;
-            const float y0 = gb[2 * w].y * sb, y1 = gb[2 * w + 1].y * sb;
-            rh[w] = cpk_hi(x0, x1);
-            ih[w] = cpk_hi(y0, y1);
-            rl[w] = cpk_lo(x0, x1, rh[w]);
-            il[w] = cpk_lo(y0, y1, ih[w]);
+            const float x0 = gb[2 * w].x, x1 = gb[2 * w + 1].x;
+            const float y0 = gb[2 * w].y, y1 = gb[2 * w + 1].y;
+            rh[w] = cpk_hi(x0, x1, sb);
+            ih[w] = cpk_hi(y0, y1, sb);
+            rl[w] = cpk_lo(x0, x1, sb, rh[w]);
+            il[w] = cpk_lo(y0, y1, sb, ih[w]);
         }
         const int ob = srow(bm, bo);
         *(cu4*)&Bs[buf][0][ob] = rh;
@@ -298,12 +305,12 @@ __global__ __launch_bounds__(kCThreads) void k_contract_split(const float2* t1, 
         cu2 arh, arl, aih, ail;
 #pragma unroll
         for (int w = 0; w < 2; ++w) {
-            const float x0 = ga[2 * w].x * sa, x1 = ga[2 * w + 1].x * sa;
-            const float y0 = ga[2 * w].y * sa, y1 = ga[2 * w + 1].y * sa;
-            arh[w] = cpk_hi(x0, x1);
-            aih[w] = cpk_hi(y0, y1);
-            arl[w] = cpk_lo(x0, x1, arh[w]);
-            ail[w] = cpk_lo(y0, y1, aih[w]);
+            const float x0 = ga[2 * w].x, x1 = ga[2 * w + 1].x;
+            const float y0 = ga[2 * w].y, y1 = ga[2 * w + 1].y;
+            arh[w] = cpk_hi(x0, x1, sa);
+            aih[w] = cpk_hi(y0, y1, sa);
+            arl[w] = cpk_lo(x0, x1, sa, arh[w]);
+            ail[w] = cpk_lo(y0, y1, sa, aih[w]);
         }
         const int oa = srow(an, aq >> 1) + 4 * (aq & 1);
         *(cu2*)&As[buf][0][oa] = arh;
@@ -321,11 +328,14 @@ __global__ __launch_bounds__(kCThreads) void k_contract_split(const float2* t1, 
             im[a][b] = re[a][b];
         }
     // lane (li, g): operand element e is k = 8 (g & 1) + e of the real part
-    // (g < 2) or the imaginary part (g >= 2); the -Bi of the real product is
-    // the sign flipped in lanes g >= 2
+    // (g < 2) or the imaginary part (g >= 2).  Re = [Br | Bi] [Ar ; -Ai] and
+    // Im = [Br | Bi] [Ai ; Ar]: both products share the A operand, and the
+    // -Ai of the real one is the sign flipped in lanes g >= 2 of its other
+    // operand (two 16-column blocks per wave, against four 16-row blocks
+    // of the A operand)
     const int o = g & 1;
     const int pA = g < 2 ? 0 : 2;                 // A operand rows: Br or Bi
-    const int pBr = g < 2 ? 0 : 2;                // [Ar ; Ai]
+    const int pBr = g < 2 ? 0 : 2;                // [Ar ; Ai], Ai negated below
     const int pBi = g < 2 ? 2 : 0;                // [Ai ; Ar]
     const uint32_t neg = g < 2 ? 0u : 0x80008000u;
 
@@ -340,8 +350,8 @@ __global__ __launch_bounds__(kCThreads) void k_contract_split(const float2* t1, 
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
             const int ob = srow(wn + 16 * b + li, o);
-            xbr_h[b] = *(const ch8*)&As[buf][pBr][ob];
-            xbr_l[b] = *(const ch8*)&As[buf][pBr + 1][ob];
+            xbr_h[b] = __builtin_bit_cast(ch8, *(const cu4*)&As[buf][pBr][ob] ^ neg);
+            xbr_l[b] = __builtin_bit_cast(ch8, *(const cu4*)&As[buf][pBr + 1][ob] ^ neg);
             xbi_h[b] = *(const ch8*)&As[buf][pBi][ob];
             xbi_l[b] = *(const ch8*)&As[buf][pBi + 1][ob];
         }
@@ -350,16 +360,15 @@ __global__ __launch_bounds__(kCThreads) void k_contract_split(const float2* t1, 
             const int oa = srow(wm + 16 * a + li, o);
             const cu4 h = *(const cu4*)&Bs[buf][pA][oa];
             const cu4 l = *(const cu4*)&Bs[buf][pA + 1][oa];
-            const ch8 ai_h = __builtin_bit_cast(ch8, h), ai_l = __builtin_bit_cast(ch8, l);
-            const ch8 ar_h = __builtin_bit_cast(ch8, h ^ neg), ar_l = __builtin_bit_cast(ch8, l ^ neg);
+            const ch8 a_h = __builtin_bit_cast(ch8, h), a_l = __builtin_bit_cast(ch8, l);
 #pragma unroll
             for (int b = 0; b < 2; ++b) {
-                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar_l, xbr_h[b], re[a][b], 0, 0, 0);
-                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai_l, xbi_h[b], im[a][b], 0, 0, 0);
-                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar_h, xbr_l[b], re[a][b], 0, 0, 0);
-                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai_h, xbi_l[b], im[a][b], 0, 0, 0);
-                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ar_h, xbr_h[b], re[a][b], 0, 0, 0);
-                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(ai_h, xbi_h[b], im[a][b], 0, 0, 0);
+                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, xbr_h[b], re[a][b], 0, 0, 0);
+                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_l, xbi_h[b], im[a][b], 0, 0, 0);
+                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, xbr_l[b], re[a][b], 0, 0, 0);
+                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, xbi_l[b], im[a][b], 0, 0, 0);
+                re[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, xbr_h[b], re[a][b], 0, 0, 0);
+                im[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a_h, xbi_h[b], im[a][b], 0, 0, 0);
             }
         }
         __builtin_amdgcn_sched_barrier(0);
