@@ -79,12 +79,21 @@ def planning_pool(workers: int = 8):
     import multiprocessing
     from concurrent.futures import ProcessPoolExecutor
     pool = ProcessPoolExecutor(max_workers=workers, mp_context=multiprocessing.get_context("spawn"))
-    list(pool.map(_warm, range(workers)))
+    # return once every worker runs (each has taken a task), so that none is
+    # still starting up while the caller goes on
+    seen = set()
+    for _ in range(20):
+        seen |= set(pool.map(_warm, range(4 * workers)))
+        if len(seen) >= workers:
+            break
     return pool
 
 
 def _warm(_):
-    return 0
+    import os
+    import time
+    time.sleep(0.02)
+    return os.getpid()
 
 
 class BuddyArena:
